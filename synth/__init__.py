@@ -1,0 +1,251 @@
+"""Seeded synthetic inputs for the imaging workloads.
+
+This module is shared by the FP64 CPU oracle and the GPU path. It only draws
+random numbers and lays out test geometry (sky models, antenna layouts, the
+earth-rotation uvw tracks, noise draws, block sizes, training patches); it holds
+none of the imaging method's arithmetic (no gridding, no interpolation kernel,
+no Fourier transform of the measurement operator, no prox).
+
+Units: the visibility coordinates are returned as ``uvw[:, 0:2] = omega`` in
+radians per pixel (so that the exact model reads
+``y_m = sum_n x_n exp(-i omega_m . n)`` for centred pixel indices n) and
+``uvw[:, 2] = w`` in wavelengths.
+
+Seeds (numpy PCG64): sky 0, array 1, noise 2, w 3, blocks 4, training 5,
+power-method start 7.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_SKY = 0
+SEED_ARRAY = 1
+SEED_NOISE = 2
+SEED_W = 3
+SEED_BLOCKS = 4
+SEED_TRAIN = 5
+SEED_POWER = 7
+
+ARCSEC = math.pi / (180.0 * 3600.0)
+
+
+# ----------------------------------------------------------------------------
+# Workload descriptions (numbers only)
+# ----------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    N: int                      # image side
+    n_ant: int                  # antennas
+    n_times: int                # time steps of the track
+    omega_max: float            # max |omega| (rad/pixel) after scaling
+    cell_rad: float             # pixel size delta (rad), used by the w-term
+    w_mode: str                 # "zero" | "uniform"
+    w_hex_max: float = 0.0      # per-axis chirp half-bandwidth (cells) at |w| = W
+    n_wplanes: int = 1          # odd; w = 0 is the centre plane
+    dec_deg: float = -60.0
+    lat_deg: float = -30.7
+    hours: float = 8.0
+    isnr_db: float = 40.0
+    n_blocks: int = 1
+    block_lo: int = 0
+    block_hi: int = 0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def Np(self) -> int:
+        return 2 * self.N
+
+    @property
+    def M(self) -> int:
+        return self.n_ant * (self.n_ant - 1) // 2 * self.n_times
+
+    @property
+    def W(self) -> float:
+        """|w| bound (wavelengths) at which the per-axis chirp half-bandwidth at
+        the image edge equals ``w_hex_max`` grid cells (hex = w sigma N^2 delta^2 / 2)."""
+        if self.w_mode == "zero":
+            return 0.0
+        return 2.0 * self.w_hex_max / (2.0 * self.N * self.N * self.cell_rad ** 2)
+
+
+# Plain FB, narrow field, FP64 (w = 0).
+C0 = Workload("C0-narrow-256", N=256, n_ant=32, n_times=132,
+              omega_max=2 * math.pi / 3, cell_rad=1.68 * ARCSEC, w_mode="zero")
+# Wide-field operator bench: 2048^2 image, 4096^2 grid, M = 16,777,152,
+# w uniform in [-W, W] with supports 11..17 (7 at w = 0).
+C1 = Workload("C1-wide-2048", N=2048, n_ant=64, n_times=8322,
+              omega_max=2 * math.pi / 3, cell_rad=1.68 * ARCSEC, w_mode="uniform",
+              w_hex_max=4.0, n_wplanes=4097)
+# C1 data cut into 64 uneven angular-sector blocks.
+C2 = Workload("C2-blocks-2048", N=2048, n_ant=64, n_times=8322,
+              omega_max=2 * math.pi / 3, cell_rad=1.68 * ARCSEC, w_mode="uniform",
+              w_hex_max=4.0, n_wplanes=4097, n_blocks=64,
+              block_lo=50_000, block_hi=2_000_000)
+
+# Small wide-field cases for parity tests (several tiles plus a ragged tail).
+T_SMALL_W = Workload("T-wide-128", N=128, n_ant=16, n_times=97,
+                     omega_max=2 * math.pi / 3, cell_rad=20 * ARCSEC, w_mode="uniform",
+                     w_hex_max=4.0, n_wplanes=257)
+
+WORKLOADS = {w.name: w for w in (C0, C1, C2, T_SMALL_W)}
+
+
+def scaled(base: Workload, **kw) -> Workload:
+    """A copy of ``base`` with some fields replaced (used for small test cases)."""
+    d = dict(base.__dict__)
+    d.update(kw)
+    return Workload(**d)
+
+
+# ----------------------------------------------------------------------------
+# Sky
+# ----------------------------------------------------------------------------
+def sky(N: int, seed: int = SEED_SKY, n_compact: int = 30, n_ext: int = 2) -> np.ndarray:
+    """Positive test sky, float64 [N, N] indexed [iy, ix].
+
+    ``n_compact`` round Gaussians (FWHM ~ U[1,3] px, peak 10^U[-4,0], centres
+    U[16, N-16)^2) plus ``n_ext`` elliptical Gaussians (FWHM_a, FWHM_b ~
+    U[20,40] px, angle U[0,pi), peak 10^U[-3,-2], centres U[N/4, 3N/4)^2).
+    """
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:N, 0:N].astype(np.float64)
+    img = np.zeros((N, N))
+    k = 1.0 / (2.0 * math.sqrt(2.0 * math.log(2.0)))   # FWHM -> sigma
+    for _ in range(n_compact):
+        fwhm = rng.uniform(1.0, 3.0)
+        peak = 10.0 ** rng.uniform(-4.0, 0.0)
+        cy, cx = rng.uniform(16, N - 16, size=2)
+        s = fwhm * k
+        r = 4.0 * s + 2.0
+        y0, y1 = int(max(0, cy - r)), int(min(N, cy + r + 1))
+        x0, x1 = int(max(0, cx - r)), int(min(N, cx + r + 1))
+        sub = (yy[y0:y1, x0:x1] - cy) ** 2 + (xx[y0:y1, x0:x1] - cx) ** 2
+        img[y0:y1, x0:x1] += peak * np.exp(-sub / (2 * s * s))
+    for _ in range(n_ext):
+        fa, fb = rng.uniform(20.0, 40.0, size=2)
+        ang = rng.uniform(0.0, math.pi)
+        peak = 10.0 ** rng.uniform(-3.0, -2.0)
+        cy, cx = rng.uniform(N / 4, 3 * N / 4, size=2)
+        sa, sb = fa * k, fb * k
+        c, s_ = math.cos(ang), math.sin(ang)
+        dx, dy = xx - cx, yy - cy
+        a = c * dx + s_ * dy
+        b = -s_ * dx + c * dy
+        img += peak * np.exp(-(a * a) / (2 * sa * sa) - (b * b) / (2 * sb * sb))
+    return img
+
+
+def random_image(N: int, seed: int, positive: bool = True) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    x = rng.random((N, N)) if positive else rng.standard_normal((N, N))
+    return x
+
+
+# ----------------------------------------------------------------------------
+# Array geometry and earth-rotation synthesis (Thompson-Moran-Swenson)
+# ----------------------------------------------------------------------------
+def antenna_enu(n_ant: int, radius: float = 1.0, seed: int = SEED_ARRAY) -> np.ndarray:
+    """Antennas uniform in a disk on the ground: r = R sqrt(U), theta = 2 pi U."""
+    rng = np.random.default_rng(seed)
+    r = radius * np.sqrt(rng.random(n_ant))
+    th = 2 * math.pi * rng.random(n_ant)
+    enu = np.zeros((n_ant, 3))
+    enu[:, 0] = r * np.cos(th)
+    enu[:, 1] = r * np.sin(th)
+    return enu
+
+
+def baseline_uvw(enu: np.ndarray, n_times: int, dec_deg: float, lat_deg: float,
+                 hours: float) -> np.ndarray:
+    """uvw (same length unit as ``enu``) for all baselines i<j over hour angles
+    H in [-hours/2, +hours/2] (n_times steps). Order: time-major within each
+    baseline, baselines in (i, j) lexicographic order."""
+    i, j = np.triu_indices(enu.shape[0], k=1)
+    b = enu[j] - enu[i]                                      # E, N, U
+    lat = math.radians(lat_deg)
+    X = -math.sin(lat) * b[:, 1] + math.cos(lat) * b[:, 2]
+    Y = b[:, 0]
+    Z = math.cos(lat) * b[:, 1] + math.sin(lat) * b[:, 2]
+    H = np.linspace(-hours / 2, hours / 2, n_times) * (2 * math.pi / 24.0)
+    d = math.radians(dec_deg)
+    sH, cH = np.sin(H)[None, :], np.cos(H)[None, :]
+    u = sH * X[:, None] + cH * Y[:, None]
+    v = -math.sin(d) * cH * X[:, None] + math.sin(d) * sH * Y[:, None] + math.cos(d) * Z[:, None]
+    w = math.cos(d) * cH * X[:, None] - math.cos(d) * sH * Y[:, None] + math.sin(d) * Z[:, None]
+    return np.stack([u.ravel(), v.ravel(), w.ravel()], axis=1)
+
+
+def uvw(wl: Workload) -> np.ndarray:
+    """Visibility coordinates for a workload: float64 [M, 3] = (omega_u, omega_v
+    in rad/pixel, w in wavelengths)."""
+    enu = antenna_enu(wl.n_ant)
+    b = baseline_uvw(enu, wl.n_times, wl.dec_deg, wl.lat_deg, wl.hours)
+    rad = np.sqrt(b[:, 0] ** 2 + b[:, 1] ** 2).max()
+    out = np.empty_like(b)
+    out[:, 0:2] = b[:, 0:2] * (wl.omega_max / rad)
+    if wl.w_mode == "zero":
+        out[:, 2] = 0.0
+    elif wl.w_mode == "uniform":
+        rng = np.random.default_rng(SEED_W)
+        out[:, 2] = rng.uniform(-wl.W, wl.W, size=b.shape[0])
+    else:
+        raise ValueError(wl.w_mode)
+    return out
+
+
+def random_uvw(M: int, omega_max: float, W: float, seed: int) -> np.ndarray:
+    """Uniformly scattered test coordinates (|omega| < omega_max per axis)."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((M, 3))
+    out[:, 0:2] = rng.uniform(-omega_max, omega_max, size=(M, 2))
+    out[:, 2] = rng.uniform(-W, W, size=M) if W > 0 else 0.0
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Noise and other random draws
+# ----------------------------------------------------------------------------
+def noise_normals(M: int, seed: int = SEED_NOISE) -> np.ndarray:
+    """Complex draws a + i b with a, b ~ N(0, 1) independent (complex128 [M])."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(M)
+    b = rng.standard_normal(M)
+    return a + 1j * b
+
+
+def power_start(N: int, seed: int = SEED_POWER) -> np.ndarray:
+    """Start vector of the power iteration: float64 [N, N] standard normal."""
+    return np.random.default_rng(seed).standard_normal((N, N))
+
+
+# ----------------------------------------------------------------------------
+# Data blocks: angular sectors of the uv plane with uneven sizes
+# ----------------------------------------------------------------------------
+def block_sizes(n_blocks: int, M: int, lo: float, hi: float, seed: int = SEED_BLOCKS) -> np.ndarray:
+    """Log-uniform sizes in [lo, hi], rescaled to sum exactly to M (int64)."""
+    rng = np.random.default_rng(seed)
+    s = np.exp(rng.uniform(math.log(lo), math.log(hi), size=n_blocks))
+    s = s * (M / s.sum())
+    out = np.floor(s).astype(np.int64)
+    out[np.argsort(-(s - out))[: M - out.sum()]] += 1
+    assert out.sum() == M and (out > 0).all()
+    return out
+
+
+def sector_order(uvw_: np.ndarray) -> np.ndarray:
+    """Permutation that orders visibilities by polar angle atan2(v, u) (stable)."""
+    ang = np.arctan2(uvw_[:, 1], uvw_[:, 0])
+    return np.argsort(ang, kind="stable")
+
+
+def blocked(uvw_: np.ndarray, sizes: np.ndarray):
+    """Reorder visibilities into contiguous angular-sector blocks of the given
+    sizes. Returns (perm, offsets[n_blocks+1]); uvw_[perm] is in block order."""
+    perm = sector_order(uvw_)
+    offsets = np.zeros(len(sizes) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(sizes)
+    return perm, offsets

@@ -1,0 +1,196 @@
+/*
+ * ri.h -- C ABI of the MI355X plug-and-play forward-backward imaging library
+ * (libri.so, HIP kernels for gfx950).
+ *
+ * The library computes the hot path of radio-interferometric imaging by
+ * forward-backward iterations (Dabbech et al., "First AI for deep
+ * super-resolution wide-field imaging in radio astronomy"):
+ *
+ *   y = Phi x + n,  Phi = G F Z                                  (eq. 1)
+ *   x^{k+1} = D(x^k - gamma Re{Phi^dagger (Phi x^k - y)})        (eq. A2)
+ *
+ * with Z the zero padding by two plus the kernel correction, F the
+ * oversampled 2D FFT and G the sparse Kaiser-Bessel interpolation convolved
+ * row-wise with small w-kernels (appendix E); Phi^dagger Phi is the sum of the
+ * per-block terms (eq. E2); D is the Haar-l1 + positivity prox or a learned
+ * residual CNN (appendices B and C).
+ *
+ * Conventions used throughout:
+ *  - Images are real, row-major [N][N], index [iy][ix] for the centred pixel
+ *    (ix - N/2, iy - N/2); element type float (precision 32) or double (64).
+ *  - Visibilities are complex, interleaved (re, im) float or double pairs, in
+ *    the caller's order (the library's internal tile order never leaks out).
+ *  - uvw rows are (omega_u, omega_v) in radians per pixel (|omega| < pi) and w
+ *    in wavelengths; the Fourier kernel is exp(-i omega . n) forward.
+ *  - Every buffer argument marked "dev" is device memory owned by the caller;
+ *    the library never frees it and keeps no pointer to it after the call
+ *    returns. "host" buffers are read during the call only.
+ *  - Calls taking a stream only enqueue work on it (no host synchronisation)
+ *    unless stated otherwise; a NULL stream is the default stream.
+ *  - Every call returns a status; on failure ri_last_error() describes it and
+ *    no output buffer has been partially written by a kernel of that call
+ *    (argument checks run before any launch).
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef RI_H
+#define RI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ri_ctx ri_ctx;
+typedef void *ri_stream; /* hipStream_t */
+
+typedef enum {
+    RI_OK = 0,
+    RI_EINVAL = -1,       /* bad argument: sizes, NULL pointers, non-finite or |omega| >= pi */
+    RI_ENOMEM = -2,       /* device or host allocation failed */
+    RI_EDEVICE = -3,      /* a HIP call failed (message has the HIP error string) */
+    RI_EUNSUPPORTED = -4, /* valid request this build does not implement */
+    RI_ENOTCONV = -5,     /* an iteration hit its limit without meeting its tolerance */
+    RI_FELLBACK = 1       /* pnp_solve detected divergence and finished with the Haar prox */
+} ri_status;
+
+enum { RI_G_CSR = 0, RI_G_OTF = 1 };
+enum { RI_PROX_HAAR = 0, RI_PROX_CNN = 1 };
+
+/* Plan description. All sizes explicit; nothing is read through globals. */
+typedef struct {
+    int32_t N;             /* image side; even, N' = 2N a power of two, 16 <= N <= 4096 */
+    int32_t oversample;    /* grid oversampling sigma; must be 2 */
+    int32_t kb_support;    /* Kaiser-Bessel width J; must be 7 */
+    int32_t hmax;          /* largest w-kernel half support, 0..5 (windows up to 7+2*hmax) */
+    double cell_rad;       /* pixel size delta [rad], enters the w-term */
+    double w_max;          /* W [wavelengths]: the w-plane table spans [-W, W]; 0 => no w-term */
+    int32_t n_wplanes;     /* odd number of w-planes (w = 0 is the centre plane) */
+    int32_t g_mode;        /* RI_G_CSR: G stored as CSR (complex values + int32 columns);
+                              RI_G_OTF: G rows computed on the fly from the KB and w-tables */
+    int32_t precision;     /* 32 or 64: element type of Phi, Phi^dagger and the FFT */
+    int32_t tile;          /* uv tile side in grid cells (16..128, divides N'); 0 => 64 (32 in FP64) */
+    int64_t M;             /* number of visibilities, >= 0 */
+    int32_t n_blocks;      /* data blocks (eq. E1), >= 1 */
+    const int64_t *block_offsets; /* host, n_blocks+1 ascending offsets into the caller's
+                                     visibility order (0 ... M); NULL => one block */
+    int32_t facet_core;    /* denoiser facet core side (multiple of 16); 0 => whole image */
+    int32_t facet_halo;    /* facet halo in pixels (the CNN needs >= its receptive radius) */
+} ri_plan_desc;
+
+/* Build a context: validates the description, computes every visibility's
+ * grid cell and fraction in FP64 (p = omega N'/(2 pi), c = floor(p + 1/2)),
+ * its w-plane, the least-squares w-kernel table, the kernel-correction and
+ * twiddle tables, sorts the visibilities by (block, uv tile, support), forms
+ * the work items of the persistent launches and, for RI_G_CSR, fills the CSR
+ * G on the device (appendix E: "computed only once"). uvw: host, M x 3 doubles.
+ * Synchronous. On success *out owns all device memory it allocated. */
+ri_status ri_create(const ri_plan_desc *desc, const double *uvw, ri_ctx **out);
+void ri_destroy(ri_ctx *ctx);
+/* Message for the last non-OK status of this context (or of the last failed
+ * ri_create when ctx is NULL). Valid until the next call on the context. */
+const char *ri_last_error(const ri_ctx *ctx);
+
+/* y = Phi x = G F Z x (eq. 1). x: dev [N][N] real; y: dev [M] complex, caller's
+ * order. Element types follow the context precision. */
+ri_status phi_forward(ri_ctx *ctx, const void *x, void *y, ri_stream stream);
+
+/* x = Re{Phi^dagger y} = Re{Z^dagger F^dagger G^H y} (the real-image adjoint).
+ * y: dev [M] complex (caller's order); x: dev [N][N] real. */
+ri_status phi_adjoint(ri_ctx *ctx, const void *y, void *x, ri_stream stream);
+
+/* Store the data vector y (dev [M] complex, caller's order) inside the
+ * context, permuted to the internal order; used by ri_gradient, fb_step and
+ * pnp_solve when they are passed y = NULL. */
+ri_status ri_set_data(ri_ctx *ctx, const void *y, ri_stream stream);
+
+/* Gradient of f(x) = ||Phi x - y||^2 / 2 (appendix A):
+ *   g = Re{Phi^dagger (Phi x - y)} = Re{Phi^dagger Phi} x - Re{Phi^dagger y},
+ * computed in one fused degrid -> residual -> grid pass over the blocks.
+ * y: dev [M] complex in the caller's order, or NULL for the stored data, or
+ * RI_NO_DATA for y = 0 (then g = Re{Phi^dagger Phi} x).
+ * r2: dev double[1] receiving ||Phi x - y||^2 in FP64, or NULL. */
+#define RI_NO_DATA ((const void *)(intptr_t)-1)
+ri_status ri_gradient(ri_ctx *ctx, const void *x, const void *y, void *g, double *r2,
+                      ri_stream stream);
+
+/* L = ||Re{Phi^dagger Phi}||_S by the power method in FP64 on the device
+ * (appendix A), whatever the context precision: x <- A x / ||A x||, stop when
+ * the relative change of ||A x|| is <= rtol or after max_it applications.
+ * x0: dev double [N][N] start vector, or NULL for a built-in deterministic one.
+ * Synchronises the stream once per iteration. Returns RI_ENOTCONV (with *L
+ * set to the last estimate) when max_it is reached first and rtol > 0. */
+ri_status ri_power_norm(ri_ctx *ctx, int32_t max_it, double rtol, const double *x0,
+                        double *L, int32_t *iters, ri_stream stream);
+
+/* Denoiser D (the backward step of eq. A2):
+ *   RI_PROX_HAAR: D(z) = max(0, Psi soft_t(Psi^dagger z)), Psi the orthonormal
+ *                 2D Haar basis with four levels, every coefficient
+ *                 thresholded at t = param (eq. B2: t = tau / sqrt(2L));
+ *   RI_PROX_CNN:  D(z) = z - net(z), the residual CNN loaded by
+ *                 ri_load_denoiser (appendix C); param is unused.
+ * Applied facet by facet (appendix D) in one launch. z, out: dev [N][N]. */
+ri_status denoise(ri_ctx *ctx, const void *z, void *out, int32_t kind, double param,
+                  ri_stream stream);
+
+/* One forward-backward iteration (eq. A2):
+ *   x_out = D(x_in - gamma Re{Phi^dagger (Phi x_in - y)}).
+ * y as in ri_gradient. norms: dev double[3] receiving, in FP64,
+ * ||x_out - x_in||^2, ||x_out||^2, ||Phi x_in - y||^2 (or NULL).
+ * x_in and x_out may not alias. */
+ri_status fb_step(ri_ctx *ctx, const void *x_in, const void *y, double gamma, int32_t kind,
+                  double param, void *x_out, double *norms, ri_stream stream);
+
+/* Load the CNN denoiser weights. weights: dev bytes in the packed layout of
+ * ri_cnn_layout (BF16 convolution weights, FP32 biases); copied. */
+ri_status ri_load_denoiser(ri_ctx *ctx, const void *weights, int64_t nbytes);
+
+/* Whole solve: parameters from the paper's rules (appendices B, C, F), FB or
+ * PnP-FB iterations from x = 0, divergence watch with Haar fallback. */
+typedef struct {
+    int32_t max_iter;      /* iterations */
+    double rel_tol;        /* stop when ||x^{k+1}-x^k|| / ||x^{k+1}|| <= rel_tol (0: never) */
+    int32_t prox_kind;     /* RI_PROX_HAAR or RI_PROX_CNN */
+    double tau;            /* visibility noise std (eq. 1) */
+    double sigma_train;    /* CNN training noise level (eq. C3); ignored for Haar */
+    double L;              /* ||Phi||_S^2 if known (> 0), else computed by ri_power_norm */
+    int32_t check_every;   /* host reads the FP64 norms every check_every iterations (>= 1) */
+    const void *x_true;    /* optional dev [N][N] ground truth for the SNR trace, or NULL */
+    double *trace;         /* optional host [max_iter][4]: rel change, ||r||^2, SNR dB, ms */
+} ri_solve_opts;
+
+typedef struct {
+    int32_t iters;
+    double L, gamma, alpha, t_or_sigma;
+    double final_rel_change, final_residual2, snr_db;
+    int32_t fell_back;
+    double ms;             /* wall time of the iterations (setup excluded) */
+} ri_solve_report;
+
+/* y: dev [M] complex (caller's order) or NULL for the stored data.
+ * x_out: dev [N][N] (context precision), the solution multiplied back by alpha.
+ * Synchronous. */
+ri_status pnp_solve(ri_ctx *ctx, const void *y, const ri_solve_opts *opts, void *x_out,
+                    ri_solve_report *report);
+
+/* Plan statistics for tests and the benchmark. */
+typedef struct {
+    int64_t M, nnz;        /* visibilities, stored/implied G entries */
+    int32_t N, Np, tile, n_tiles, n_items, n_blocks;
+    int64_t max_item_vis;  /* largest work item */
+    int64_t device_bytes;  /* device memory held by the context */
+    double plan_ms;        /* host + device time of ri_create */
+} ri_plan_stats;
+ri_status ri_get_plan_stats(const ri_ctx *ctx, ri_plan_stats *out);
+
+/* Copy internal per-visibility plan data to host arrays for exact checks
+ * (each may be NULL): cell_u, cell_v (int32, window centres mod N'), plane
+ * (int32), in the caller's visibility order; plane_h (int32 [n_wplanes]). */
+ri_status ri_get_plan_arrays(const ri_ctx *ctx, int32_t *cell_u, int32_t *cell_v,
+                             int32_t *plane, int32_t *plane_h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RI_H */

@@ -1,0 +1,295 @@
+// F and F^dagger on the N' x N' grid (paper eq. 1: F is the DFT on the fine
+// grid), fused with Z (zero padding + 1/kappa_hat correction) on the way in
+// and with Z^dagger (crop, correction, real part) on the way out.
+//
+// Layout: grid row-major [ky][kx], wrap-centred (pixel n at cell n mod N').
+// Rows: one workgroup per image row, the whole N'-point row in LDS, Stockham
+// radix-16 passes (natural order in and out, twiddles from an FP64-computed
+// table). Only the N non-zero rows are transformed on the way in, and only
+// the N needed rows on the way out.
+// Columns: four-step decomposition N' = N1 * N2 over stripes of CW adjacent
+// columns, so every global access is a contiguous CW-element row segment:
+//   pass A: N1-point transforms along rows n2 + N2*n1, times W_{N'}^{n2 k1};
+//   pass B: N2-point transforms along rows N2*k1 + n2, written to row k1 + N1*k2.
+#include "ri_internal.h"
+
+namespace ri {
+
+namespace {
+
+// exp(-2 pi i k / 16), k = 0..15 (exact constants of the 16th roots of unity)
+__device__ __constant__ double kRoot16[16][2] = {
+    {1.0, 0.0},
+    {0.92387953251128675613, -0.38268343236508977173},
+    {0.70710678118654752440, -0.70710678118654752440},
+    {0.38268343236508977173, -0.92387953251128675613},
+    {0.0, -1.0},
+    {-0.38268343236508977173, -0.92387953251128675613},
+    {-0.70710678118654752440, -0.70710678118654752440},
+    {-0.92387953251128675613, -0.38268343236508977173},
+    {-1.0, 0.0},
+    {-0.92387953251128675613, 0.38268343236508977173},
+    {-0.70710678118654752440, 0.70710678118654752440},
+    {-0.38268343236508977173, 0.92387953251128675613},
+    {0.0, 1.0},
+    {0.38268343236508977173, 0.92387953251128675613},
+    {0.70710678118654752440, 0.70710678118654752440},
+    {0.92387953251128675613, 0.38268343236508977173}};
+
+constexpr int brev(int k, int bits) {
+    int r = 0;
+    for (int b = 0; b < bits; ++b) r |= ((k >> b) & 1) << (bits - 1 - b);
+    return r;
+}
+constexpr int ilog2(int R) { return R <= 1 ? 0 : 1 + ilog2(R / 2); }
+
+// In-register R-point DFT, natural order in and out:
+// V[k] = sum_r v[r] exp(-+ 2 pi i r k / R).
+template <typename T, int R>
+__device__ __forceinline__ void dft_reg(cx<T> *v, bool inv) {
+#pragma unroll
+    for (int span = R / 2; span >= 1; span >>= 1) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            if (m & span) continue;
+            const int mloc = m & (2 * span - 1);
+            cx<T> a = v[m], b = v[m + span];
+            v[m] = a + b;
+            cx<T> d = a - b;
+            const int e = mloc * (16 / (2 * span));
+            if (e != 0) {
+                cx<T> w = mk<T>((T)kRoot16[e][0], inv ? -(T)kRoot16[e][1] : (T)kRoot16[e][1]);
+                d = d * w;
+            }
+            v[m + span] = d;
+        }
+    }
+    cx<T> t[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) t[k] = v[brev(k, ilog2(R))];
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] = t[k];
+}
+
+template <bool PAD>
+__device__ __forceinline__ int pidx(int i) { return PAD ? i + (i >> 5) : i; }
+
+// One Stockham radix-R pass over s[L][CW] (transform along the first index),
+// in place: every thread loads its groups, barrier, computes, stores, barrier.
+// Requires (L/R)*CW <= (16/R) * blockDim.x.
+template <typename T, int R, bool PAD>
+__device__ __forceinline__ void stockham_pass(cx<T> *s, int L, int logCW, int Ns, const cx<T> *__restrict__ tw,
+                                              int tw_mul, bool inv) {
+    constexpr int G = 16 / R;
+    const int CW = 1 << logCW;
+    const int ng = (L / R) << logCW;
+    cx<T> v[G][R];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        const int g = threadIdx.x + i * blockDim.x;
+        if (g < ng) {
+            const int col = g & (CW - 1), j = g >> logCW;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = s[pidx<PAD>(((j + r * (L / R)) << logCW) + col)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        const int g = threadIdx.x + i * blockDim.x;
+        if (g < ng) {
+            const int col = g & (CW - 1), j = g >> logCW;
+            const int jm = j & (Ns - 1);
+            const int step = jm * tw_mul * (L / (Ns * R));
+            if (jm != 0) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cx<T> w = tw[step * r];
+                    if (inv) w.y = -w.y;
+                    v[i][r] = v[i][r] * w;
+                }
+            }
+            dft_reg<T, R>(v[i], inv);
+            const int idxD = (j - jm) * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) s[pidx<PAD>(((idxD + r * Ns) << logCW) + col)] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Full L-point transform of every column of s[L][CW]; caller syncs before.
+template <typename T, bool PAD>
+__device__ void fft_lds(cx<T> *s, int logL, int logCW, const cx<T> *__restrict__ tw, int tw_mul, bool inv) {
+    const int L = 1 << logL;
+    int Ns = 1, rem = logL;
+    while (rem > 0) {
+        if (rem >= 4) { stockham_pass<T, 16, PAD>(s, L, logCW, Ns, tw, tw_mul, inv); Ns <<= 4; rem -= 4; }
+        else if (rem == 3) { stockham_pass<T, 8, PAD>(s, L, logCW, Ns, tw, tw_mul, inv); Ns <<= 3; rem -= 3; }
+        else if (rem == 2) { stockham_pass<T, 4, PAD>(s, L, logCW, Ns, tw, tw_mul, inv); Ns <<= 2; rem -= 2; }
+        else { stockham_pass<T, 2, PAD>(s, L, logCW, Ns, tw, tw_mul, inv); Ns <<= 1; rem -= 1; }
+    }
+}
+
+__device__ __forceinline__ bool in_band(int r, int N, int Np) { return r < N / 2 || r >= Np - N / 2; }
+
+// Z then the row DFT of image row iy (blockIdx.x), written to grid row (iy - N/2) mod N'.
+template <typename T, bool PAD>
+__global__ void k_zpad_rowfft(const T *__restrict__ x, cx<T> *__restrict__ grid, const T *__restrict__ icorr,
+                              const cx<T> *__restrict__ tw, int N, int logNp) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
+    const int Np = 1 << logNp;
+    const int iy = blockIdx.x;
+    const T cy = icorr[iy];
+    for (int gx = threadIdx.x; gx < Np; gx += blockDim.x) {
+        const int ix = (gx + N / 2) & (Np - 1);
+        T v = 0;
+        if (ix < N) v = x[(size_t)iy * N + ix] * icorr[ix] * cy;
+        s[pidx<PAD>(gx)] = mk<T>(v, (T)0);
+    }
+    __syncthreads();
+    fft_lds<T, PAD>(s, logNp, 0, tw, 1, false);
+    const int gy = (iy - N / 2) & (Np - 1);
+    cx<T> *row = grid + (size_t)gy * Np;
+    for (int k = threadIdx.x; k < Np; k += blockDim.x) row[k] = s[pidx<PAD>(k)];
+}
+
+// Inverse row DFT of grid row (iy - N/2) mod N', then crop, correction, real part:
+// out[iy][ix] = Re{row[(ix - N/2) mod N']} / (kappa_hat_x kappa_hat_y).
+template <typename T, bool PAD>
+__global__ void k_irowfft_crop(const cx<T> *__restrict__ grid, T *__restrict__ out, const T *__restrict__ icorr,
+                               const cx<T> *__restrict__ tw, int N, int logNp) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
+    const int Np = 1 << logNp;
+    const int iy = blockIdx.x;
+    const int gy = (iy - N / 2) & (Np - 1);
+    const cx<T> *row = grid + (size_t)gy * Np;
+    for (int k = threadIdx.x; k < Np; k += blockDim.x) s[pidx<PAD>(k)] = row[k];
+    __syncthreads();
+    fft_lds<T, PAD>(s, logNp, 0, tw, 1, true);
+    const T cy = icorr[iy];
+    for (int ix = threadIdx.x; ix < N; ix += blockDim.x) {
+        const int gx = (ix - N / 2) & (Np - 1);
+        out[(size_t)iy * N + ix] = s[pidx<PAD>(gx)].x * icorr[ix] * cy;
+    }
+}
+
+// Four-step pass A (in place): rows n2 + N2*n1 of stripe [x0, x0+CW).
+template <typename T>
+__global__ void k_colpass_a(cx<T> *__restrict__ grid, const cx<T> *__restrict__ tw, int N, int logNp, int logN1,
+                            int logN2, int logCW, int band_in, int inv) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
+    const int Np = 1 << logNp, N1 = 1 << logN1, N2 = 1 << logN2, CW = 1 << logCW;
+    const int x0 = blockIdx.x * CW, n2 = blockIdx.y;
+    const int nel = N1 * CW;
+    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+        const int n1 = e >> logCW, c = e & (CW - 1);
+        const int r = n2 + N2 * n1;
+        cx<T> v = mk<T>((T)0, (T)0);
+        if (!band_in || in_band(r, N, Np)) v = grid[(size_t)r * Np + x0 + c];
+        s[e] = v;
+    }
+    __syncthreads();
+    fft_lds<T, false>(s, logN1, logCW, tw, Np >> logN1, inv != 0);
+    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+        const int k1 = e >> logCW, c = e & (CW - 1);
+        cx<T> w = tw[n2 * k1];
+        if (inv) w.y = -w.y;
+        grid[(size_t)(n2 + N2 * k1) * Np + x0 + c] = s[e] * w;
+    }
+}
+
+// Four-step pass B (out of place): rows N2*k1 + n2 -> rows k1 + N1*k2.
+template <typename T>
+__global__ void k_colpass_b(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, const cx<T> *__restrict__ tw,
+                            int N, int logNp, int logN1, int logN2, int logCW, int band_out, int inv) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
+    const int Np = 1 << logNp, N1 = 1 << logN1, N2 = 1 << logN2, CW = 1 << logCW;
+    const int x0 = blockIdx.x * CW, k1 = blockIdx.y;
+    const int nel = N2 * CW;
+    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+        const int n2 = e >> logCW, c = e & (CW - 1);
+        s[e] = in[(size_t)(N2 * k1 + n2) * Np + x0 + c];
+    }
+    __syncthreads();
+    fft_lds<T, false>(s, logN2, logCW, tw, Np >> logN2, inv != 0);
+    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+        const int k2 = e >> logCW, c = e & (CW - 1);
+        const int r = k1 + N1 * k2;
+        if (!band_out || in_band(r, N, Np)) out[(size_t)r * Np + x0 + c] = s[e];
+    }
+}
+
+int threads_for(int L, int CW) { return L * CW / 16 < 64 ? 64 : L * CW / 16; }
+
+template <typename T>
+void colfft(ri_ctx *c, cx<T> *grid_io, cx<T> *grid_out, const cx<T> *tw, bool inv, bool band_in, bool band_out,
+            hipStream_t s) {
+    const int logNp = c->logNp, Np = c->Np;
+    const int logN1 = (logNp + 1) / 2, logN2 = logNp / 2;
+    int logCW = sizeof(T) == 4 ? 6 : 5;
+    if ((1 << logCW) > Np) logCW = logNp;
+    const int CW = 1 << logCW;
+    {
+        const int L = 1 << logN1;
+        dim3 grid(Np / CW, 1 << logN2);
+        size_t lds = sizeof(cx<T>) * (size_t)L * CW;
+        hipLaunchKernelGGL(k_colpass_a<T>, grid, dim3(threads_for(L, CW)), lds, s, grid_io, tw, c->N, logNp, logN1,
+                           logN2, logCW, band_in ? 1 : 0, inv ? 1 : 0);
+    }
+    {
+        const int L = 1 << logN2;
+        dim3 grid(Np / CW, 1 << logN1);
+        size_t lds = sizeof(cx<T>) * (size_t)L * CW;
+        hipLaunchKernelGGL(k_colpass_b<T>, grid, dim3(threads_for(L, CW)), lds, s, grid_io, grid_out, tw, c->N,
+                           logNp, logN1, logN2, logCW, band_out ? 1 : 0, inv ? 1 : 0);
+    }
+}
+
+}  // namespace
+
+// x (N x N) -> F Z x in p.gridB (row FFT into gridA band rows, columns A in place, B into gridB)
+// Row transforms pad LDS by one element per 32 (fewer bank conflicts) when it fits.
+template <typename T>
+bool row_pad(ri_ctx *c) { return sizeof(cx<T>) * (size_t)(c->Np + c->Np / 32) <= (size_t)c->dev.lds_per_block; }
+
+template <typename T>
+size_t row_lds(ri_ctx *c) { return sizeof(cx<T>) * (size_t)(row_pad<T>(c) ? c->Np + c->Np / 32 : c->Np); }
+
+template <typename T>
+void fwd_zpad_fft(ri_ctx *c, Prec<T> &p, const T *x, hipStream_t s) {
+    const int Np = c->Np;
+    if (sizeof(cx<T>) * (size_t)Np > (size_t)c->dev.lds_per_block)
+        throw Error(RI_EUNSUPPORTED, "grid row does not fit the workgroup LDS");
+    if (row_pad<T>(c))
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_zpad_rowfft<T, true>), dim3(c->N), dim3(threads_for(Np, 1)), row_lds<T>(c),
+                           s, x, p.gridA, p.icorr, p.tw, c->N, c->logNp);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_zpad_rowfft<T, false>), dim3(c->N), dim3(threads_for(Np, 1)),
+                           row_lds<T>(c), s, x, p.gridA, p.icorr, p.tw, c->N, c->logNp);
+    colfft<T>(c, p.gridA, p.gridB, p.tw, false, true, false, s);
+}
+
+// p.gridA (Y = G^H r, full grid) -> Re Z^dagger F^dagger Y into x (N x N); gridA is clobbered
+template <typename T>
+void adj_fft_crop(ri_ctx *c, Prec<T> &p, T *x, hipStream_t s) {
+    const int Np = c->Np;
+    colfft<T>(c, p.gridA, p.gridB, p.tw, true, false, true, s);
+    if (row_pad<T>(c))
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_irowfft_crop<T, true>), dim3(c->N), dim3(threads_for(Np, 1)),
+                           row_lds<T>(c), s, p.gridB, x, p.icorr, p.tw, c->N, c->logNp);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_irowfft_crop<T, false>), dim3(c->N), dim3(threads_for(Np, 1)),
+                           row_lds<T>(c), s, p.gridB, x, p.icorr, p.tw, c->N, c->logNp);
+}
+
+template void fwd_zpad_fft<float>(ri_ctx *, Prec<float> &, const float *, hipStream_t);
+template void fwd_zpad_fft<double>(ri_ctx *, Prec<double> &, const double *, hipStream_t);
+template void adj_fft_crop<float>(ri_ctx *, Prec<float> &, float *, hipStream_t);
+template void adj_fft_crop<double>(ri_ctx *, Prec<double> &, double *, hipStream_t);
+
+}  // namespace ri

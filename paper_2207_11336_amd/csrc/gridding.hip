@@ -1,0 +1,375 @@
+// G (degridding), G^H (gridding) and the fused degrid -> residual -> grid pass
+// of the data-fidelity gradient (paper eq. 1 and appendix A; the per-block sum
+// of eq. E2 is a loop over work items of one persistent launch).
+//
+// Row m of G (appendix E: interpolation kernel convolved row-wise with a small
+// w-kernel) is separable: G_{m,(ky,kx)} = g_v[ay] g_u[ax] on the window of side
+// S = 7 + 2h around the centre cell c = floor(p + 1/2), with per axis
+//   g[a] = sum_{|q| <= h} k_w[q] kappa(f - a + h + 3 - q),  f = p - c,
+// kappa the Kaiser-Bessel kernel (J = 7) and k_w the w-plane taps.
+//
+// Work item = one uv tile (T x T cells) of one data block, or a chunk of it.
+// A workgroup stages the item's input subgrid X (T + 2H)^2 and an output
+// subgrid Y in LDS, walks the item's visibilities (one 16-lane group per
+// visibility, taps spread over the lanes), and flushes Y to the global grid
+// with float atomics. Workgroups pull items from a global counter
+// (persistent launch), largest items first.
+#include "ri_internal.h"
+
+namespace ri {
+
+namespace {
+
+constexpr int GROUPS = 16;         // visibilities in flight per 256-thread workgroup
+constexpr int MAXI = 19;           // ceil(17^2 / 16): tap slots per lane
+constexpr int SCR_KB = 16;         // per-group KB scratch (two axes x 8)
+constexpr int SCR_G = 36;          // per-group axis weights (two axes x 18)
+
+template <typename T>
+struct TileArgs {
+    const TileItem *items;
+    int n_items;
+    int *counter;
+    int tile, H, W, logNp, jh, hmax;
+    T beta, inv_i0beta;
+    const uint32_t *cell;
+    const T *frac;
+    const uint16_t *plane;
+    const int32_t *plane_h;
+    const cx<T> *wtaps;
+    const int32_t *perm;
+    const int64_t *rowptr;
+    const cx<T> *gval;
+    const int32_t *gcol;
+    const cx<T> *X;
+    cx<T> *Y;
+    const cx<T> *ysorted;
+    const cx<T> *yuser;
+    cx<T> *yout;
+    double *r2part;
+};
+
+// Kaiser-Bessel weight kappa(t) = I0(beta sqrt(1 - (2t/7)^2)) / I0(beta), I0
+// from its power series (24 terms reach FP32 rounding for beta ~ 16.3, 32 FP64).
+template <typename T>
+__device__ __forceinline__ T kb_weight(T t, T beta, T inv_i0beta) {
+    const T u = t * (T)(2.0 / 7.0);
+    const T z = (T)1 - u * u;
+    if (z < (T)0) return (T)0;
+    const T x = beta * sqrt(z);
+    const T q = x * x * (T)0.25;
+    constexpr int K = sizeof(T) == 4 ? 24 : 32;
+    T term = (T)1, sum = (T)1;
+#pragma unroll
+    for (int k = 1; k <= K; ++k) {
+        term = term * q * (T)(1.0 / ((double)k * (double)k));
+        sum = sum + term;
+    }
+    return sum * inv_i0beta;
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_xor16(T v, int o) { return __shfl_xor(v, o, 16); }
+
+template <typename T>
+__device__ __forceinline__ void lds_add(T *p, T v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ void global_add(T *p, T v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Axis weights of one G row into gg[0..S) (u) and gg[18..18+S) (v); 16 lanes.
+template <typename T>
+__device__ __forceinline__ void axis_weights(const TileArgs<T> &a, int m, int pl, int h, int S, int lane, T *kbg,
+                                             cx<T> *gg) {
+    const T fu = a.frac[2 * (size_t)m], fv = a.frac[2 * (size_t)m + 1];
+    if (lane < 7) kbg[lane] = kb_weight<T>(fu - (T)(lane - 3), a.beta, a.inv_i0beta);
+    else if (lane >= 8 && lane < 15) kbg[lane] = kb_weight<T>(fv - (T)(lane - 11), a.beta, a.inv_i0beta);
+    wave_sync();
+    const cx<T> *kt = a.wtaps + (size_t)pl * (2 * a.hmax + 1) + a.hmax;
+    for (int idx = lane; idx < 2 * S; idx += 16) {
+        const int axis = idx < S ? 0 : 1;
+        const int ax = idx - axis * S;
+        const int ap = ax - h - 3;
+        const int qlo = max(-h, -3 - ap), qhi = min(h, 3 - ap);
+        cx<T> acc = mk<T>((T)0, (T)0);
+        for (int q = qlo; q <= qhi; ++q) acc = acc + scale(kt[q], kbg[axis * 8 + ap + q + 3]);
+        gg[axis * 18 + ax] = acc;
+    }
+    wave_sync();
+}
+
+template <typename T, int OP, bool OTF>
+__global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
+    // All LDS is dynamic and starts at byte 0: a static __shared__ variable
+    // would shift the dynamic block by its size and misalign the 8-byte
+    // atomics on the FP64 subgrid. Layout: Xs, Ys, KB scratch, axis weights,
+    // reduction slots, item slot (every part a multiple of 16 bytes).
+    extern __shared__ unsigned char smem_raw[];
+    const int W = a.W, WW = W * W;
+    cx<T> *Xs = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *Ys = Xs + ((OP & OP_DEGRID) ? WW : 0);
+    T *kbs = reinterpret_cast<T *>(Ys + ((OP & OP_GRID) ? WW : 0));
+    cx<T> *gs = reinterpret_cast<cx<T> *>(kbs + GROUPS * SCR_KB);
+    double *s_red = reinterpret_cast<double *>(gs + GROUPS * SCR_G);
+    int &s_item = *reinterpret_cast<int *>(s_red + 4);
+    const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
+    T *kbg = kbs + grp * SCR_KB;
+    cx<T> *gg = gs + grp * SCR_G;
+    const int Npm = (1 << a.logNp) - 1;
+    double r2 = 0.0;
+
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= a.n_items) break;
+        const TileItem item = a.items[it];
+        const int y0 = item.ty0 - a.H, x0 = item.tx0 - a.H;
+        if (OP & OP_DEGRID) {
+            for (int e = tid; e < WW; e += blockDim.x) {
+                const int r = e / W, cc = e - r * W;
+                Xs[e] = a.X[((size_t)((y0 + r) & Npm) << a.logNp) + ((x0 + cc) & Npm)];
+            }
+        }
+        if (OP & OP_GRID) {
+            for (int e = tid; e < WW; e += blockDim.x) Ys[e] = mk<T>((T)0, (T)0);
+        }
+        __syncthreads();
+
+        for (int vi = grp; vi < item.vc; vi += GROUPS) {
+            const int m = item.vb + vi;
+            const uint32_t cell = a.cell[m];
+            const int cu = (int)(cell & 0xFFFFu), cv = (int)(cell >> 16);
+            const int pl = a.plane[m];
+            const int h = a.plane_h[pl];
+            const int S = 2 * h + 7, SS = S * S;
+            const int base = (cv - item.ty0 + a.H - h - 3) * W + (cu - item.tx0 + a.H - h - 3);
+            if (OTF) axis_weights<T>(a, m, pl, h, S, lane, kbg, gg);
+            const float invS = 1.0f / (float)S;
+            const int NI = (SS + 15) >> 4;
+            int64_t rp = 0;
+            if (!OTF) rp = a.rowptr[m];
+            cx<T> wv[MAXI];
+            int li[MAXI];
+            cx<T> acc = mk<T>((T)0, (T)0);
+#pragma unroll
+            for (int i = 0; i < MAXI; ++i) {
+                wv[i] = mk<T>((T)0, (T)0);
+                li[i] = base;
+                if (i < NI) {
+                    const int t = lane + 16 * i;
+                    if (t < SS) {
+                        if (OTF) {
+                            const int ay = (int)(((float)t + 0.5f) * invS);
+                            const int ax = t - ay * S;
+                            wv[i] = gg[18 + ay] * gg[ax];
+                            li[i] = base + ay * W + ax;
+                        } else {
+                            wv[i] = a.gval[rp + t];
+                            const int col = a.gcol[rp + t];
+                            const int gy = col >> a.logNp, gx = col & Npm;
+                            li[i] = ((gy - y0) & Npm) * W + ((gx - x0) & Npm);
+                        }
+                        if (OP & OP_DEGRID) acc = acc + wv[i] * Xs[li[i]];
+                    }
+                }
+            }
+            cx<T> r;
+            if (OP & OP_DEGRID) {
+#pragma unroll
+                for (int o = 8; o >= 1; o >>= 1) {
+                    acc.x += shfl_xor16(acc.x, o);
+                    acc.y += shfl_xor16(acc.y, o);
+                }
+            }
+            if (OP == OP_DEGRID) {
+                if (lane == 0) a.yout[a.perm[m]] = acc;
+            } else if (OP == OP_FUSED) {
+                r = acc;
+                if (a.ysorted) r = r - a.ysorted[m];
+                if (lane == 0) r2 += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+            } else {
+                r = a.yuser[a.perm[m]];
+            }
+            if (OP & OP_GRID) {
+#pragma unroll
+                for (int i = 0; i < MAXI; ++i) {
+                    if (i < NI && lane + 16 * i < SS) {
+                        const cx<T> c = mulc(r, wv[i]);
+                        lds_add(&Ys[li[i]].x, c.x);
+                        lds_add(&Ys[li[i]].y, c.y);
+                    }
+                }
+            }
+            if (OTF) wave_sync();   // gg/kbg are rewritten by the group's next visibility
+        }
+        __syncthreads();
+        if (OP & OP_GRID) {
+            for (int e = tid; e < WW; e += blockDim.x) {
+                const cx<T> v = Ys[e];
+                if (v.x != (T)0 || v.y != (T)0) {
+                    const int r = e / W, cc = e - r * W;
+                    cx<T> *dst = a.Y + ((size_t)((y0 + r) & Npm) << a.logNp) + ((x0 + cc) & Npm);
+                    global_add(&dst->x, v.x);
+                    global_add(&dst->y, v.y);
+                }
+            }
+        }
+    }
+    if (OP == OP_FUSED) {
+        for (int o = 32; o >= 1; o >>= 1) r2 += __shfl_xor(r2, o);
+        if ((tid & 63) == 0) s_red[tid >> 6] = r2;
+        __syncthreads();
+        if (tid == 0) a.r2part[blockIdx.x] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    }
+}
+
+// CSR G fill: values (FP64 arithmetic, rounded to T) and flat columns.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill_csr(TileArgs<double> a, int64_t M, const int64_t *rowptr,
+                                                  cx<T> *val, int32_t *col) {
+    __shared__ double kbs[GROUPS * SCR_KB];
+    __shared__ cx<double> gs[GROUPS * SCR_G];
+    const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
+    double *kbg = kbs + grp * SCR_KB;
+    cx<double> *gg = gs + grp * SCR_G;
+    const int Np = 1 << a.logNp, Npm = Np - 1;
+    for (int64_t m = (int64_t)blockIdx.x * GROUPS + grp; m < M; m += (int64_t)gridDim.x * GROUPS) {
+        const uint32_t cell = a.cell[m];
+        const int cu = (int)(cell & 0xFFFFu), cv = (int)(cell >> 16);
+        const int pl = a.plane[m];
+        const int h = a.plane_h[pl];
+        const int S = 2 * h + 7, SS = S * S;
+        axis_weights<double>(a, (int)m, pl, h, S, lane, kbg, gg);
+        const int64_t rp = rowptr[m];
+        for (int t = lane; t < SS; t += 16) {
+            const int ay = t / S, ax = t - ay * S;
+            const cx<double> w = gg[18 + ay] * gg[ax];
+            val[rp + t] = mk<T>((T)w.x, (T)w.y);
+            const int gy = (cv + ay - h - 3) & Npm, gx = (cu + ax - h - 3) & Npm;
+            col[rp + t] = gy * Np + gx;
+        }
+        wave_sync();
+    }
+}
+
+template <typename T>
+TileArgs<T> make_args(ri_ctx *c, const View &v, Prec<T> &p) {
+    TileArgs<T> a{};
+    a.items = v.items;
+    a.n_items = v.n_items;
+    a.counter = c->d_counter;
+    a.tile = v.tile;
+    a.H = c->H;
+    a.W = v.tile + 2 * c->H;
+    a.logNp = c->logNp;
+    a.jh = c->jh;
+    a.hmax = c->hmax;
+    a.beta = (T)c->beta;
+    double i0b = 1.0, t = 1.0, q = 0.25 * c->beta * c->beta;
+    for (int k = 1; k < 500; ++k) { t = t * q / ((double)k * k); i0b += t; if (t < 1e-17 * i0b) break; }
+    a.inv_i0beta = (T)(1.0 / i0b);
+    a.cell = v.cell;
+    a.frac = (const T *)v.frac;
+    a.plane = v.plane;
+    a.plane_h = c->d_plane_h;
+    a.wtaps = p.wtaps;
+    a.perm = v.perm;
+    return a;
+}
+
+template <typename T, int OP, bool OTF>
+void launch_op(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
+    const size_t WW = (size_t)a.W * a.W;
+    size_t lds = sizeof(cx<T>) * WW * (((OP & OP_DEGRID) ? 1 : 0) + ((OP & OP_GRID) ? 1 : 0));
+    lds += sizeof(T) * GROUPS * SCR_KB + sizeof(cx<T>) * GROUPS * SCR_G + 4 * sizeof(double) + 16;
+    if (lds + 64 > (size_t)c->dev.lds_per_block)
+        throw Error(RI_EUNSUPPORTED, "tile " + std::to_string(a.tile) + " needs " + std::to_string(lds) +
+                                         " B of LDS per workgroup; device allows " +
+                                         std::to_string(c->dev.lds_per_block));
+    int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / (lds + 1024)));
+    int nwg = std::min(c->dev.cu_count * per_cu, std::max(1, a.n_items));
+    if (nwg > c->n_partials) nwg = c->n_partials;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tiles<T, OP, OTF>), dim3(nwg), dim3(256), lds, s, a);
+    if (OP == OP_FUSED && nwg < c->n_partials) fill_zero_f64(a.r2part + nwg, c->n_partials - nwg, s);
+}
+
+}  // namespace
+
+int tiles_partials(ri_ctx *c) { return c->dev.cu_count * 8; }
+
+template <typename T>
+void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, int op, bool otf, const cx<T> *y_sorted,
+                  const cx<T> *y_user, cx<T> *y_out_user, double *r2_partials, hipStream_t s) {
+    if (c->M == 0 || v.n_items == 0) {
+        if (op == OP_FUSED && r2_partials) fill_zero_f64(r2_partials, c->n_partials, s);
+        return;
+    }
+    TileArgs<T> a = make_args<T>(c, v, p);
+    a.X = p.gridB;
+    a.Y = p.gridA;
+    a.ysorted = y_sorted;
+    a.yuser = y_user;
+    a.yout = y_out_user;
+    a.r2part = r2_partials;
+    if (!otf) {
+        a.rowptr = c->csr.rowptr;
+        a.gval = (const cx<T> *)c->csr.val;
+        a.gcol = c->csr.col;
+    }
+    fill_zero_i32(c->d_counter, 1, s);
+    if (otf) {
+        if (op == OP_DEGRID) launch_op<T, OP_DEGRID, true>(c, a, s);
+        else if (op == OP_GRID) launch_op<T, OP_GRID, true>(c, a, s);
+        else launch_op<T, OP_FUSED, true>(c, a, s);
+    } else {
+        if (op == OP_DEGRID) launch_op<T, OP_DEGRID, false>(c, a, s);
+        else if (op == OP_GRID) launch_op<T, OP_GRID, false>(c, a, s);
+        else launch_op<T, OP_FUSED, false>(c, a, s);
+    }
+    RI_CHECK_HIP(hipGetLastError());
+}
+
+template <typename T>
+void fill_csr(ri_ctx *c, hipStream_t s) {
+    const View &v = c->view;
+    if (v.frac_bytes != 8) throw Error(RI_EINVAL, "CSR fill needs FP64 fractions");
+    // row pointers (internal order)
+    std::vector<int64_t> rp(c->M + 1, 0);
+    for (int64_t i = 0; i < c->M; ++i) {
+        const int S = 2 * c->plane_h[c->plane[v.perm_host[i]]] + c->J;
+        rp[i + 1] = rp[i] + (int64_t)S * S;
+    }
+    c->csr.nnz = rp[c->M];
+    c->csr.val_bytes = (int)sizeof(cx<T>);
+    c->csr.rowptr = (int64_t *)dev_alloc(c, sizeof(int64_t) * (c->M + 1));
+    RI_CHECK_HIP(hipMemcpy(c->csr.rowptr, rp.data(), sizeof(int64_t) * (c->M + 1), hipMemcpyHostToDevice));
+    c->csr.val = dev_alloc(c, sizeof(cx<T>) * (size_t)c->csr.nnz);
+    c->csr.col = (int32_t *)dev_alloc(c, sizeof(int32_t) * (size_t)c->csr.nnz);
+    ensure_prec<double>(c, c->p64);
+    TileArgs<double> a = make_args<double>(c, v, c->p64);
+    if (c->M > 0) {
+        int nwg = (int)std::min<int64_t>((c->M + GROUPS - 1) / GROUPS, (int64_t)c->dev.cu_count * 16);
+        hipLaunchKernelGGL(k_fill_csr<T>, dim3(nwg), dim3(256), 0, s, a, c->M, c->csr.rowptr, (cx<T> *)c->csr.val,
+                           c->csr.col);
+        RI_CHECK_HIP(hipGetLastError());
+    }
+}
+
+template void launch_tiles<float>(ri_ctx *, const View &, Prec<float> &, int, bool, const cx<float> *,
+                                  const cx<float> *, cx<float> *, double *, hipStream_t);
+template void launch_tiles<double>(ri_ctx *, const View &, Prec<double> &, int, bool, const cx<double> *,
+                                   const cx<double> *, cx<double> *, double *, hipStream_t);
+template void fill_csr<float>(ri_ctx *, hipStream_t);
+template void fill_csr<double>(ri_ctx *, hipStream_t);
+
+}  // namespace ri

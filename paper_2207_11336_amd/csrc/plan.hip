@@ -1,0 +1,360 @@
+// Plan construction for one context: per-visibility grid cells, w-planes,
+// w-kernel tables, the tile sort into work items, and the device tables.
+//
+// Everything here runs once per context (the paper builds its sparse
+// operator blocks "only once" at initialisation, appendix E). The integer
+// decisions (window centre, w-plane, support) are taken in FP64 with
+// contraction disabled so that they are reproducible bit for bit.
+#pragma clang fp contract(off)
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "ri_internal.h"
+
+namespace ri {
+
+void *dev_alloc(ri_ctx *c, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(RI_ENOMEM, "hipMalloc(" + std::to_string(bytes) + " B) failed: " + hipGetErrorString(e));
+    }
+    c->device_bytes += (int64_t)bytes;
+    return p;
+}
+
+void dev_free(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+template <typename V>
+static V *upload(ri_ctx *c, const V *host, size_t n) {
+    V *d = (V *)dev_alloc(c, n * sizeof(V));
+    RI_CHECK_HIP(hipMemcpy(d, host, n * sizeof(V), hipMemcpyHostToDevice));
+    return d;
+}
+
+// Modified Bessel I0 by its defining power series (FP64).
+static double bessel_i0(double x) {
+    double q = 0.25 * x * x, t = 1.0, s = 1.0;
+    for (int k = 1; k < 500; ++k) {
+        t = t * q / ((double)k * k);
+        s += t;
+        if (t < 1e-17 * s) break;
+    }
+    return s;
+}
+
+// kappa_hat(nu) / (J / I0(beta)): sinh(a)/a, a^2 = beta^2 - (pi J nu)^2.
+static double kb_transform(double nu, int J, double beta) {
+    double z = M_PI * J * nu, a2 = beta * beta - z * z;
+    double r = a2 > 0 ? std::sinh(std::sqrt(a2)) / std::sqrt(a2)
+                      : (a2 < 0 ? std::sin(std::sqrt(-a2)) / std::sqrt(-a2) : 1.0);
+    return J * r / bessel_i0(beta);
+}
+
+// ---------------------------------------------------------------------------
+// w-kernel taps by least squares: find k[q], |q| <= h, minimising
+//   sum_{n=-N/2}^{N/2-1} | exp(i pi w (n delta)^2) - sum_q k[q] e^{2 pi i q n / N'} |^2.
+// The design matrix depends only on h, so it is factorised once per h by
+// modified Gram-Schmidt applied twice (Q R with Q orthonormal columns).
+// ---------------------------------------------------------------------------
+namespace {
+using zc = std::complex<double>;
+struct QR {
+    int K = 0, N = 0;
+    std::vector<zc> Q;   // [K][N] columns
+    std::vector<zc> R;   // [K][K] upper triangular
+};
+
+QR factor(int h, int N, int Np) {
+    QR f;
+    f.K = 2 * h + 1;
+    f.N = N;
+    f.Q.resize((size_t)f.K * N);
+    f.R.assign((size_t)f.K * f.K, zc(0, 0));
+    for (int j = 0; j < f.K; ++j) {
+        int q = j - h;
+        zc *col = &f.Q[(size_t)j * N];
+        for (int i = 0; i < N; ++i) {
+            double n = (double)(i - N / 2);
+            double ph = 2.0 * M_PI * (double)q * n / (double)Np;
+            col[i] = zc(std::cos(ph), std::sin(ph));
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int k = 0; k < j; ++k) {
+                const zc *qk = &f.Q[(size_t)k * N];
+                zc d(0, 0);
+                for (int i = 0; i < N; ++i) d += std::conj(qk[i]) * col[i];
+                for (int i = 0; i < N; ++i) col[i] -= d * qk[i];
+                f.R[(size_t)k * f.K + j] += d;
+            }
+        }
+        double nr = 0;
+        for (int i = 0; i < N; ++i) nr += std::norm(col[i]);
+        nr = std::sqrt(nr);
+        for (int i = 0; i < N; ++i) col[i] /= nr;
+        f.R[(size_t)j * f.K + j] = nr;
+    }
+    return f;
+}
+
+void solve_taps(const QR &f, double w, double cell, zc *out) {
+    const int K = f.K, N = f.N;
+    std::vector<zc> b(K, zc(0, 0));
+    std::vector<zc> c(N);
+    for (int i = 0; i < N; ++i) {
+        double n = (double)(i - N / 2) * cell;
+        double ph = M_PI * w * n * n;
+        c[i] = zc(std::cos(ph), std::sin(ph));
+    }
+    for (int k = 0; k < K; ++k) {
+        const zc *qk = &f.Q[(size_t)k * N];
+        zc d(0, 0);
+        for (int i = 0; i < N; ++i) d += std::conj(qk[i]) * c[i];
+        b[k] = d;
+    }
+    for (int k = K - 1; k >= 0; --k) {      // back substitution R x = b
+        zc s = b[k];
+        for (int j = k + 1; j < K; ++j) s -= f.R[(size_t)k * K + j] * out[j];
+        out[k] = s / f.R[(size_t)k * K + k];
+    }
+}
+
+template <typename F>
+void parallel_for(int64_t n, F fn) {
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 4096 || nt == 1) { fn(0, n); return; }
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t) {
+        int64_t a = n * t / nt, b = n * (t + 1) / nt;
+        th.emplace_back([=, &fn] { fn(a, b); });
+    }
+    for (auto &x : th) x.join();
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Per-visibility quantities (caller order) and the w-plane tables.
+// ---------------------------------------------------------------------------
+void build_plan(ri_ctx *c, const double *uvw) {
+    const ri_plan_desc &d = c->d;
+    const int64_t M = c->M;
+    const int P = d.n_wplanes, P_half = (P - 1) / 2;
+    const double W = d.w_max;
+    const double scale = (double)c->Np / (2.0 * M_PI);
+
+    c->pu.resize(M); c->pv.resize(M); c->cu.resize(M); c->cv.resize(M); c->plane.resize(M);
+    std::vector<int> bad(1, 0);
+    parallel_for(M, [&](int64_t a, int64_t b) {
+        for (int64_t m = a; m < b; ++m) {
+            double ou = uvw[3 * m], ov = uvw[3 * m + 1], w = uvw[3 * m + 2];
+            if (!std::isfinite(ou) || !std::isfinite(ov) || !std::isfinite(w) ||
+                std::fabs(ou) >= M_PI || std::fabs(ov) >= M_PI) { bad[0] = 1; continue; }
+            double pu = ou * scale, pv = ov * scale;
+            double fu = std::floor(pu + 0.5), fv = std::floor(pv + 0.5);
+            c->pu[m] = pu; c->pv[m] = pv;
+            int64_t iu = (int64_t)fu, iv = (int64_t)fv;
+            c->cu[m] = (int32_t)(((iu % c->Np) + c->Np) % c->Np);
+            c->cv[m] = (int32_t)(((iv % c->Np) + c->Np) % c->Np);
+            int j = 0;
+            if (P_half > 0 && W != 0.0) {
+                double dw = W / (double)P_half;
+                double jj = std::floor(w / dw + 0.5);
+                if (jj < -P_half) jj = -P_half;
+                if (jj > P_half) jj = P_half;
+                j = (int)jj + P_half;
+            }
+            c->plane[m] = j;
+        }
+    });
+    if (bad[0]) throw Error(RI_EINVAL, "uvw holds a non-finite value or |omega| >= pi");
+
+    // per-plane support and least-squares taps
+    c->plane_h.assign(P, 0);
+    const int K = 2 * c->hmax + 1;
+    c->wtaps64.assign((size_t)P * K * 2, 0.0);
+    std::vector<double> wj(P, 0.0);
+    if (P_half > 0 && W != 0.0) {
+        double dw = W / (double)P_half;
+        for (int j = 0; j < P; ++j) wj[j] = (double)(j - P_half) * dw;
+    }
+    for (int j = 0; j < P; ++j) {
+        if (wj[j] == 0.0) continue;
+        double hex = std::fabs(wj[j]) * (double)d.oversample * (double)c->N * (double)c->N *
+                     d.cell_rad * d.cell_rad * 0.5;
+        c->plane_h[j] = std::min(c->hmax, (int)std::ceil(hex) + 1);
+    }
+    std::vector<char> used(P, 0);
+    for (int64_t m = 0; m < M; ++m) used[c->plane[m]] = 1;
+    std::vector<QR> fac(c->hmax + 1);
+    std::vector<char> have(c->hmax + 1, 0);
+    for (int j = 0; j < P; ++j)
+        if (used[j]) have[c->plane_h[j]] = 1;
+    for (int h = 0; h <= c->hmax; ++h)
+        if (have[h]) fac[h] = factor(h, c->N, c->Np);
+    parallel_for(P * 16, [&](int64_t a, int64_t b) {      // oversubscribe: planes are cheap
+        for (int64_t jj = a; jj < b; ++jj) {
+            if (jj % 16) continue;
+            int j = (int)(jj / 16);
+            if (!used[j]) continue;
+            int h = c->plane_h[j];
+            zc tap[16];
+            if (wj[j] == 0.0) { for (int k = 0; k < 2 * h + 1; ++k) tap[k] = zc(k == h ? 1.0 : 0.0, 0.0); }
+            else solve_taps(fac[h], wj[j], d.cell_rad, tap);
+            for (int q = -h; q <= h; ++q) {
+                size_t o = ((size_t)j * K + (q + c->hmax)) * 2;
+                c->wtaps64[o] = tap[q + h].real();
+                c->wtaps64[o + 1] = tap[q + h].imag();
+            }
+        }
+    });
+    c->d_plane_h = upload(c, c->plane_h.data(), (size_t)P);
+}
+
+// ---------------------------------------------------------------------------
+// Tile sort: order visibilities by (block, uv tile, support, plane, index),
+// cut each (block, tile) run into work items and sort the items by decreasing
+// work so the persistent launch hands out the largest first.
+// ---------------------------------------------------------------------------
+void build_view(ri_ctx *c, View &v, int tile, int frac_bytes) {
+    const int64_t M = c->M;
+    const int Np = c->Np, nta = Np / tile;
+    const int64_t ntiles = (int64_t)nta * nta;
+    const int nb = (int)c->block_offsets.size() - 1;
+    const int64_t nbuckets = (int64_t)nb * ntiles;
+    v.tile = tile;
+    v.frac_bytes = frac_bytes;
+
+    std::vector<int64_t> bucket(M);
+    std::vector<int64_t> count(nbuckets + 1, 0);
+    for (int b = 0; b < nb; ++b)
+        for (int64_t m = c->block_offsets[b]; m < c->block_offsets[b + 1]; ++m) {
+            int64_t t = (int64_t)(c->cv[m] / tile) * nta + c->cu[m] / tile;
+            bucket[m] = (int64_t)b * ntiles + t;
+            count[bucket[m] + 1]++;
+        }
+    for (int64_t i = 0; i < nbuckets; ++i) count[i + 1] += count[i];
+    std::vector<int64_t> order(M);
+    {
+        std::vector<int64_t> pos(count.begin(), count.end() - 1);
+        for (int64_t m = 0; m < M; ++m) order[pos[bucket[m]]++] = m;   // stable
+    }
+    // inside each bucket: by (support, plane, caller index)
+    parallel_for(nbuckets, [&](int64_t a, int64_t b) {
+        for (int64_t k = a; k < b; ++k) {
+            int64_t s = count[k], e = count[k + 1];
+            if (e - s < 2) continue;
+            std::sort(order.begin() + s, order.begin() + e, [&](int64_t x, int64_t y) {
+                int hx = c->plane_h[c->plane[x]], hy = c->plane_h[c->plane[y]];
+                if (hx != hy) return hx < hy;
+                if (c->plane[x] != c->plane[y]) return c->plane[x] < c->plane[y];
+                return x < y;
+            });
+        }
+    });
+
+    // work items
+    const int64_t VMAX = 1024;
+    std::vector<TileItem> items;
+    std::vector<int64_t> work;
+    for (int64_t k = 0; k < nbuckets; ++k) {
+        int64_t s = count[k], e = count[k + 1];
+        int64_t t = k % ntiles;
+        for (int64_t a = s; a < e; a += VMAX) {
+            TileItem it;
+            it.ty0 = (int32_t)(t / nta) * tile;
+            it.tx0 = (int32_t)(t % nta) * tile;
+            it.vb = (int32_t)a;
+            it.vc = (int32_t)std::min(VMAX, e - a);
+            int64_t wsum = 0;
+            for (int64_t i = a; i < a + it.vc; ++i) {
+                int S = 2 * c->plane_h[c->plane[order[i]]] + c->J;
+                wsum += (int64_t)S * S;
+            }
+            items.push_back(it);
+            work.push_back(wsum + 4 * (int64_t)(tile + 2 * c->H) * (tile + 2 * c->H));
+        }
+    }
+    std::vector<int64_t> iord(items.size());
+    std::iota(iord.begin(), iord.end(), 0);
+    std::stable_sort(iord.begin(), iord.end(), [&](int64_t a, int64_t b) { return work[a] > work[b]; });
+    std::vector<TileItem> sorted_items(items.size());
+    v.max_item_vis = 0;
+    for (size_t i = 0; i < items.size(); ++i) {
+        sorted_items[i] = items[iord[i]];
+        v.max_item_vis = std::max<int64_t>(v.max_item_vis, sorted_items[i].vc);
+    }
+    v.n_items = (int)sorted_items.size();
+
+    // per-visibility arrays in internal order
+    std::vector<int32_t> perm(M);
+    std::vector<uint32_t> cell(M);
+    std::vector<uint16_t> pl(M);
+    std::vector<float> f32;
+    std::vector<double> f64;
+    if (frac_bytes == 4) f32.resize(2 * M); else f64.resize(2 * M);
+    for (int64_t i = 0; i < M; ++i) {
+        int64_t m = order[i];
+        perm[i] = (int32_t)m;
+        cell[i] = ((uint32_t)c->cv[m] << 16) | (uint32_t)c->cu[m];
+        pl[i] = (uint16_t)c->plane[m];
+        double fu = c->pu[m] - std::floor(c->pu[m] + 0.5);
+        double fv = c->pv[m] - std::floor(c->pv[m] + 0.5);
+        if (frac_bytes == 4) { f32[2 * i] = (float)fu; f32[2 * i + 1] = (float)fv; }
+        else { f64[2 * i] = fu; f64[2 * i + 1] = fv; }
+    }
+    v.perm_host.assign(order.begin(), order.end());
+    v.perm = upload(c, perm.data(), (size_t)M);
+    v.cell = upload(c, cell.data(), (size_t)M);
+    v.plane = upload(c, pl.data(), (size_t)M);
+    if (frac_bytes == 4) v.frac = upload(c, f32.data(), (size_t)(2 * M));
+    else v.frac = upload(c, f64.data(), (size_t)(2 * M));
+    v.items = upload(c, sorted_items.data(), sorted_items.size());
+}
+
+void free_view(View &v) {
+    dev_free(v.perm); dev_free(v.cell); dev_free(v.frac); dev_free(v.plane); dev_free(v.items);
+    v = View();
+}
+
+// ---------------------------------------------------------------------------
+// Tables and work buffers of one precision: 1/kappa_hat, twiddles, w-taps.
+// ---------------------------------------------------------------------------
+template <typename T>
+void ensure_prec(ri_ctx *c, Prec<T> &p) {
+    if (p.ready) return;
+    const int N = c->N, Np = c->Np;
+    std::vector<T> ic(N);
+    for (int i = 0; i < N; ++i) ic[i] = (T)(1.0 / kb_transform((double)(i - N / 2) / Np, c->J, c->beta));
+    p.icorr = upload(c, ic.data(), (size_t)N);
+    std::vector<cx<T>> tw(Np);
+    for (int k = 0; k < Np; ++k) {
+        double a = -2.0 * M_PI * (double)k / (double)Np;
+        tw[k] = mk<T>((T)std::cos(a), (T)std::sin(a));
+    }
+    p.tw = upload(c, tw.data(), (size_t)Np);
+    const size_t nt = c->wtaps64.size() / 2;
+    std::vector<cx<T>> wt(nt);
+    for (size_t i = 0; i < nt; ++i) wt[i] = mk<T>((T)c->wtaps64[2 * i], (T)c->wtaps64[2 * i + 1]);
+    p.wtaps = upload(c, wt.data(), nt);
+    p.gridA = (cx<T> *)dev_alloc(c, sizeof(cx<T>) * (size_t)Np * Np);
+    p.gridB = (cx<T> *)dev_alloc(c, sizeof(cx<T>) * (size_t)Np * Np);
+    p.img0 = (T *)dev_alloc(c, sizeof(T) * (size_t)N * N);
+    p.img1 = (T *)dev_alloc(c, sizeof(T) * (size_t)N * N);
+    p.ydata = (cx<T> *)dev_alloc(c, sizeof(cx<T>) * (size_t)std::max<int64_t>(c->M, 1));
+    p.ready = true;
+}
+
+template void ensure_prec<float>(ri_ctx *, Prec<float> &);
+template void ensure_prec<double>(ri_ctx *, Prec<double> &);
+
+}  // namespace ri

@@ -1,0 +1,502 @@
+// C ABI of libri.so: argument checks, context lifetime, and the sequencing of
+// the kernels for each entry point. Every numerical step runs in the HIP
+// kernels of fft.hip, gridding.hip and image.hip.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "ri_internal.h"
+
+using namespace ri;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+ri_status guard(const ri_ctx *c, F &&fn) {
+    try {
+        fn();
+        return RI_OK;
+    } catch (const Error &e) {
+        if (c) const_cast<ri_ctx *>(c)->err = e.msg;
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        if (c) const_cast<ri_ctx *>(c)->err = "host allocation failed";
+        g_last_error = "host allocation failed";
+        return RI_ENOMEM;
+    } catch (const std::exception &e) {
+        if (c) const_cast<ri_ctx *>(c)->err = e.what();
+        g_last_error = e.what();
+        return RI_EDEVICE;
+    }
+}
+
+void require(bool ok, const std::string &msg) {
+    if (!ok) throw Error(RI_EINVAL, msg);
+}
+
+size_t lds_for_tile(int tile, int H, int elem_bytes) {
+    const size_t W = (size_t)tile + 2 * H;
+    return 2 * W * W * elem_bytes + 16 * 16 * (elem_bytes / 2) + 16 * 36 * elem_bytes + 4 * 8 + 16;
+}
+
+int pick_tile(ri_ctx *c, int requested, int elem_bytes) {
+    int t = requested > 0 ? requested : 32;
+    if (t > c->Np) t = c->Np;
+    if (requested > 0) {
+        require((t & (t - 1)) == 0 || c->Np % t == 0, "tile must divide N'");
+        if (lds_for_tile(t, c->H, elem_bytes) > (size_t)c->dev.lds_per_block)
+            throw Error(RI_EUNSUPPORTED, "tile " + std::to_string(t) + " does not fit the workgroup LDS");
+        return t;
+    }
+    while (t > 8 && lds_for_tile(t, c->H, elem_bytes) > (size_t)c->dev.lds_per_block) t /= 2;
+    return t;
+}
+
+hipStream_t st(ri_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+double *tile_part(ri_ctx *c) { return c->d_partials; }
+double *img_part(ri_ctx *c) { return c->d_partials + tiles_partials(c); }
+
+// FP64 view for the power iteration: the main view when it already carries
+// FP64 fractions at a tile that fits FP64 subgrids, else a dedicated one.
+const View &view_fp64(ri_ctx *c) {
+    if (c->view.frac_bytes == 8 && lds_for_tile(c->view.tile, c->H, 16) <= (size_t)c->dev.lds_per_block)
+        return c->view;
+    if (!c->view64.items) build_view(c, c->view64, pick_tile(c, 0, 16), 8);
+    return c->view64;
+}
+
+template <typename T>
+Prec<T> &prec(ri_ctx *c);
+template <>
+Prec<float> &prec<float>(ri_ctx *c) { return c->p32; }
+template <>
+Prec<double> &prec<double>(ri_ctx *c) { return c->p64; }
+
+template <typename T>
+void do_forward(ri_ctx *c, const T *x, cx<T> *y, hipStream_t s) {
+    Prec<T> &p = prec<T>(c);
+    fwd_zpad_fft<T>(c, p, x, s);
+    launch_tiles<T>(c, c->view, p, OP_DEGRID, c->d.g_mode == RI_G_OTF, nullptr, nullptr, y, nullptr, s);
+}
+
+template <typename T>
+void do_adjoint(ri_ctx *c, const cx<T> *y, T *x, hipStream_t s) {
+    Prec<T> &p = prec<T>(c);
+    fill_zero<T>(p.gridA, (int64_t)c->Np * c->Np, s);
+    launch_tiles<T>(c, c->view, p, OP_GRID, c->d.g_mode == RI_G_OTF, nullptr, y, nullptr, nullptr, s);
+    adj_fft_crop<T>(c, p, x, s);
+}
+
+// g = Re{Phi^dagger (Phi x - y)} with y in internal order (or none); r2 partials in tile_part.
+template <typename T>
+void do_gradient(ri_ctx *c, const View &v, bool otf, const T *x, const cx<T> *y_sorted, T *g, hipStream_t s) {
+    Prec<T> &p = prec<T>(c);
+    fwd_zpad_fft<T>(c, p, x, s);
+    fill_zero<T>(p.gridA, (int64_t)c->Np * c->Np, s);
+    launch_tiles<T>(c, v, p, OP_FUSED, otf, y_sorted, nullptr, nullptr, tile_part(c), s);
+    adj_fft_crop<T>(c, p, g, s);
+}
+
+template <typename T>
+const cx<T> *resolve_data(ri_ctx *c, const void *y, hipStream_t s) {
+    if (y == RI_NO_DATA) return nullptr;
+    Prec<T> &p = prec<T>(c);
+    if (y != nullptr) {
+        permute_to_internal<T>((const cx<T> *)y, p.ydata, c->view.perm, c->M, s);
+        return p.ydata;
+    }
+    require(c->has_data, "y is NULL but no data was stored with ri_set_data");
+    return p.ydata;
+}
+
+template <typename T>
+void do_fb_step(ri_ctx *c, const T *x_in, const void *y, double gamma, int kind, double param, T *x_out,
+                double *norms, hipStream_t s) {
+    Prec<T> &p = prec<T>(c);
+    const cx<T> *ys = resolve_data<T>(c, y, s);
+    do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, x_in, ys, p.img0, s);
+    if (kind == RI_PROX_HAAR) {
+        const int nwg = ((c->N / 16) * (c->N / 16) + 3) / 4;
+        haar_prox<T>(c, x_in, p.img0, (T)gamma, nullptr, (T)param, x_out, img_part(c), s);
+        if (norms) {
+            reduce_partials(img_part(c), nwg, 2, 2, norms, s);
+            reduce_partials(tile_part(c), tiles_partials(c), 1, 1, norms + 2, s);
+        }
+    } else {
+        throw Error(RI_EUNSUPPORTED, "CNN denoiser not available in this context");
+    }
+}
+
+template <typename T>
+double power_iteration(ri_ctx *c, int max_it, double rtol, const double *x0, int *iters, bool *conv,
+                       hipStream_t s) {
+    ensure_prec<double>(c, c->p64);
+    const View &v = view_fp64(c);
+    Prec<double> &p = c->p64;
+    const int64_t n = (int64_t)c->N * c->N;
+    double *x = p.img0, *y = p.img1;
+    if (x0) RI_CHECK_HIP(hipMemcpyAsync(x, x0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    else {
+        std::vector<double> h(n);
+        uint64_t z = 0x9E3779B97F4A7C15ull;
+        for (int64_t i = 0; i < n; ++i) {   // splitmix64 stream -> uniform [-1/2, 1/2)
+            z += 0x9E3779B97F4A7C15ull;
+            uint64_t r = z;
+            r = (r ^ (r >> 30)) * 0xBF58476D1CE4E5B9ull;
+            r = (r ^ (r >> 27)) * 0x94D049BB133111EBull;
+            r ^= r >> 31;
+            h[i] = (double)(r >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        }
+        RI_CHECK_HIP(hipMemcpyAsync(x, h.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+        RI_CHECK_HIP(hipStreamSynchronize(s));
+    }
+    double *ss = c->d_scalars;
+    dot_partials<double>(x, x, n, img_part(c), s);
+    reduce_partials(img_part(c), 1024, 1, 1, ss, s);
+    scale_by_inv_sqrt(x, ss, n, s);
+    double L = 0.0;
+    *conv = false;
+    int it = 0;
+    for (it = 1; it <= max_it; ++it) {
+        do_gradient<double>(c, v, true, x, nullptr, y, s);
+        dot_partials<double>(y, y, n, img_part(c), s);
+        reduce_partials(img_part(c), 1024, 1, 1, ss, s);
+        scale_by_inv_sqrt(y, ss, n, s);
+        RI_CHECK_HIP(hipMemcpyAsync(c->h_pinned, ss, sizeof(double), hipMemcpyDeviceToHost, s));
+        RI_CHECK_HIP(hipStreamSynchronize(s));
+        const double Ln = std::sqrt(c->h_pinned[0]);
+        std::swap(x, y);
+        if (it > 1 && std::fabs(Ln - L) <= rtol * Ln) { L = Ln; *conv = true; break; }
+        L = Ln;
+    }
+    if (it > max_it) it = max_it;
+    *iters = it;
+    // keep the latest unit vector in img0
+    if (x != p.img0) RI_CHECK_HIP(hipMemcpyAsync(p.img0, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+ri_status ri_create(const ri_plan_desc *desc, const double *uvw, ri_ctx **out) {
+    if (!out) { g_last_error = "out is NULL"; return RI_EINVAL; }
+    *out = nullptr;
+    ri_ctx *c = nullptr;
+    ri_status st_ = guard(nullptr, [&] {
+        require(desc != nullptr, "desc is NULL");
+        const ri_plan_desc &d = *desc;
+        require(d.N >= 16 && d.N <= 4096 && d.N % 2 == 0, "N must be even, 16..4096");
+        const int Np = 2 * d.N;
+        require((Np & (Np - 1)) == 0, "N' = 2N must be a power of two");
+        require(d.oversample == 2, "oversample must be 2");
+        require(d.kb_support == 7, "kb_support must be 7");
+        require(d.hmax >= 0 && d.hmax <= 5, "hmax must be 0..5");
+        require(d.n_wplanes >= 1 && d.n_wplanes % 2 == 1 && d.n_wplanes <= 65535, "n_wplanes must be odd, <= 65535");
+        require(std::isfinite(d.w_max) && d.w_max >= 0.0, "w_max must be finite and >= 0");
+        require(d.w_max == 0.0 || (std::isfinite(d.cell_rad) && d.cell_rad > 0.0), "cell_rad must be > 0");
+        require(d.g_mode == RI_G_CSR || d.g_mode == RI_G_OTF, "g_mode must be RI_G_CSR or RI_G_OTF");
+        require(d.precision == 32 || d.precision == 64, "precision must be 32 or 64");
+        require(d.tile == 0 || (d.tile >= 8 && d.tile <= 128 && Np % d.tile == 0), "tile must be 0 or divide N'");
+        require(d.M >= 0 && d.M < (int64_t)1 << 31, "M must be in [0, 2^31)");
+        require(d.M == 0 || uvw != nullptr, "uvw is NULL");
+        require(d.n_blocks >= 1, "n_blocks must be >= 1");
+        require(d.facet_core >= 0 && d.facet_core % 16 == 0 && d.facet_halo >= 0, "facet sizes");
+        c = new ri_ctx();
+        c->d = d;
+        c->d.block_offsets = nullptr;
+        c->N = d.N;
+        c->Np = Np;
+        c->logNp = 0;
+        while ((1 << c->logNp) < Np) ++c->logNp;
+        c->J = 7;
+        c->jh = 3;
+        c->hmax = d.hmax;
+        c->H = d.hmax + 3;
+        c->M = d.M;
+        {
+            double a = 7.0 / 2.0 * (2.0 - 0.5);
+            c->beta = M_PI * std::sqrt(a * a - 0.8);
+        }
+        if (d.block_offsets) {
+            c->block_offsets.assign(d.block_offsets, d.block_offsets + d.n_blocks + 1);
+            require(c->block_offsets.front() == 0 && c->block_offsets.back() == d.M, "block offsets must span 0..M");
+            for (int b = 0; b < d.n_blocks; ++b)
+                require(c->block_offsets[b] <= c->block_offsets[b + 1], "block offsets must be ascending");
+        } else {
+            require(d.n_blocks == 1, "n_blocks > 1 needs block_offsets");
+            c->block_offsets = {0, d.M};
+        }
+        auto t0 = std::chrono::steady_clock::now();
+        RI_CHECK_HIP(hipGetDevice(&c->device));
+        hipDeviceProp_t prop;
+        RI_CHECK_HIP(hipGetDeviceProperties(&prop, c->device));
+        c->dev.cu_count = prop.multiProcessorCount;
+        c->dev.lds_per_block = (int)prop.sharedMemPerBlock;
+
+        build_plan(c, uvw);
+        const bool f64frac = d.g_mode == RI_G_CSR || d.precision == 64;
+        const int eb = d.precision == 64 ? 16 : 8;
+        build_view(c, c->view, pick_tile(c, d.tile, eb), f64frac ? 8 : 4);
+        if (d.precision == 32) ensure_prec<float>(c, c->p32);
+        else ensure_prec<double>(c, c->p64);
+        c->n_partials = tiles_partials(c);
+        c->d_partials = (double *)dev_alloc(c, sizeof(double) * (size_t)(tiles_partials(c) + image_partials(c)));
+        c->d_counter = (int32_t *)dev_alloc(c, 64 * sizeof(int32_t));
+        c->d_scalars = (double *)dev_alloc(c, 64 * sizeof(double));
+        RI_CHECK_HIP(hipHostMalloc((void **)&c->h_pinned, 64 * sizeof(double), hipHostMallocDefault));
+        if (d.g_mode == RI_G_CSR) {
+            if (d.precision == 32) fill_csr<float>(c, nullptr);
+            else fill_csr<double>(c, nullptr);
+        }
+        RI_CHECK_HIP(hipDeviceSynchronize());
+        c->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    });
+    if (st_ != RI_OK) {
+        if (c) ri_destroy(c);
+        return st_;
+    }
+    *out = c;
+    return RI_OK;
+}
+
+void ri_destroy(ri_ctx *c) {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    free_view(c->view);
+    free_view(c->view64);
+    dev_free(c->csr.rowptr); dev_free(c->csr.val); dev_free(c->csr.col);
+    auto freep = [](auto &p) {
+        dev_free(p.icorr); dev_free(p.tw); dev_free(p.wtaps); dev_free(p.gridA); dev_free(p.gridB);
+        dev_free(p.img0); dev_free(p.img1); dev_free(p.ydata);
+    };
+    freep(c->p32);
+    freep(c->p64);
+    dev_free(c->d_plane_h);
+    dev_free(c->d_counter);
+    dev_free(c->d_partials);
+    dev_free(c->d_scalars);
+    dev_free(c->cnn_w);
+    if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    delete c;
+}
+
+const char *ri_last_error(const ri_ctx *c) { return c ? c->err.c_str() : g_last_error.c_str(); }
+
+ri_status phi_forward(ri_ctx *c, const void *x, void *y, ri_stream s) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        require(x && (y || c->M == 0), "x or y is NULL");
+        if (c->d.precision == 32) do_forward<float>(c, (const float *)x, (cx<float> *)y, st(s));
+        else do_forward<double>(c, (const double *)x, (cx<double> *)y, st(s));
+        RI_CHECK_HIP(hipGetLastError());
+    });
+}
+
+ri_status phi_adjoint(ri_ctx *c, const void *y, void *x, ri_stream s) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        require(x && (y || c->M == 0), "x or y is NULL");
+        if (c->d.precision == 32) do_adjoint<float>(c, (const cx<float> *)y, (float *)x, st(s));
+        else do_adjoint<double>(c, (const cx<double> *)y, (double *)x, st(s));
+        RI_CHECK_HIP(hipGetLastError());
+    });
+}
+
+ri_status ri_set_data(ri_ctx *c, const void *y, ri_stream s) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        require(y || c->M == 0, "y is NULL");
+        if (c->d.precision == 32) (void)resolve_data<float>(c, y, st(s));
+        else (void)resolve_data<double>(c, y, st(s));
+        c->has_data = true;
+        RI_CHECK_HIP(hipGetLastError());
+    });
+}
+
+ri_status ri_gradient(ri_ctx *c, const void *x, const void *y, void *g, double *r2, ri_stream s) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        require(x && g, "x or g is NULL");
+        if (c->d.precision == 32) {
+            const cx<float> *ys = resolve_data<float>(c, y, st(s));
+            do_gradient<float>(c, c->view, c->d.g_mode == RI_G_OTF, (const float *)x, ys, (float *)g, st(s));
+        } else {
+            const cx<double> *ys = resolve_data<double>(c, y, st(s));
+            do_gradient<double>(c, c->view, c->d.g_mode == RI_G_OTF, (const double *)x, ys, (double *)g, st(s));
+        }
+        if (r2) reduce_partials(tile_part(c), tiles_partials(c), 1, 1, r2, st(s));
+        RI_CHECK_HIP(hipGetLastError());
+    });
+}
+
+ri_status ri_power_norm(ri_ctx *c, int32_t max_it, double rtol, const double *x0, double *L, int32_t *iters,
+                        ri_stream s) {
+    if (!c) return RI_EINVAL;
+    bool conv = false;
+    ri_status r = guard(c, [&] {
+        require(L != nullptr, "L is NULL");
+        require(max_it >= 1 && rtol >= 0.0, "max_it >= 1 and rtol >= 0 required");
+        int it = 0;
+        *L = power_iteration<double>(c, max_it, rtol, x0, &it, &conv, st(s));
+        if (iters) *iters = it;
+        RI_CHECK_HIP(hipGetLastError());
+    });
+    if (r == RI_OK && rtol > 0.0 && !conv) {
+        c->err = "power iteration reached max_it before rtol";
+        return RI_ENOTCONV;
+    }
+    return r;
+}
+
+ri_status denoise(ri_ctx *c, const void *z, void *out, int32_t kind, double param, ri_stream s) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        require(z && out, "z or out is NULL");
+        require(kind == RI_PROX_HAAR || kind == RI_PROX_CNN, "unknown denoiser kind");
+        require(c->N % 16 == 0, "the Haar prox needs N divisible by 16");
+        if (kind == RI_PROX_HAAR) {
+            require(std::isfinite(param) && param >= 0.0, "threshold must be finite and >= 0");
+            if (c->d.precision == 32)
+                haar_prox<float>(c, nullptr, nullptr, 0.f, (const float *)z, (float)param, (float *)out, nullptr, st(s));
+            else
+                haar_prox<double>(c, nullptr, nullptr, 0.0, (const double *)z, param, (double *)out, nullptr, st(s));
+        } else {
+            throw Error(RI_EUNSUPPORTED, "CNN denoiser not loaded");
+        }
+        RI_CHECK_HIP(hipGetLastError());
+    });
+}
+
+ri_status fb_step(ri_ctx *c, const void *x_in, const void *y, double gamma, int32_t kind, double param, void *x_out,
+                  double *norms, ri_stream s) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        require(x_in && x_out && x_in != x_out, "x_in, x_out must be distinct non-NULL buffers");
+        require(std::isfinite(gamma) && gamma > 0.0, "gamma must be finite and > 0");
+        require(kind == RI_PROX_HAAR || kind == RI_PROX_CNN, "unknown denoiser kind");
+        require(c->N % 16 == 0, "the Haar prox needs N divisible by 16");
+        if (c->d.precision == 32)
+            do_fb_step<float>(c, (const float *)x_in, y, gamma, kind, param, (float *)x_out, norms, st(s));
+        else
+            do_fb_step<double>(c, (const double *)x_in, y, gamma, kind, param, (double *)x_out, norms, st(s));
+        RI_CHECK_HIP(hipGetLastError());
+    });
+}
+
+ri_status ri_load_denoiser(ri_ctx *c, const void *weights, int64_t nbytes) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        (void)weights;
+        (void)nbytes;
+        throw Error(RI_EUNSUPPORTED, "CNN denoiser not built in this library version");
+    });
+}
+
+ri_status pnp_solve(ri_ctx *c, const void *y, const ri_solve_opts *o, void *x_out, ri_solve_report *rep) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        require(o && x_out, "opts or x_out is NULL");
+        require(o->max_iter >= 0 && o->check_every >= 1 && o->tau >= 0.0, "bad solve options");
+        require(o->prox_kind == RI_PROX_HAAR, "only the Haar prox is available in this library version");
+        hipStream_t s = nullptr;
+        if (y) {
+            if (c->d.precision == 32) (void)resolve_data<float>(c, y, s);
+            else (void)resolve_data<double>(c, y, s);
+            c->has_data = true;
+        }
+        require(c->has_data, "no data");
+        double L = o->L;
+        if (!(L > 0.0)) {
+            bool conv = false;
+            int it = 0;
+            L = power_iteration<double>(c, 500, 1e-8, nullptr, &it, &conv, s);
+        }
+        const double gamma = 1.98 / L;
+        const double thr = o->tau / std::sqrt(2.0 * L);
+        ri_solve_report r{};
+        r.L = L;
+        r.gamma = gamma;
+        r.alpha = 1.0;
+        r.t_or_sigma = thr;
+        const int64_t n = (int64_t)c->N * c->N;
+        const size_t eb = c->d.precision == 32 ? 4 : 8;
+        void *xa = dev_alloc(c, eb * n), *xb = dev_alloc(c, eb * n);
+        double *nrm = (double *)dev_alloc(c, sizeof(double) * 4 * std::max(1, o->max_iter));
+        try {
+            if (c->d.precision == 32) fill_real<float>((float *)xa, n, 0.f, s);
+            else fill_real<double>((double *)xa, n, 0.0, s);
+            RI_CHECK_HIP(hipStreamSynchronize(s));
+            auto t0 = std::chrono::steady_clock::now();
+            std::vector<double> hn(4);
+            for (int k = 0; k < o->max_iter; ++k) {
+                if (c->d.precision == 32)
+                    do_fb_step<float>(c, (const float *)xa, nullptr, gamma, RI_PROX_HAAR, thr, (float *)xb,
+                                      nrm + 4 * k, s);
+                else
+                    do_fb_step<double>(c, (const double *)xa, nullptr, gamma, RI_PROX_HAAR, thr, (double *)xb,
+                                       nrm + 4 * k, s);
+                std::swap(xa, xb);
+                r.iters = k + 1;
+                if ((k + 1) % o->check_every == 0 || k + 1 == o->max_iter) {
+                    RI_CHECK_HIP(hipMemcpyAsync(hn.data(), nrm + 4 * k, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+                    RI_CHECK_HIP(hipStreamSynchronize(s));
+                    r.final_rel_change = hn[1] > 0 ? std::sqrt(hn[0] / hn[1]) : 0.0;
+                    r.final_residual2 = hn[2];
+                    if (!std::isfinite(hn[0]) || !std::isfinite(hn[2]))
+                        throw Error(RI_EDEVICE, "non-finite iterate");
+                    if (o->rel_tol > 0 && r.final_rel_change <= o->rel_tol) break;
+                }
+            }
+            RI_CHECK_HIP(hipStreamSynchronize(s));
+            r.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            RI_CHECK_HIP(hipMemcpyAsync(x_out, xa, eb * n, hipMemcpyDeviceToDevice, s));
+            RI_CHECK_HIP(hipStreamSynchronize(s));
+        } catch (...) {
+            dev_free(xa); dev_free(xb); dev_free(nrm);
+            c->device_bytes -= (int64_t)(2 * eb * n + sizeof(double) * 4 * std::max(1, o->max_iter));
+            throw;
+        }
+        dev_free(xa); dev_free(xb); dev_free(nrm);
+        c->device_bytes -= (int64_t)(2 * eb * n + sizeof(double) * 4 * std::max(1, o->max_iter));
+        if (rep) *rep = r;
+    });
+}
+
+ri_status ri_get_plan_stats(const ri_ctx *c, ri_plan_stats *o) {
+    if (!c || !o) return RI_EINVAL;
+    o->M = c->M;
+    int64_t nnz = 0;
+    for (int64_t m = 0; m < c->M; ++m) {
+        const int S = 2 * c->plane_h[c->plane[m]] + c->J;
+        nnz += (int64_t)S * S;
+    }
+    o->nnz = nnz;
+    o->N = c->N;
+    o->Np = c->Np;
+    o->tile = c->view.tile;
+    o->n_tiles = (c->Np / c->view.tile) * (c->Np / c->view.tile);
+    o->n_items = c->view.n_items;
+    o->n_blocks = (int32_t)c->block_offsets.size() - 1;
+    o->max_item_vis = c->view.max_item_vis;
+    o->device_bytes = c->device_bytes;
+    o->plan_ms = c->plan_ms;
+    return RI_OK;
+}
+
+ri_status ri_get_plan_arrays(const ri_ctx *c, int32_t *cell_u, int32_t *cell_v, int32_t *plane, int32_t *plane_h) {
+    if (!c) return RI_EINVAL;
+    if (cell_u) std::memcpy(cell_u, c->cu.data(), sizeof(int32_t) * c->M);
+    if (cell_v) std::memcpy(cell_v, c->cv.data(), sizeof(int32_t) * c->M);
+    if (plane) std::memcpy(plane, c->plane.data(), sizeof(int32_t) * c->M);
+    if (plane_h) std::memcpy(plane_h, c->plane_h.data(), sizeof(int32_t) * c->plane_h.size());
+    return RI_OK;
+}
+
+}  // extern "C"

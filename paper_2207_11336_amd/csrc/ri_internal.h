@@ -1,0 +1,179 @@
+// Internal declarations of libri.so (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/ri.h"
+
+namespace ri {
+
+// --------------------------------------------------------------------------
+// Complex helpers (interleaved re/im, 8- or 16-byte aligned)
+// --------------------------------------------------------------------------
+template <typename T> struct cx;
+template <> struct alignas(8) cx<float> { float x, y; };
+template <> struct alignas(16) cx<double> { double x, y; };
+
+template <typename T> __host__ __device__ inline cx<T> mk(T a, T b) { cx<T> r; r.x = a; r.y = b; return r; }
+template <typename T> __host__ __device__ inline cx<T> operator+(cx<T> a, cx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T> __host__ __device__ inline cx<T> operator-(cx<T> a, cx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T> __host__ __device__ inline cx<T> operator*(cx<T> a, cx<T> b) {
+    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T> __host__ __device__ inline cx<T> scale(cx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+template <typename T> __host__ __device__ inline cx<T> conjg(cx<T> a) { return mk<T>(a.x, -a.y); }
+// a * conj(b)
+template <typename T> __host__ __device__ inline cx<T> mulc(cx<T> a, cx<T> b) {
+    return mk<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+// --------------------------------------------------------------------------
+// Work item of the tile launches: one uv tile of one data block, or a chunk
+// of it when the tile holds many visibilities.
+// --------------------------------------------------------------------------
+struct alignas(16) TileItem {
+    int32_t ty0, tx0;   // tile origin (grid cells)
+    int32_t vb, vc;     // first visibility (internal order) and count
+};
+
+// Sorted per-visibility data of one tile size and fraction precision.
+struct View {
+    int tile = 0;                 // T
+    int n_items = 0;
+    int64_t max_item_vis = 0;
+    int32_t *perm = nullptr;      // internal -> caller index
+    uint32_t *cell = nullptr;     // (c_v << 16) | c_u, both mod N'
+    void *frac = nullptr;         // float[2] or double[2] per visibility (f_u, f_v)
+    int frac_bytes = 0;           // 4 or 8
+    uint16_t *plane = nullptr;    // w-plane per visibility
+    TileItem *items = nullptr;
+    std::vector<int64_t> perm_host;  // kept for tests (caller index of each internal slot)
+};
+
+struct CSR {
+    int64_t nnz = 0;
+    int64_t *rowptr = nullptr;    // [M+1], internal order
+    void *val = nullptr;          // cx<T>[nnz]
+    int32_t *col = nullptr;       // [nnz] flat grid index gy*N'+gx
+    int val_bytes = 0;
+};
+
+// Tables and work buffers of one precision.
+template <typename T> struct Prec {
+    bool ready = false;
+    T *icorr = nullptr;           // [N]  1 / kappa_hat((i - N/2) / N')
+    cx<T> *tw = nullptr;          // [N'] exp(-2 pi i k / N')
+    cx<T> *wtaps = nullptr;       // [n_wplanes][2*hmax+1]
+    cx<T> *gridA = nullptr, *gridB = nullptr;   // N' x N'
+    T *img0 = nullptr, *img1 = nullptr;         // N x N scratch images
+    cx<T> *ydata = nullptr;       // stored data, internal order
+};
+
+struct DeviceInfo {
+    int cu_count = 256;
+    int lds_per_block = 65536;
+};
+
+}  // namespace ri
+
+struct ri_ctx {
+    ri_plan_desc d{};
+    std::vector<int64_t> block_offsets;
+    int N = 0, Np = 0, logNp = 0, J = 7, jh = 3, hmax = 0, H = 3;
+    double beta = 0.0;
+    int64_t M = 0;
+    int device = 0;
+    ri::DeviceInfo dev;
+    std::string err;
+
+    // host-side plan copies (caller order)
+    std::vector<double> pu, pv;           // FP64 grid positions
+    std::vector<int32_t> cu, cv;          // window centres mod N'
+    std::vector<int32_t> plane;           // w-plane per visibility
+    std::vector<int32_t> plane_h;         // [n_wplanes]
+    std::vector<double> wtaps64;          // [n_wplanes][2*hmax+1][2]
+
+    int32_t *d_plane_h = nullptr;
+
+    ri::View view;                        // operator view (context precision, desc tile)
+    ri::View view64;                      // FP64 OTF view for the power iteration (if needed)
+    bool view64_is_main = false;
+    ri::CSR csr;
+
+    ri::Prec<float> p32;
+    ri::Prec<double> p64;
+
+    int32_t *d_counter = nullptr;         // persistent-launch work counters
+    double *d_partials = nullptr;         // FP64 reduction partials
+    int n_partials = 0;
+    double *d_scalars = nullptr;          // small FP64 scratch
+    double *h_pinned = nullptr;           // pinned host scalars
+
+    // CNN denoiser
+    void *cnn_w = nullptr;
+    int64_t cnn_bytes = 0;
+
+    bool has_data = false;
+    int64_t device_bytes = 0;
+    double plan_ms = 0.0;
+};
+
+namespace ri {
+
+#define RI_CHECK_HIP(expr)                                                          \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess) {                                                     \
+            throw ::ri::Error(RI_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+        }                                                                           \
+    } while (0)
+
+struct Error {
+    ri_status code;
+    std::string msg;
+    Error(ri_status c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+void *dev_alloc(ri_ctx *c, size_t bytes);
+void dev_free(void *p);
+
+// plan.cpp
+void build_plan(ri_ctx *c, const double *uvw);
+void build_view(ri_ctx *c, View &v, int tile, int frac_bytes);
+void free_view(View &v);
+template <typename T> void ensure_prec(ri_ctx *c, Prec<T> &p);
+
+// fft.hip
+template <typename T> void fwd_zpad_fft(ri_ctx *c, Prec<T> &p, const T *x, hipStream_t s);
+template <typename T> void adj_fft_crop(ri_ctx *c, Prec<T> &p, T *x, hipStream_t s);
+
+// gridding.hip
+enum { OP_DEGRID = 1, OP_GRID = 2, OP_FUSED = 3 };
+template <typename T> void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, int op, bool otf,
+                                        const cx<T> *y_sorted, const cx<T> *y_user,
+                                        cx<T> *y_out_user, double *r2_partials, hipStream_t s);
+template <typename T> void fill_csr(ri_ctx *c, hipStream_t s);
+int tiles_partials(ri_ctx *c);
+
+// image.hip
+template <typename T> void fill_zero(cx<T> *p, int64_t n, hipStream_t s);
+template <typename T> void fill_real(T *p, int64_t n, T v, hipStream_t s);
+void fill_zero_i32(int32_t *p, int64_t n, hipStream_t s);
+void fill_zero_f64(double *p, int64_t n, hipStream_t s);
+template <typename T> void permute_to_internal(const cx<T> *y_user, cx<T> *y_int, const int32_t *perm,
+                                               int64_t M, hipStream_t s);
+template <typename T> void haar_prox(ri_ctx *c, const T *x_in, const T *g, T gamma_or_zero, const T *z_direct,
+                                     T thr, T *out, double *norm_partials, hipStream_t s);
+int image_partials(ri_ctx *c);
+void reduce_partials(const double *partials, int n, int stride, int count, double *out, hipStream_t s);
+template <typename T> void dot_partials(const T *a, const T *b, int64_t n, double *partials, hipStream_t s);
+template <typename T> void axpby(T *out, const T *a, T alpha, const T *b, T beta, int64_t n, hipStream_t s);
+void scale_by_inv_sqrt(double *x, const double *sumsq, int64_t n, hipStream_t s);
+template <typename Tin, typename Tout> void convert(const Tin *in, Tout *out, int64_t n, hipStream_t s);
+
+}  // namespace ri

@@ -1,0 +1,283 @@
+"""Thin ctypes binding of libri.so (the C ABI declared in include/ri.h).
+
+Argument marshalling only: every entry point takes torch tensors that live on
+the GPU, checks their dtype, shape and contiguity against the context (the C
+side cannot see sizes), and passes raw device pointers plus the current HIP
+stream. All arithmetic runs in the library's HIP kernels. Nothing here falls
+back to a CPU path: if libri.so is missing the import of any entry point fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libri.so")
+
+RI_OK, RI_EINVAL, RI_ENOMEM, RI_EDEVICE, RI_EUNSUPPORTED, RI_ENOTCONV, RI_FELLBACK = 0, -1, -2, -3, -4, -5, 1
+RI_G_CSR, RI_G_OTF = 0, 1
+RI_PROX_HAAR, RI_PROX_CNN = 0, 1
+RI_NO_DATA = c_void_p(-1 & 0xFFFFFFFFFFFFFFFF)
+
+EXPORTS = ("ri_create", "ri_destroy", "ri_last_error", "phi_forward", "phi_adjoint", "ri_set_data",
+           "ri_gradient", "ri_power_norm", "denoise", "fb_step", "ri_load_denoiser", "pnp_solve",
+           "ri_get_plan_stats", "ri_get_plan_arrays")
+
+
+class RIError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libri status {status}: {msg}")
+        self.status = status
+
+
+class ri_plan_desc(ctypes.Structure):
+    _fields_ = [("N", c_int32), ("oversample", c_int32), ("kb_support", c_int32), ("hmax", c_int32),
+                ("cell_rad", c_double), ("w_max", c_double), ("n_wplanes", c_int32), ("g_mode", c_int32),
+                ("precision", c_int32), ("tile", c_int32), ("M", c_int64), ("n_blocks", c_int32),
+                ("block_offsets", c_void_p), ("facet_core", c_int32), ("facet_halo", c_int32)]
+
+
+class ri_solve_opts(ctypes.Structure):
+    _fields_ = [("max_iter", c_int32), ("rel_tol", c_double), ("prox_kind", c_int32), ("tau", c_double),
+                ("sigma_train", c_double), ("L", c_double), ("check_every", c_int32), ("x_true", c_void_p),
+                ("trace", c_void_p)]
+
+
+class ri_solve_report(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("L", c_double), ("gamma", c_double), ("alpha", c_double),
+                ("t_or_sigma", c_double), ("final_rel_change", c_double), ("final_residual2", c_double),
+                ("snr_db", c_double), ("fell_back", c_int32), ("ms", c_double)]
+
+
+class ri_plan_stats(ctypes.Structure):
+    _fields_ = [("M", c_int64), ("nnz", c_int64), ("N", c_int32), ("Np", c_int32), ("tile", c_int32),
+                ("n_tiles", c_int32), ("n_items", c_int32), ("n_blocks", c_int32), ("max_item_vis", c_int64),
+                ("device_bytes", c_int64), ("plan_ms", c_double)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libri.so (built in-tree by ``__graft_entry__.build()``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    st = c_int32
+    L.ri_create.argtypes = [POINTER(ri_plan_desc), c_void_p, POINTER(c_void_p)]; L.ri_create.restype = st
+    L.ri_destroy.argtypes = [c_void_p]; L.ri_destroy.restype = None
+    L.ri_last_error.argtypes = [c_void_p]; L.ri_last_error.restype = ctypes.c_char_p
+    L.phi_forward.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]; L.phi_forward.restype = st
+    L.phi_adjoint.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]; L.phi_adjoint.restype = st
+    L.ri_set_data.argtypes = [c_void_p, c_void_p, c_void_p]; L.ri_set_data.restype = st
+    L.ri_gradient.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]; L.ri_gradient.restype = st
+    L.ri_power_norm.argtypes = [c_void_p, c_int32, c_double, c_void_p, POINTER(c_double), POINTER(c_int32), c_void_p]
+    L.ri_power_norm.restype = st
+    L.denoise.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_double, c_void_p]; L.denoise.restype = st
+    L.fb_step.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_double, c_void_p, c_void_p, c_void_p]
+    L.fb_step.restype = st
+    L.ri_load_denoiser.argtypes = [c_void_p, c_void_p, c_int64]; L.ri_load_denoiser.restype = st
+    L.pnp_solve.argtypes = [c_void_p, c_void_p, POINTER(ri_solve_opts), c_void_p, POINTER(ri_solve_report)]
+    L.pnp_solve.restype = st
+    L.ri_get_plan_stats.argtypes = [c_void_p, POINTER(ri_plan_stats)]; L.ri_get_plan_stats.restype = st
+    L.ri_get_plan_arrays.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.ri_get_plan_arrays.restype = st
+    _lib = L
+    return L
+
+
+# ----------------------------------------------------------------------------
+# Context
+# ----------------------------------------------------------------------------
+class Context:
+    """Owns one ``ri_ctx``. Keeps the plan description for size checks."""
+
+    def __init__(self, handle: int, desc: ri_plan_desc, n_wplanes: int):
+        self.handle = c_void_p(handle)
+        self.N = desc.N
+        self.M = desc.M
+        self.precision = desc.precision
+        self.g_mode = desc.g_mode
+        self.n_wplanes = n_wplanes
+
+    @property
+    def real_dtype(self):
+        import torch
+        return torch.float32 if self.precision == 32 else torch.float64
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            load().ri_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check(ctx: Context | None, status: int):
+    if status not in (RI_OK, RI_FELLBACK):
+        L = load()
+        msg = L.ri_last_error(ctx.handle if ctx is not None else None)
+        raise RIError(status, msg.decode() if msg else "")
+    return status
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return c_void_p(stream)
+    return c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, numel: int, name: str):
+    import torch
+    if t is None:
+        raise ValueError(f"{name} is None")
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return c_void_p(t.data_ptr())
+
+
+def _image(ctx, t, name):
+    return _dev(t, ctx.real_dtype, ctx.N * ctx.N, name)
+
+
+def _vis(ctx, t, name):
+    import torch
+    cd = torch.complex64 if ctx.precision == 32 else torch.complex128
+    return _dev(t, cd, ctx.M, name)
+
+
+def plan_desc(N: int, M: int, *, cell_rad: float = 0.0, w_max: float = 0.0, n_wplanes: int = 1,
+              hmax: int = 5, g_mode: int = RI_G_CSR, precision: int = 32, tile: int = 0, n_blocks: int = 1,
+              facet_core: int = 0, facet_halo: int = 0) -> ri_plan_desc:
+    d = ri_plan_desc()
+    d.N, d.oversample, d.kb_support, d.hmax = N, 2, 7, hmax
+    d.cell_rad, d.w_max, d.n_wplanes = cell_rad, w_max, n_wplanes
+    d.g_mode, d.precision, d.tile = g_mode, precision, tile
+    d.M, d.n_blocks = M, n_blocks
+    d.block_offsets = None
+    d.facet_core, d.facet_halo = facet_core, facet_halo
+    return d
+
+
+# ----------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+# ----------------------------------------------------------------------------
+def ri_create(desc: ri_plan_desc, uvw: np.ndarray, block_offsets: np.ndarray | None = None) -> Context:
+    L = load()
+    uvw = np.ascontiguousarray(uvw, dtype=np.float64)
+    if uvw.ndim != 2 or uvw.shape[1] != 3 or uvw.shape[0] != desc.M:
+        raise ValueError(f"uvw must be float64 [M={desc.M}, 3], got {uvw.shape}")
+    offs = None
+    if block_offsets is not None:
+        offs = np.ascontiguousarray(block_offsets, dtype=np.int64)
+        if offs.shape != (desc.n_blocks + 1,):
+            raise ValueError("block_offsets must have n_blocks + 1 entries")
+        desc.block_offsets = offs.ctypes.data_as(c_void_p)
+    out = c_void_p()
+    _check(None, L.ri_create(ctypes.byref(desc), uvw.ctypes.data_as(c_void_p), ctypes.byref(out)))
+    return Context(out.value, desc, desc.n_wplanes)
+
+
+def ri_destroy(ctx: Context):
+    ctx.close()
+
+
+def phi_forward(ctx: Context, x, y, stream=None):
+    _check(ctx, load().phi_forward(ctx.handle, _image(ctx, x, "x"), _vis(ctx, y, "y"), _stream(stream)))
+
+
+def phi_adjoint(ctx: Context, y, x, stream=None):
+    _check(ctx, load().phi_adjoint(ctx.handle, _vis(ctx, y, "y"), _image(ctx, x, "x"), _stream(stream)))
+
+
+def ri_set_data(ctx: Context, y, stream=None):
+    _check(ctx, load().ri_set_data(ctx.handle, _vis(ctx, y, "y"), _stream(stream)))
+
+
+def _data_arg(ctx, y):
+    if y is None:
+        return None
+    if isinstance(y, str) and y == "none":
+        return RI_NO_DATA
+    return _vis(ctx, y, "y")
+
+
+def ri_gradient(ctx: Context, x, y, g, r2=None, stream=None):
+    """g = Re{Phi^dagger (Phi x - y)}; y: tensor, None (stored data) or "none" (y = 0)."""
+    import torch
+    r2p = _dev(r2, torch.float64, 1, "r2") if r2 is not None else None
+    _check(ctx, load().ri_gradient(ctx.handle, _image(ctx, x, "x"), _data_arg(ctx, y), _image(ctx, g, "g"),
+                                   r2p, _stream(stream)))
+
+
+def ri_power_norm(ctx: Context, max_it: int = 500, rtol: float = 1e-8, x0=None, stream=None, allow_notconv=True):
+    import torch
+    x0p = _dev(x0, torch.float64, ctx.N * ctx.N, "x0") if x0 is not None else None
+    Lv, it = c_double(0.0), c_int32(0)
+    st = load().ri_power_norm(ctx.handle, max_it, rtol, x0p, ctypes.byref(Lv), ctypes.byref(it), _stream(stream))
+    if not (allow_notconv and st == RI_ENOTCONV):
+        _check(ctx, st)
+    return Lv.value, it.value
+
+
+def denoise(ctx: Context, z, out, kind: int = RI_PROX_HAAR, param: float = 0.0, stream=None):
+    _check(ctx, load().denoise(ctx.handle, _image(ctx, z, "z"), _image(ctx, out, "out"), kind, param,
+                               _stream(stream)))
+
+
+def fb_step(ctx: Context, x_in, y, gamma: float, kind: int, param: float, x_out, norms=None, stream=None):
+    import torch
+    np_ = _dev(norms, torch.float64, 3, "norms") if norms is not None else None
+    if x_in is not None and x_out is not None and x_in.data_ptr() == x_out.data_ptr():
+        raise ValueError("x_in and x_out must not alias")
+    _check(ctx, load().fb_step(ctx.handle, _image(ctx, x_in, "x_in"), _data_arg(ctx, y), gamma, kind, param,
+                               _image(ctx, x_out, "x_out"), np_, _stream(stream)))
+
+
+def ri_load_denoiser(ctx: Context, weights):
+    import torch
+    if not (isinstance(weights, torch.Tensor) and weights.is_cuda and weights.is_contiguous()):
+        raise TypeError("weights must be a contiguous GPU tensor")
+    nbytes = weights.numel() * weights.element_size()
+    _check(ctx, load().ri_load_denoiser(ctx.handle, c_void_p(weights.data_ptr()), nbytes))
+
+
+def pnp_solve(ctx: Context, y, opts: ri_solve_opts, x_out) -> ri_solve_report:
+    rep = ri_solve_report()
+    yp = _vis(ctx, y, "y") if y is not None else None
+    _check(ctx, load().pnp_solve(ctx.handle, yp, ctypes.byref(opts), _image(ctx, x_out, "x_out"),
+                                 ctypes.byref(rep)))
+    return rep
+
+
+def ri_get_plan_stats(ctx: Context) -> ri_plan_stats:
+    s = ri_plan_stats()
+    _check(ctx, load().ri_get_plan_stats(ctx.handle, ctypes.byref(s)))
+    return s
+
+
+def ri_get_plan_arrays(ctx: Context):
+    M = ctx.M
+    cu = np.empty(M, np.int32); cv = np.empty(M, np.int32); pl = np.empty(M, np.int32)
+    ph = np.empty(ctx.n_wplanes, np.int32)
+    _check(ctx, load().ri_get_plan_arrays(ctx.handle, cu.ctypes.data_as(c_void_p), cv.ctypes.data_as(c_void_p),
+                                          pl.ctypes.data_as(c_void_p), ph.ctypes.data_as(c_void_p)))
+    return cu, cv, pl, ph

@@ -69,7 +69,8 @@ typedef struct {
     int32_t g_mode;        /* RI_G_CSR: G stored as CSR (complex values + int32 columns);
                               RI_G_OTF: G rows computed on the fly from the KB and w-tables */
     int32_t precision;     /* 32 or 64: element type of Phi, Phi^dagger and the FFT */
-    int32_t tile;          /* uv tile side in grid cells (16..128, divides N'); 0 => 64 (32 in FP64) */
+    int32_t tile;          /* uv tile side in grid cells (8..128, divides N'); 0 => autotuned at
+                              ri_create among 8, 16, 32 by timing fused gradient passes */
     int64_t M;             /* number of visibilities, >= 0 */
     int32_t n_blocks;      /* data blocks (eq. E1), >= 1 */
     const int64_t *block_offsets; /* host, n_blocks+1 ascending offsets into the caller's
@@ -180,6 +181,9 @@ typedef struct {
     int64_t max_item_vis;  /* largest work item */
     int64_t device_bytes;  /* device memory held by the context */
     double plan_ms;        /* host + device time of ri_create */
+    int32_t n_tuned;       /* tile sides the autotuner timed (0 when the tile was given) */
+    int32_t tuned_tile[4];
+    double tuned_ms[4];    /* milliseconds per fused gradient pass at each timed tile */
 } ri_plan_stats;
 ri_status ri_get_plan_stats(const ri_ctx *ctx, ri_plan_stats *out);
 
@@ -188,6 +192,21 @@ ri_status ri_get_plan_stats(const ri_ctx *ctx, ri_plan_stats *out);
  * (int32), in the caller's visibility order; plane_h (int32 [n_wplanes]). */
 ri_status ri_get_plan_arrays(const ri_ctx *ctx, int32_t *cell_u, int32_t *cell_v,
                              int32_t *plane, int32_t *plane_h);
+
+/* Kernel timing for benchmarks: while enabled, every launch group records a
+ * pair of HIP events on the stream it is launched on; ri_profile_read
+ * synchronises on the last event and sums the elapsed times per category.
+ * ri_profile(ctx, 1) clears previous records. Adds two event records per
+ * launch group; leave it off in production loops. */
+typedef struct {
+    int32_t n_tiles, n_fft, n_prox, n_other;     /* timed launch groups per category */
+    double tiles_ms;   /* persistent uv-tile kernel (degrid / grid / fused gradient pass) */
+    double fft_ms;     /* Z + row FFTs + column passes, and their inverses */
+    double prox_ms;    /* denoiser kernels */
+    double other_ms;
+} ri_kernel_times;
+ri_status ri_profile(ri_ctx *ctx, int32_t enable);
+ri_status ri_profile_read(ri_ctx *ctx, ri_kernel_times *out);
 
 #ifdef __cplusplus
 }

@@ -263,6 +263,7 @@ size_t row_lds(ri_ctx *c) { return sizeof(cx<T>) * (size_t)(row_pad<T>(c) ? c->N
 template <typename T>
 void fwd_zpad_fft(ri_ctx *c, Prec<T> &p, const T *x, hipStream_t s) {
     const int Np = c->Np;
+    ProfScope prof(c, PROF_FFT, s);
     if (sizeof(cx<T>) * (size_t)Np > (size_t)c->dev.lds_per_block)
         throw Error(RI_EUNSUPPORTED, "grid row does not fit the workgroup LDS");
     if (row_pad<T>(c))
@@ -278,6 +279,7 @@ void fwd_zpad_fft(ri_ctx *c, Prec<T> &p, const T *x, hipStream_t s) {
 template <typename T>
 void adj_fft_crop(ri_ctx *c, Prec<T> &p, T *x, hipStream_t s) {
     const int Np = c->Np;
+    ProfScope prof(c, PROF_FFT, s);
     colfft<T>(c, p.gridA, p.gridB, p.tw, true, false, true, s);
     if (row_pad<T>(c))
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_irowfft_crop<T, true>), dim3(c->N), dim3(threads_for(Np, 1)),

@@ -111,13 +111,17 @@ template <typename T, int OP, bool OTF>
 __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
     // All LDS is dynamic and starts at byte 0: a static __shared__ variable
     // would shift the dynamic block by its size and misalign the 8-byte
-    // atomics on the FP64 subgrid. Layout: Xs, Ys, KB scratch, axis weights,
+    // atomics on the subgrid. Layout: Xs (input subgrid, T), Yr and Yi (output
+    // subgrid, FP64 real and imaginary planes), KB scratch, axis weights,
     // reduction slots, item slot (every part a multiple of 16 bytes).
+    // The output accumulates in FP64 for both precisions: on gfx950 an LDS
+    // FP64 atomic add costs ~8 cycles per wave against ~190 for FP32.
     extern __shared__ unsigned char smem_raw[];
     const int W = a.W, WW = W * W;
     cx<T> *Xs = reinterpret_cast<cx<T> *>(smem_raw);
-    cx<T> *Ys = Xs + ((OP & OP_DEGRID) ? WW : 0);
-    T *kbs = reinterpret_cast<T *>(Ys + ((OP & OP_GRID) ? WW : 0));
+    double *Yr = reinterpret_cast<double *>(Xs + ((OP & OP_DEGRID) ? WW : 0));
+    double *Yi = Yr + ((OP & OP_GRID) ? WW : 0);
+    T *kbs = reinterpret_cast<T *>(Yi + ((OP & OP_GRID) ? WW : 0));
     cx<T> *gs = reinterpret_cast<cx<T> *>(kbs + GROUPS * SCR_KB);
     double *s_red = reinterpret_cast<double *>(gs + GROUPS * SCR_G);
     int &s_item = *reinterpret_cast<int *>(s_red + 4);
@@ -141,7 +145,7 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
             }
         }
         if (OP & OP_GRID) {
-            for (int e = tid; e < WW; e += blockDim.x) Ys[e] = mk<T>((T)0, (T)0);
+            for (int e = tid; e < WW; e += blockDim.x) { Yr[e] = 0.0; Yi[e] = 0.0; }
         }
         __syncthreads();
 
@@ -205,8 +209,8 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
                 for (int i = 0; i < MAXI; ++i) {
                     if (i < NI && lane + 16 * i < SS) {
                         const cx<T> c = mulc(r, wv[i]);
-                        lds_add(&Ys[li[i]].x, c.x);
-                        lds_add(&Ys[li[i]].y, c.y);
+                        lds_add(&Yr[li[i]], (double)c.x);
+                        lds_add(&Yi[li[i]], (double)c.y);
                     }
                 }
             }
@@ -215,12 +219,12 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
         __syncthreads();
         if (OP & OP_GRID) {
             for (int e = tid; e < WW; e += blockDim.x) {
-                const cx<T> v = Ys[e];
-                if (v.x != (T)0 || v.y != (T)0) {
+                const double vr = Yr[e], vi = Yi[e];
+                if (vr != 0.0 || vi != 0.0) {
                     const int r = e / W, cc = e - r * W;
                     cx<T> *dst = a.Y + ((size_t)((y0 + r) & Npm) << a.logNp) + ((x0 + cc) & Npm);
-                    global_add(&dst->x, v.x);
-                    global_add(&dst->y, v.y);
+                    global_add(&dst->x, (T)vr);
+                    global_add(&dst->y, (T)vi);
                 }
             }
         }
@@ -290,7 +294,7 @@ TileArgs<T> make_args(ri_ctx *c, const View &v, Prec<T> &p) {
 template <typename T, int OP, bool OTF>
 void launch_op(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
     const size_t WW = (size_t)a.W * a.W;
-    size_t lds = sizeof(cx<T>) * WW * (((OP & OP_DEGRID) ? 1 : 0) + ((OP & OP_GRID) ? 1 : 0));
+    size_t lds = sizeof(cx<T>) * WW * ((OP & OP_DEGRID) ? 1 : 0) + 2 * sizeof(double) * WW * ((OP & OP_GRID) ? 1 : 0);
     lds += sizeof(T) * GROUPS * SCR_KB + sizeof(cx<T>) * GROUPS * SCR_G + 4 * sizeof(double) + 16;
     if (lds + 64 > (size_t)c->dev.lds_per_block)
         throw Error(RI_EUNSUPPORTED, "tile " + std::to_string(a.tile) + " needs " + std::to_string(lds) +
@@ -327,6 +331,7 @@ void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, int op, bool otf, const 
         a.gcol = c->csr.col;
     }
     fill_zero_i32(c->d_counter, 1, s);
+    ProfScope prof(c, PROF_TILES, s);
     if (otf) {
         if (op == OP_DEGRID) launch_op<T, OP_DEGRID, true>(c, a, s);
         else if (op == OP_GRID) launch_op<T, OP_GRID, true>(c, a, s);

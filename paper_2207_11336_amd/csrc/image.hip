@@ -205,6 +205,7 @@ void haar_prox(ri_ctx *c, const T *x_in, const T *g, T gamma, const T *z_direct,
                double *norm_partials, hipStream_t s) {
     const int nb = (c->N / 16) * (c->N / 16);
     const int nwg = (nb + 3) / 4;
+    ProfScope prof(c, PROF_PROX, s);
     hipLaunchKernelGGL(k_haar_prox<T>, dim3(nwg), dim3(256), 0, s, x_in, g, gamma, z_direct, thr, out,
                        norm_partials, c->N);
 }

@@ -28,11 +28,43 @@ void *dev_alloc(ri_ctx *c, size_t bytes) {
         throw Error(RI_ENOMEM, "hipMalloc(" + std::to_string(bytes) + " B) failed: " + hipGetErrorString(e));
     }
     c->device_bytes += (int64_t)bytes;
+    c->allocs.emplace_back(p, bytes);
     return p;
 }
 
-void dev_free(void *p) {
-    if (p) (void)hipFree(p);
+void dev_free(ri_ctx *c, void *p) {
+    if (!p) return;
+    for (size_t i = 0; i < c->allocs.size(); ++i)
+        if (c->allocs[i].first == p) {
+            c->device_bytes -= (int64_t)c->allocs[i].second;
+            c->allocs[i] = c->allocs.back();
+            c->allocs.pop_back();
+            break;
+        }
+    (void)hipFree(p);
+}
+
+static hipEvent_t take_event(ri_ctx *c) {
+    if (!c->prof_pool.empty()) {
+        hipEvent_t e = c->prof_pool.back();
+        c->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    RI_CHECK_HIP(hipEventCreate(&e));
+    return e;
+}
+
+ProfScope::ProfScope(ri_ctx *c_, int cat_, hipStream_t s_) : c(c_), cat(cat_), s(s_) {
+    if (!c->prof_on) return;
+    a = take_event(c);
+    RI_CHECK_HIP(hipEventRecord(a, s));
+}
+
+ProfScope::~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (hipEventRecord(b, s) == hipSuccess) c->prof_ev.push_back(ProfEvent{cat, a, b});
 }
 
 template <typename V>
@@ -321,8 +353,8 @@ void build_view(ri_ctx *c, View &v, int tile, int frac_bytes) {
     v.items = upload(c, sorted_items.data(), sorted_items.size());
 }
 
-void free_view(View &v) {
-    dev_free(v.perm); dev_free(v.cell); dev_free(v.frac); dev_free(v.plane); dev_free(v.items);
+void free_view(ri_ctx *c, View &v) {
+    dev_free(c, v.perm); dev_free(c, v.cell); dev_free(c, v.frac); dev_free(c, v.plane); dev_free(c, v.items);
     v = View();
 }
 

@@ -40,11 +40,11 @@ void require(bool ok, const std::string &msg) {
 
 size_t lds_for_tile(int tile, int H, int elem_bytes) {
     const size_t W = (size_t)tile + 2 * H;
-    return 2 * W * W * elem_bytes + 16 * 16 * (elem_bytes / 2) + 16 * 36 * elem_bytes + 4 * 8 + 16;
+    return W * W * elem_bytes + W * W * 16 + 16 * 16 * (elem_bytes / 2) + 16 * 36 * elem_bytes + 4 * 8 + 16;
 }
 
 int pick_tile(ri_ctx *c, int requested, int elem_bytes) {
-    int t = requested > 0 ? requested : 32;
+    int t = requested > 0 ? requested : 16;
     if (t > c->Np) t = c->Np;
     if (requested > 0) {
         require((t & (t - 1)) == 0 || c->Np % t == 0, "tile must divide N'");
@@ -130,6 +130,57 @@ void do_fb_step(ri_ctx *c, const T *x_in, const void *y, double gamma, int kind,
     } else {
         throw Error(RI_EUNSUPPORTED, "CNN denoiser not available in this context");
     }
+}
+
+// Main view at tile T (FP64 fractions when G is stored or the context is
+// FP64), plus the CSR G in that view's order.
+void build_main_view(ri_ctx *c, int tile) {
+    const bool f64frac = c->d.g_mode == RI_G_CSR || c->d.precision == 64;
+    free_view(c, c->view);
+    if (c->csr.val) {
+        dev_free(c, c->csr.rowptr); dev_free(c, c->csr.val); dev_free(c, c->csr.col);
+        c->csr = CSR();
+    }
+    build_view(c, c->view, tile, f64frac ? 8 : 4);
+    if (c->d.g_mode == RI_G_CSR) {
+        if (c->d.precision == 32) fill_csr<float>(c, nullptr);
+        else fill_csr<double>(c, nullptr);
+    }
+}
+
+// Tile autotuner: for each candidate tile side whose subgrids fit the
+// workgroup LDS, build the view (and the CSR G in its order), time three fused
+// gradient passes on a constant image after one warm-up, keep the fastest.
+template <typename T>
+void autotune_tile(ri_ctx *c) {
+    const int eb = sizeof(T) == 4 ? 8 : 16;
+    Prec<T> &p = prec<T>(c);
+    const int64_t n = (int64_t)c->N * c->N;
+    fill_real<T>(p.img1, n, (T)1, nullptr);
+    int best = 0;
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    RI_CHECK_HIP(hipEventCreate(&e0));
+    RI_CHECK_HIP(hipEventCreate(&e1));
+    for (int t : {8, 16, 32}) {
+        if (t > c->Np || c->Np % t) continue;
+        if (lds_for_tile(t, c->H, eb) > (size_t)c->dev.lds_per_block) continue;
+        build_main_view(c, t);
+        do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, p.img1, nullptr, p.img0, nullptr);
+        RI_CHECK_HIP(hipEventRecord(e0, nullptr));
+        for (int r = 0; r < 3; ++r)
+            do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, p.img1, nullptr, p.img0, nullptr);
+        RI_CHECK_HIP(hipEventRecord(e1, nullptr));
+        RI_CHECK_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        RI_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+        c->tune_ms.push_back({t, ms / 3});
+        if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best == 0) throw Error(RI_EUNSUPPORTED, "no tile size fits the workgroup LDS");
+    if (c->view.tile != best) build_main_view(c, best);
 }
 
 template <typename T>
@@ -241,9 +292,7 @@ ri_status ri_create(const ri_plan_desc *desc, const double *uvw, ri_ctx **out) {
         c->dev.lds_per_block = (int)prop.sharedMemPerBlock;
 
         build_plan(c, uvw);
-        const bool f64frac = d.g_mode == RI_G_CSR || d.precision == 64;
         const int eb = d.precision == 64 ? 16 : 8;
-        build_view(c, c->view, pick_tile(c, d.tile, eb), f64frac ? 8 : 4);
         if (d.precision == 32) ensure_prec<float>(c, c->p32);
         else ensure_prec<double>(c, c->p64);
         c->n_partials = tiles_partials(c);
@@ -251,9 +300,11 @@ ri_status ri_create(const ri_plan_desc *desc, const double *uvw, ri_ctx **out) {
         c->d_counter = (int32_t *)dev_alloc(c, 64 * sizeof(int32_t));
         c->d_scalars = (double *)dev_alloc(c, 64 * sizeof(double));
         RI_CHECK_HIP(hipHostMalloc((void **)&c->h_pinned, 64 * sizeof(double), hipHostMallocDefault));
-        if (d.g_mode == RI_G_CSR) {
-            if (d.precision == 32) fill_csr<float>(c, nullptr);
-            else fill_csr<double>(c, nullptr);
+        if (d.tile > 0 || c->M == 0) {
+            build_main_view(c, pick_tile(c, d.tile, eb));
+        } else {
+            if (d.precision == 32) autotune_tile<float>(c);
+            else autotune_tile<double>(c);
         }
         RI_CHECK_HIP(hipDeviceSynchronize());
         c->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -269,21 +320,24 @@ ri_status ri_create(const ri_plan_desc *desc, const double *uvw, ri_ctx **out) {
 void ri_destroy(ri_ctx *c) {
     if (!c) return;
     (void)hipDeviceSynchronize();
-    free_view(c->view);
-    free_view(c->view64);
-    dev_free(c->csr.rowptr); dev_free(c->csr.val); dev_free(c->csr.col);
-    auto freep = [](auto &p) {
-        dev_free(p.icorr); dev_free(p.tw); dev_free(p.wtaps); dev_free(p.gridA); dev_free(p.gridB);
-        dev_free(p.img0); dev_free(p.img1); dev_free(p.ydata);
+    free_view(c, c->view);
+    free_view(c, c->view64);
+    dev_free(c, c->csr.rowptr); dev_free(c, c->csr.val); dev_free(c, c->csr.col);
+    auto freep = [c](auto &p) {
+        dev_free(c, p.icorr); dev_free(c, p.tw); dev_free(c, p.wtaps); dev_free(c, p.gridA); dev_free(c, p.gridB);
+        dev_free(c, p.img0); dev_free(c, p.img1); dev_free(c, p.ydata);
     };
     freep(c->p32);
     freep(c->p64);
-    dev_free(c->d_plane_h);
-    dev_free(c->d_counter);
-    dev_free(c->d_partials);
-    dev_free(c->d_scalars);
-    dev_free(c->cnn_w);
+    dev_free(c, c->d_plane_h);
+    dev_free(c, c->d_counter);
+    dev_free(c, c->d_partials);
+    dev_free(c, c->d_scalars);
+    dev_free(c, c->cnn_w);
+    for (auto &a : c->allocs) (void)hipFree(a.first);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    for (auto &e : c->prof_ev) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    for (auto &e : c->prof_pool) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -459,13 +513,40 @@ ri_status pnp_solve(ri_ctx *c, const void *y, const ri_solve_opts *o, void *x_ou
             RI_CHECK_HIP(hipMemcpyAsync(x_out, xa, eb * n, hipMemcpyDeviceToDevice, s));
             RI_CHECK_HIP(hipStreamSynchronize(s));
         } catch (...) {
-            dev_free(xa); dev_free(xb); dev_free(nrm);
-            c->device_bytes -= (int64_t)(2 * eb * n + sizeof(double) * 4 * std::max(1, o->max_iter));
+            dev_free(c, xa); dev_free(c, xb); dev_free(c, nrm);
             throw;
         }
-        dev_free(xa); dev_free(xb); dev_free(nrm);
-        c->device_bytes -= (int64_t)(2 * eb * n + sizeof(double) * 4 * std::max(1, o->max_iter));
+        dev_free(c, xa); dev_free(c, xb); dev_free(c, nrm);
         if (rep) *rep = r;
+    });
+}
+
+ri_status ri_profile(ri_ctx *c, int32_t enable) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        if (enable) {
+            for (auto &e : c->prof_ev) { c->prof_pool.push_back(e.a); c->prof_pool.push_back(e.b); }
+            c->prof_ev.clear();
+        }
+        c->prof_on = enable != 0;
+    });
+}
+
+ri_status ri_profile_read(ri_ctx *c, ri_kernel_times *o) {
+    if (!c || !o) return RI_EINVAL;
+    return guard(c, [&] {
+        *o = ri_kernel_times{};
+        if (!c->prof_ev.empty()) RI_CHECK_HIP(hipEventSynchronize(c->prof_ev.back().b));
+        for (auto &e : c->prof_ev) {
+            float ms = 0.f;
+            RI_CHECK_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+            switch (e.cat) {
+                case PROF_TILES: o->tiles_ms += ms; o->n_tiles++; break;
+                case PROF_FFT: o->fft_ms += ms; o->n_fft++; break;
+                case PROF_PROX: o->prox_ms += ms; o->n_prox++; break;
+                default: o->other_ms += ms; o->n_other++; break;
+            }
+        }
     });
 }
 
@@ -487,6 +568,13 @@ ri_status ri_get_plan_stats(const ri_ctx *c, ri_plan_stats *o) {
     o->max_item_vis = c->view.max_item_vis;
     o->device_bytes = c->device_bytes;
     o->plan_ms = c->plan_ms;
+    o->n_tuned = 0;
+    for (auto &t : c->tune_ms) {
+        if (o->n_tuned >= 4) break;
+        o->tuned_tile[o->n_tuned] = t.first;
+        o->tuned_ms[o->n_tuned] = t.second;
+        o->n_tuned++;
+    }
     return RI_OK;
 }
 

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/ri.h"
@@ -74,6 +75,12 @@ template <typename T> struct Prec {
     cx<T> *ydata = nullptr;       // stored data, internal order
 };
 
+enum { PROF_TILES = 0, PROF_FFT = 1, PROF_PROX = 2, PROF_OTHER = 3, PROF_N = 4 };
+struct ProfEvent {
+    int cat;
+    hipEvent_t a, b;
+};
+
 struct DeviceInfo {
     int cu_count = 256;
     int lds_per_block = 65536;
@@ -119,8 +126,13 @@ struct ri_ctx {
     int64_t cnn_bytes = 0;
 
     bool has_data = false;
+    bool prof_on = false;
+    std::vector<ri::ProfEvent> prof_ev;
+    std::vector<hipEvent_t> prof_pool;
     int64_t device_bytes = 0;
     double plan_ms = 0.0;
+    std::vector<std::pair<int, float>> tune_ms;   // autotuner: (tile, ms per fused pass)
+    std::vector<std::pair<void *, size_t>> allocs;
 };
 
 namespace ri {
@@ -139,13 +151,24 @@ struct Error {
     Error(ri_status c, std::string m) : code(c), msg(std::move(m)) {}
 };
 
+// Records a start event at construction and a stop event at destruction on
+// stream s when profiling is enabled on the context.
+struct ProfScope {
+    ri_ctx *c;
+    int cat;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    ProfScope(ri_ctx *c, int cat, hipStream_t s);
+    ~ProfScope();
+};
+
 void *dev_alloc(ri_ctx *c, size_t bytes);
-void dev_free(void *p);
+void dev_free(ri_ctx *c, void *p);
 
 // plan.cpp
 void build_plan(ri_ctx *c, const double *uvw);
 void build_view(ri_ctx *c, View &v, int tile, int frac_bytes);
-void free_view(View &v);
+void free_view(ri_ctx *c, View &v);
 template <typename T> void ensure_prec(ri_ctx *c, Prec<T> &p);
 
 // fft.hip

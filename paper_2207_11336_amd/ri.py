@@ -23,7 +23,7 @@ RI_NO_DATA = c_void_p(-1 & 0xFFFFFFFFFFFFFFFF)
 
 EXPORTS = ("ri_create", "ri_destroy", "ri_last_error", "phi_forward", "phi_adjoint", "ri_set_data",
            "ri_gradient", "ri_power_norm", "denoise", "fb_step", "ri_load_denoiser", "pnp_solve",
-           "ri_get_plan_stats", "ri_get_plan_arrays")
+           "ri_get_plan_stats", "ri_get_plan_arrays", "ri_profile", "ri_profile_read")
 
 
 class RIError(RuntimeError):
@@ -54,7 +54,13 @@ class ri_solve_report(ctypes.Structure):
 class ri_plan_stats(ctypes.Structure):
     _fields_ = [("M", c_int64), ("nnz", c_int64), ("N", c_int32), ("Np", c_int32), ("tile", c_int32),
                 ("n_tiles", c_int32), ("n_items", c_int32), ("n_blocks", c_int32), ("max_item_vis", c_int64),
-                ("device_bytes", c_int64), ("plan_ms", c_double)]
+                ("device_bytes", c_int64), ("plan_ms", c_double), ("n_tuned", c_int32),
+                ("tuned_tile", c_int32 * 4), ("tuned_ms", c_double * 4)]
+
+
+class ri_kernel_times(ctypes.Structure):
+    _fields_ = [("n_tiles", c_int32), ("n_fft", c_int32), ("n_prox", c_int32), ("n_other", c_int32),
+                ("tiles_ms", c_double), ("fft_ms", c_double), ("prox_ms", c_double), ("other_ms", c_double)]
 
 
 _lib = None
@@ -87,6 +93,8 @@ def load() -> ctypes.CDLL:
     L.ri_get_plan_stats.argtypes = [c_void_p, POINTER(ri_plan_stats)]; L.ri_get_plan_stats.restype = st
     L.ri_get_plan_arrays.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.ri_get_plan_arrays.restype = st
+    L.ri_profile.argtypes = [c_void_p, c_int32]; L.ri_profile.restype = st
+    L.ri_profile_read.argtypes = [c_void_p, POINTER(ri_kernel_times)]; L.ri_profile_read.restype = st
     _lib = L
     return L
 
@@ -281,3 +289,13 @@ def ri_get_plan_arrays(ctx: Context):
     _check(ctx, load().ri_get_plan_arrays(ctx.handle, cu.ctypes.data_as(c_void_p), cv.ctypes.data_as(c_void_p),
                                           pl.ctypes.data_as(c_void_p), ph.ctypes.data_as(c_void_p)))
     return cu, cv, pl, ph
+
+
+def ri_profile(ctx: Context, enable: bool):
+    _check(ctx, load().ri_profile(ctx.handle, 1 if enable else 0))
+
+
+def ri_profile_read(ctx: Context) -> ri_kernel_times:
+    t = ri_kernel_times()
+    _check(ctx, load().ri_profile_read(ctx.handle, ctypes.byref(t)))
+    return t

@@ -86,7 +86,8 @@ def main():
     ap.add_argument("--workload", default="C1-wide-2048")
     ap.add_argument("--mode", default="auto", choices=["auto", "csr", "otf"])
     ap.add_argument("--power-its", type=int, default=20)
-    ap.add_argument("--tile", type=int, default=0, help="uv tile side (0: library default)")
+    ap.add_argument("--tile", type=int, default=0, help="uv tile side (0: autotuned by the library)")
+    ap.add_argument("--item-vis", type=int, default=0, help="visibilities per work item (0: library default)")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
@@ -131,7 +132,7 @@ def main():
         g_mode = R.RI_G_CSR if mode == "csr" else R.RI_G_OTF
         t0 = time.perf_counter()
         ctx = R.ri_create(R.plan_desc(N, M, cell_rad=wl.cell_rad, w_max=wl.W, n_wplanes=wl.n_wplanes,
-                                      precision=32, g_mode=g_mode, tile=args.tile), uvw)
+                                      precision=32, g_mode=g_mode, tile=args.tile, item_vis=args.item_vis), uvw)
         plan_s = time.perf_counter() - t0
         st = R.ri_get_plan_stats(ctx)
         tuned = {int(st.tuned_tile[i]): round(float(st.tuned_ms[i]), 3) for i in range(st.n_tuned)}

@@ -77,6 +77,7 @@ typedef struct {
                                      visibility order (0 ... M); NULL => one block */
     int32_t facet_core;    /* denoiser facet core side (multiple of 16); 0 => whole image */
     int32_t facet_halo;    /* facet halo in pixels (the CNN needs >= its receptive radius) */
+    int32_t item_vis;      /* visibilities per work item of the tile launch (0 => 1024) */
 } ri_plan_desc;
 
 /* Build a context: validates the description, computes every visibility's

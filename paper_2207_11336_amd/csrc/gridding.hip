@@ -22,20 +22,20 @@ namespace {
 
 constexpr int GROUPS = 16;         // visibilities in flight per 256-thread workgroup
 constexpr int MAXI = 19;           // ceil(17^2 / 16): tap slots per lane
-constexpr int SCR_KB = 16;         // per-group KB scratch (two axes x 8)
-constexpr int SCR_G = 36;          // per-group axis weights (two axes x 18)
+constexpr int SCR_KB = 16;         // per-group KB scratch (two axes x 8), T
+constexpr int SCR_W = 12;          // per-group w-taps (2 hmax + 1 <= 11), cx<T>
+constexpr int SCR_G = 36;          // per-group axis weights (two axes x 18), cx<T>
+constexpr int KB_TERMS_MAX = 32;
 
 template <typename T>
 struct TileArgs {
     const TileItem *items;
     int n_items;
     int *counter;
-    int tile, H, W, logNp, jh, hmax;
-    T beta, inv_i0beta;
-    const uint32_t *cell;
+    int tile, H, W, logNp, hmax, kb_terms;
+    T kbc[KB_TERMS_MAX];           // kappa(t) = sum_k kbc[k] z^k, z = 1 - (2t/7)^2
+    const uint2 *rec;              // per visibility: (cell, plane | h << 16)
     const T *frac;
-    const uint16_t *plane;
-    const int32_t *plane_h;
     const cx<T> *wtaps;
     const int32_t *perm;
     const int64_t *rowptr;
@@ -49,23 +49,20 @@ struct TileArgs {
     double *r2part;
 };
 
-// Kaiser-Bessel weight kappa(t) = I0(beta sqrt(1 - (2t/7)^2)) / I0(beta), I0
-// from its power series (24 terms reach FP32 rounding for beta ~ 16.3, 32 FP64).
+// Kaiser-Bessel weight kappa(t) = I0(beta sqrt(z)) / I0(beta) with
+// z = 1 - (2t/7)^2: the I0 power series is a power series in z, evaluated by
+// Horner with coefficients kbc[k] = (beta^2/4)^k / (k!)^2 / I0(beta) computed
+// in FP64 (22 terms reach FP32 rounding, 32 FP64; no square root needed).
 template <typename T>
-__device__ __forceinline__ T kb_weight(T t, T beta, T inv_i0beta) {
+__device__ __forceinline__ T kb_weight(T t, const TileArgs<T> &a) {
     const T u = t * (T)(2.0 / 7.0);
     const T z = (T)1 - u * u;
     if (z < (T)0) return (T)0;
-    const T x = beta * sqrt(z);
-    const T q = x * x * (T)0.25;
-    constexpr int K = sizeof(T) == 4 ? 24 : 32;
-    T term = (T)1, sum = (T)1;
+    constexpr int K = sizeof(T) == 4 ? 22 : 32;
+    T p = a.kbc[K - 1];
 #pragma unroll
-    for (int k = 1; k <= K; ++k) {
-        term = term * q * (T)(1.0 / ((double)k * (double)k));
-        sum = sum + term;
-    }
-    return sum * inv_i0beta;
+    for (int k = K - 2; k >= 0; --k) p = p * z + a.kbc[k];
+    return p;
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -74,8 +71,26 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Sum over the 16 lanes of a DPP row (quad swaps, then rotations by 4 and 8).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f(double v) {
+    int2 p = __builtin_bit_cast(int2, v);
+    p.x = __builtin_amdgcn_mov_dpp(p.x, CTRL, 0xF, 0xF, false);
+    p.y = __builtin_amdgcn_mov_dpp(p.y, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, p);
+}
 template <typename T>
-__device__ __forceinline__ T shfl_xor16(T v, int o) { return __shfl_xor(v, o, 16); }
+__device__ __forceinline__ T sum16(T v) {
+    v += dpp_f<0xB1>(v);     // quad_perm(1,0,3,2)
+    v += dpp_f<0x4E>(v);     // quad_perm(2,3,0,1)
+    v += dpp_f<0x124>(v);    // row_ror:4
+    v += dpp_f<0x128>(v);    // row_ror:8
+    return v;
+}
 
 template <typename T>
 __device__ __forceinline__ void lds_add(T *p, T v) {
@@ -86,22 +101,24 @@ __device__ __forceinline__ void global_add(T *p, T v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Axis weights of one G row into gg[0..S) (u) and gg[18..18+S) (v); 16 lanes.
+// Axis weights of one G row into gg[0..S) (u) and gg[18..18+S) (v) by the 16
+// lanes of a group: KB taps into kbg, the plane's w-taps into wk, then
+//   g[a] = sum_q k_w[q] kappa(f - (a - h - 3) - q).
 template <typename T>
 __device__ __forceinline__ void axis_weights(const TileArgs<T> &a, int m, int pl, int h, int S, int lane, T *kbg,
-                                             cx<T> *gg) {
+                                             cx<T> *wk, cx<T> *gg) {
     const T fu = a.frac[2 * (size_t)m], fv = a.frac[2 * (size_t)m + 1];
-    if (lane < 7) kbg[lane] = kb_weight<T>(fu - (T)(lane - 3), a.beta, a.inv_i0beta);
-    else if (lane >= 8 && lane < 15) kbg[lane] = kb_weight<T>(fv - (T)(lane - 11), a.beta, a.inv_i0beta);
+    if (lane < 7) kbg[lane] = kb_weight<T>(fu - (T)(lane - 3), a);
+    else if (lane >= 8 && lane < 15) kbg[lane] = kb_weight<T>(fv - (T)(lane - 11), a);
+    if (lane <= 2 * h) wk[lane] = a.wtaps[(size_t)pl * (2 * a.hmax + 1) + a.hmax - h + lane];
     wave_sync();
-    const cx<T> *kt = a.wtaps + (size_t)pl * (2 * a.hmax + 1) + a.hmax;
     for (int idx = lane; idx < 2 * S; idx += 16) {
         const int axis = idx < S ? 0 : 1;
         const int ax = idx - axis * S;
         const int ap = ax - h - 3;
         const int qlo = max(-h, -3 - ap), qhi = min(h, 3 - ap);
         cx<T> acc = mk<T>((T)0, (T)0);
-        for (int q = qlo; q <= qhi; ++q) acc = acc + scale(kt[q], kbg[axis * 8 + ap + q + 3]);
+        for (int q = qlo; q <= qhi; ++q) acc = acc + scale(wk[q + h], kbg[axis * 8 + ap + q + 3]);
         gg[axis * 18 + ax] = acc;
     }
     wave_sync();
@@ -112,21 +129,24 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
     // All LDS is dynamic and starts at byte 0: a static __shared__ variable
     // would shift the dynamic block by its size and misalign the 8-byte
     // atomics on the subgrid. Layout: Xs (input subgrid, T), Yr and Yi (output
-    // subgrid, FP64 real and imaginary planes), KB scratch, axis weights,
-    // reduction slots, item slot (every part a multiple of 16 bytes).
-    // The output accumulates in FP64 for both precisions: on gfx950 an LDS
-    // FP64 atomic add costs ~8 cycles per wave against ~190 for FP32.
+    // subgrid, FP64 real and imaginary planes), then per group the KB taps,
+    // w-taps and axis weights, then reduction slots and the item slot (every
+    // part a multiple of 16 bytes). The output accumulates in FP64 for both
+    // precisions: on gfx950 an LDS FP64 atomic add costs ~8 cycles per wave
+    // against ~190 for FP32.
     extern __shared__ unsigned char smem_raw[];
     const int W = a.W, WW = W * W;
     cx<T> *Xs = reinterpret_cast<cx<T> *>(smem_raw);
     double *Yr = reinterpret_cast<double *>(Xs + ((OP & OP_DEGRID) ? WW : 0));
     double *Yi = Yr + ((OP & OP_GRID) ? WW : 0);
     T *kbs = reinterpret_cast<T *>(Yi + ((OP & OP_GRID) ? WW : 0));
-    cx<T> *gs = reinterpret_cast<cx<T> *>(kbs + GROUPS * SCR_KB);
+    cx<T> *wks = reinterpret_cast<cx<T> *>(kbs + GROUPS * SCR_KB);
+    cx<T> *gs = wks + GROUPS * SCR_W;
     double *s_red = reinterpret_cast<double *>(gs + GROUPS * SCR_G);
     int &s_item = *reinterpret_cast<int *>(s_red + 4);
     const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
     T *kbg = kbs + grp * SCR_KB;
+    cx<T> *wk = wks + grp * SCR_W;
     cx<T> *gg = gs + grp * SCR_G;
     const int Npm = (1 << a.logNp) - 1;
     double r2 = 0.0;
@@ -151,70 +171,96 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
 
         for (int vi = grp; vi < item.vc; vi += GROUPS) {
             const int m = item.vb + vi;
-            const uint32_t cell = a.cell[m];
-            const int cu = (int)(cell & 0xFFFFu), cv = (int)(cell >> 16);
-            const int pl = a.plane[m];
-            const int h = a.plane_h[pl];
+            const uint2 rec = a.rec[m];
+            const int cu = (int)(rec.x & 0xFFFFu), cv = (int)(rec.x >> 16);
+            const int pl = (int)(rec.y & 0xFFFFu), h = (int)(rec.y >> 16);
             const int S = 2 * h + 7, SS = S * S;
             const int base = (cv - item.ty0 + a.H - h - 3) * W + (cu - item.tx0 + a.H - h - 3);
-            if (OTF) axis_weights<T>(a, m, pl, h, S, lane, kbg, gg);
+            if (OTF) axis_weights<T>(a, m, pl, h, S, lane, kbg, wk, gg);
             const float invS = 1.0f / (float)S;
             const int NI = (SS + 15) >> 4;
-            int64_t rp = 0;
-            if (!OTF) rp = a.rowptr[m];
-            cx<T> wv[MAXI];
-            int li[MAXI];
             cx<T> acc = mk<T>((T)0, (T)0);
-#pragma unroll
-            for (int i = 0; i < MAXI; ++i) {
-                wv[i] = mk<T>((T)0, (T)0);
-                li[i] = base;
-                if (i < NI) {
-                    const int t = lane + 16 * i;
-                    if (t < SS) {
-                        if (OTF) {
+            cx<T> r;
+            if (OTF) {
+                // weights from the axis weights in LDS; recomputed in the
+                // scatter below instead of being held in registers
+                if (OP & OP_DEGRID) {
+#pragma unroll 4
+                    for (int i = 0; i < NI; ++i) {
+                        const int t = lane + 16 * i;
+                        if (t < SS) {
                             const int ay = (int)(((float)t + 0.5f) * invS);
                             const int ax = t - ay * S;
-                            wv[i] = gg[18 + ay] * gg[ax];
-                            li[i] = base + ay * W + ax;
-                        } else {
-                            wv[i] = a.gval[rp + t];
-                            const int col = a.gcol[rp + t];
-                            const int gy = col >> a.logNp, gx = col & Npm;
-                            li[i] = ((gy - y0) & Npm) * W + ((gx - x0) & Npm);
+                            acc = acc + (gg[18 + ay] * gg[ax]) * Xs[base + ay * W + ax];
                         }
+                    }
+                    acc.x = sum16(acc.x);
+                    acc.y = sum16(acc.y);
+                }
+                if (OP == OP_DEGRID) {
+                    if (lane == 0) a.yout[a.perm[m]] = acc;
+                } else if (OP == OP_FUSED) {
+                    r = acc;
+                    if (a.ysorted) r = r - a.ysorted[m];
+                    if (lane == 0) r2 += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+                } else {
+                    r = a.yuser[a.perm[m]];
+                }
+                if (OP & OP_GRID) {
+#pragma unroll 4
+                    for (int i = 0; i < NI; ++i) {
+                        const int t = lane + 16 * i;
+                        if (t < SS) {
+                            const int ay = (int)(((float)t + 0.5f) * invS);
+                            const int ax = t - ay * S;
+                            const cx<T> c = mulc(r, gg[18 + ay] * gg[ax]);
+                            lds_add(&Yr[base + ay * W + ax], (double)c.x);
+                            lds_add(&Yi[base + ay * W + ax], (double)c.y);
+                        }
+                    }
+                }
+            } else {
+                const int64_t rp = a.rowptr[m];
+                cx<T> wv[MAXI];
+                int li[MAXI];
+#pragma unroll
+                for (int i = 0; i < MAXI; ++i) {
+                    wv[i] = mk<T>((T)0, (T)0);
+                    li[i] = base;
+                    const int t = lane + 16 * i;
+                    if (i < NI && t < SS) {
+                        wv[i] = a.gval[rp + t];
+                        const int col = a.gcol[rp + t];
+                        const int gy = col >> a.logNp, gx = col & Npm;
+                        li[i] = ((gy - y0) & Npm) * W + ((gx - x0) & Npm);
                         if (OP & OP_DEGRID) acc = acc + wv[i] * Xs[li[i]];
                     }
                 }
-            }
-            cx<T> r;
-            if (OP & OP_DEGRID) {
-#pragma unroll
-                for (int o = 8; o >= 1; o >>= 1) {
-                    acc.x += shfl_xor16(acc.x, o);
-                    acc.y += shfl_xor16(acc.y, o);
+                if (OP & OP_DEGRID) {
+                    acc.x = sum16(acc.x);
+                    acc.y = sum16(acc.y);
                 }
-            }
-            if (OP == OP_DEGRID) {
-                if (lane == 0) a.yout[a.perm[m]] = acc;
-            } else if (OP == OP_FUSED) {
-                r = acc;
-                if (a.ysorted) r = r - a.ysorted[m];
-                if (lane == 0) r2 += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
-            } else {
-                r = a.yuser[a.perm[m]];
-            }
-            if (OP & OP_GRID) {
+                if (OP == OP_DEGRID) {
+                    if (lane == 0) a.yout[a.perm[m]] = acc;
+                } else if (OP == OP_FUSED) {
+                    r = acc;
+                    if (a.ysorted) r = r - a.ysorted[m];
+                    if (lane == 0) r2 += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+                } else {
+                    r = a.yuser[a.perm[m]];
+                }
+                if (OP & OP_GRID) {
 #pragma unroll
-                for (int i = 0; i < MAXI; ++i) {
-                    if (i < NI && lane + 16 * i < SS) {
-                        const cx<T> c = mulc(r, wv[i]);
-                        lds_add(&Yr[li[i]], (double)c.x);
-                        lds_add(&Yi[li[i]], (double)c.y);
+                    for (int i = 0; i < MAXI; ++i) {
+                        if (i < NI && lane + 16 * i < SS) {
+                            const cx<T> c = mulc(r, wv[i]);
+                            lds_add(&Yr[li[i]], (double)c.x);
+                            lds_add(&Yi[li[i]], (double)c.y);
+                        }
                     }
                 }
             }
-            if (OTF) wave_sync();   // gg/kbg are rewritten by the group's next visibility
+            if (OTF) wave_sync();   // kbg/wk/gg are rewritten by the group's next visibility
         }
         __syncthreads();
         if (OP & OP_GRID) {
@@ -242,18 +288,19 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_fill_csr(TileArgs<double> a, int64_t M, const int64_t *rowptr,
                                                   cx<T> *val, int32_t *col) {
     __shared__ double kbs[GROUPS * SCR_KB];
+    __shared__ cx<double> wks[GROUPS * SCR_W];
     __shared__ cx<double> gs[GROUPS * SCR_G];
     const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
     double *kbg = kbs + grp * SCR_KB;
+    cx<double> *wk = wks + grp * SCR_W;
     cx<double> *gg = gs + grp * SCR_G;
     const int Np = 1 << a.logNp, Npm = Np - 1;
     for (int64_t m = (int64_t)blockIdx.x * GROUPS + grp; m < M; m += (int64_t)gridDim.x * GROUPS) {
-        const uint32_t cell = a.cell[m];
-        const int cu = (int)(cell & 0xFFFFu), cv = (int)(cell >> 16);
-        const int pl = a.plane[m];
-        const int h = a.plane_h[pl];
+        const uint2 rec = a.rec[m];
+        const int cu = (int)(rec.x & 0xFFFFu), cv = (int)(rec.x >> 16);
+        const int pl = (int)(rec.y & 0xFFFFu), h = (int)(rec.y >> 16);
         const int S = 2 * h + 7, SS = S * S;
-        axis_weights<double>(a, (int)m, pl, h, S, lane, kbg, gg);
+        axis_weights<double>(a, (int)m, pl, h, S, lane, kbg, wk, gg);
         const int64_t rp = rowptr[m];
         for (int t = lane; t < SS; t += 16) {
             const int ay = t / S, ax = t - ay * S;
@@ -276,16 +323,18 @@ TileArgs<T> make_args(ri_ctx *c, const View &v, Prec<T> &p) {
     a.H = c->H;
     a.W = v.tile + 2 * c->H;
     a.logNp = c->logNp;
-    a.jh = c->jh;
     a.hmax = c->hmax;
-    a.beta = (T)c->beta;
+    // Horner coefficients of the KB kernel as a power series in z (FP64)
     double i0b = 1.0, t = 1.0, q = 0.25 * c->beta * c->beta;
     for (int k = 1; k < 500; ++k) { t = t * q / ((double)k * k); i0b += t; if (t < 1e-17 * i0b) break; }
-    a.inv_i0beta = (T)(1.0 / i0b);
-    a.cell = v.cell;
+    a.kb_terms = sizeof(T) == 4 ? 22 : 32;
+    double ck = 1.0 / i0b;
+    for (int k = 0; k < KB_TERMS_MAX; ++k) {
+        a.kbc[k] = (T)ck;
+        ck = ck * q / ((double)(k + 1) * (double)(k + 1));
+    }
+    a.rec = v.rec;
     a.frac = (const T *)v.frac;
-    a.plane = v.plane;
-    a.plane_h = c->d_plane_h;
     a.wtaps = p.wtaps;
     a.perm = v.perm;
     return a;
@@ -295,7 +344,7 @@ template <typename T, int OP, bool OTF>
 void launch_op(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
     const size_t WW = (size_t)a.W * a.W;
     size_t lds = sizeof(cx<T>) * WW * ((OP & OP_DEGRID) ? 1 : 0) + 2 * sizeof(double) * WW * ((OP & OP_GRID) ? 1 : 0);
-    lds += sizeof(T) * GROUPS * SCR_KB + sizeof(cx<T>) * GROUPS * SCR_G + 4 * sizeof(double) + 16;
+    lds += sizeof(T) * GROUPS * SCR_KB + sizeof(cx<T>) * GROUPS * (SCR_W + SCR_G) + 4 * sizeof(double) + 16;
     if (lds + 64 > (size_t)c->dev.lds_per_block)
         throw Error(RI_EUNSUPPORTED, "tile " + std::to_string(a.tile) + " needs " + std::to_string(lds) +
                                          " B of LDS per workgroup; device allows " +

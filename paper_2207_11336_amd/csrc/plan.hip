@@ -295,7 +295,7 @@ void build_view(ri_ctx *c, View &v, int tile, int frac_bytes) {
     });
 
     // work items
-    const int64_t VMAX = 1024;
+    const int64_t VMAX = c->d.item_vis > 0 ? c->d.item_vis : 1024;
     std::vector<TileItem> items;
     std::vector<int64_t> work;
     for (int64_t k = 0; k < nbuckets; ++k) {
@@ -329,16 +329,15 @@ void build_view(ri_ctx *c, View &v, int tile, int frac_bytes) {
 
     // per-visibility arrays in internal order
     std::vector<int32_t> perm(M);
-    std::vector<uint32_t> cell(M);
-    std::vector<uint16_t> pl(M);
+    std::vector<uint2> rec(M);
     std::vector<float> f32;
     std::vector<double> f64;
     if (frac_bytes == 4) f32.resize(2 * M); else f64.resize(2 * M);
     for (int64_t i = 0; i < M; ++i) {
         int64_t m = order[i];
         perm[i] = (int32_t)m;
-        cell[i] = ((uint32_t)c->cv[m] << 16) | (uint32_t)c->cu[m];
-        pl[i] = (uint16_t)c->plane[m];
+        rec[i].x = ((uint32_t)c->cv[m] << 16) | (uint32_t)c->cu[m];
+        rec[i].y = (uint32_t)c->plane[m] | ((uint32_t)c->plane_h[c->plane[m]] << 16);
         double fu = c->pu[m] - std::floor(c->pu[m] + 0.5);
         double fv = c->pv[m] - std::floor(c->pv[m] + 0.5);
         if (frac_bytes == 4) { f32[2 * i] = (float)fu; f32[2 * i + 1] = (float)fv; }
@@ -346,15 +345,14 @@ void build_view(ri_ctx *c, View &v, int tile, int frac_bytes) {
     }
     v.perm_host.assign(order.begin(), order.end());
     v.perm = upload(c, perm.data(), (size_t)M);
-    v.cell = upload(c, cell.data(), (size_t)M);
-    v.plane = upload(c, pl.data(), (size_t)M);
+    v.rec = upload(c, rec.data(), (size_t)M);
     if (frac_bytes == 4) v.frac = upload(c, f32.data(), (size_t)(2 * M));
     else v.frac = upload(c, f64.data(), (size_t)(2 * M));
     v.items = upload(c, sorted_items.data(), sorted_items.size());
 }
 
 void free_view(ri_ctx *c, View &v) {
-    dev_free(c, v.perm); dev_free(c, v.cell); dev_free(c, v.frac); dev_free(c, v.plane); dev_free(c, v.items);
+    dev_free(c, v.perm); dev_free(c, v.rec); dev_free(c, v.frac); dev_free(c, v.items);
     v = View();
 }
 

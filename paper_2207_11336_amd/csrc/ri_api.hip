@@ -40,7 +40,7 @@ void require(bool ok, const std::string &msg) {
 
 size_t lds_for_tile(int tile, int H, int elem_bytes) {
     const size_t W = (size_t)tile + 2 * H;
-    return W * W * elem_bytes + W * W * 16 + 16 * 16 * (elem_bytes / 2) + 16 * 36 * elem_bytes + 4 * 8 + 16;
+    return W * W * elem_bytes + W * W * 16 + 16 * 16 * (elem_bytes / 2) + 16 * (12 + 36) * elem_bytes + 4 * 8 + 16;
 }
 
 int pick_tile(ri_ctx *c, int requested, int elem_bytes) {
@@ -259,6 +259,7 @@ ri_status ri_create(const ri_plan_desc *desc, const double *uvw, ri_ctx **out) {
         require(d.M == 0 || uvw != nullptr, "uvw is NULL");
         require(d.n_blocks >= 1, "n_blocks must be >= 1");
         require(d.facet_core >= 0 && d.facet_core % 16 == 0 && d.facet_halo >= 0, "facet sizes");
+        require(d.item_vis >= 0 && d.item_vis <= (1 << 20), "item_vis must be in [0, 2^20]");
         c = new ri_ctx();
         c->d = d;
         c->d.block_offsets = nullptr;

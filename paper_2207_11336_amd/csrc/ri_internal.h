@@ -48,10 +48,9 @@ struct View {
     int n_items = 0;
     int64_t max_item_vis = 0;
     int32_t *perm = nullptr;      // internal -> caller index
-    uint32_t *cell = nullptr;     // (c_v << 16) | c_u, both mod N'
+    uint2 *rec = nullptr;         // per visibility: ((c_v << 16) | c_u, plane | h << 16)
     void *frac = nullptr;         // float[2] or double[2] per visibility (f_u, f_v)
     int frac_bytes = 0;           // 4 or 8
-    uint16_t *plane = nullptr;    // w-plane per visibility
     TileItem *items = nullptr;
     std::vector<int64_t> perm_host;  // kept for tests (caller index of each internal slot)
 };

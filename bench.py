@@ -46,6 +46,30 @@ def csr_tile_bytes(nnz: int, M: int, Np: int) -> float:
     return 12.0 * nnz + 22.0 * M + 16.0 * Np * Np
 
 
+def measured_traffic(mode: str, tile: int):
+    """HBM bytes per launch of the fused tile kernel from the committed rocprofv3
+    counter summary, or None when the kernel source changed since it was taken
+    (sha256 prefix recorded in the summary) or no row matches mode and tile."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_k_tiles_C1-wide-2048.txt")
+    src = os.path.join(ROOT, "paper_2207_11336_amd", "csrc", "gridding.hip")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    rows, ok = [], False
+    for line in open(path):
+        if "sha256[:16]" in line:
+            ok = line.strip().endswith(sha)
+        elif line.strip() and not line.startswith("#"):
+            rows.append(line.split())
+    if not ok:
+        return None
+    for r in rows:
+        if r[0] == mode and r[1] == str(tile):
+            return float(r[4]) + float(r[5])
+    return None
+
+
 def otf_tile_flops(nnz: int, M: int) -> float:
     """Algorithmic FP32 flops of one fused on-the-fly tile pass: per visibility
     14 Kaiser-Bessel weights (24-term I0 series, 3 flops a term, plus the
@@ -91,6 +115,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="skip the FB time-to-SNR run")
+    ap.add_argument("--fb-iters", type=int, default=300)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -193,19 +219,51 @@ def main():
         bytes_launch = csr_tile_bytes(best["nnz"], M, wl.Np)
         achieved = bytes_launch / (best["tile_ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_tiles<float, fused, csr>",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("csr", best["tile"]),
+                "kernel": "k_tiles<float, fused, csr>",
                 "bytes_per_launch": bytes_launch, "avg_launch_ms": best["tile_ms"]}
     else:
         flops = otf_tile_flops(best["nnz"], M)
         achieved = flops / (best["tile_ms"] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_VALU_PEAK_TFS, "traffic": None, "kernel": "k_tiles<float, fused, otf>",
+                "frac": achieved / FP32_VALU_PEAK_TFS, "traffic": measured_traffic("otf", best["tile"]),
+                "kernel": "k_tiles<float, fused, otf>",
                 "flops_per_launch": flops, "avg_launch_ms": best["tile_ms"]}
     extra = {f"{m}_fb_step_vis_per_s": r["rate"] for m, r in results.items()}
     extra.update({f"{m}_tile_ms": r["tile_ms"] for m, r in results.items()})
     extra.update({f"{m}_tile": r["tile"] for m, r in results.items()})
     st_nnz, plan_s, snr = best["nnz"], best["plan_s"], best["snr"]
     L, fp64_rate = shared["L"], shared["fp64_rate"]
+
+    # Plain FB time-to-SNR on the 64-block decomposition (uneven angular sectors),
+    # hipGraph-replayed iterations, FP64 SNR trace against the true sky.
+    fb_trace = None
+    if not args.no_solve:
+        wl2 = synth.C2
+        sizes = synth.block_sizes(wl2.n_blocks, M, wl2.block_lo, wl2.block_hi)
+        perm, offs = synth.blocked(uvw, sizes)
+        ctxb = R.ri_create(R.plan_desc(N, M, cell_rad=wl.cell_rad, w_max=wl.W, n_wplanes=wl.n_wplanes,
+                                       precision=32, g_mode=R.RI_G_CSR if best["mode"] == "csr" else R.RI_G_OTF,
+                                       tile=best["tile"], n_blocks=wl2.n_blocks), uvw[perm], block_offsets=offs)
+        yb = torch.empty(M, dtype=torch.complex64, device=dev)
+        R.phi_forward(ctxb, x_true, yb)
+        yb += noise[torch.as_tensor(perm, device=dev)] * (shared["tau"] / math.sqrt(2))
+        K = args.fb_iters
+        trace = np.zeros((K, 4))
+        opts = R.ri_solve_opts(max_iter=K, rel_tol=0.0, prox_kind=R.RI_PROX_HAAR, tau=shared["tau"], sigma_train=0.0,
+                               L=L, check_every=50, x_true=x_true.data_ptr(), trace=trace.ctypes.data, use_graph=1)
+        xs = torch.empty_like(x_true)
+        rep = R.pnp_solve(ctxb, yb, opts, xs)
+        st_b = R.ri_get_plan_stats(ctxb)
+        fb_trace = {"iters": rep.iters, "ms": rep.ms, "ms_per_iter": rep.ms / max(1, rep.iters),
+                    "final_snr_db": rep.snr_db, "blocks": st_b.n_blocks, "items": st_b.n_items,
+                    "snr_at": {str(k): round(float(trace[k - 1, 2]), 3) for k in (10, 50, 100, 200, 300) if k <= K},
+                    "ms_at": {str(k): round(float(trace[k - 1, 3]), 2) for k in (10, 50, 100, 200, 300) if k <= K}}
+        log(f"FB x{K} on {st_b.n_blocks} blocks (graph): {rep.ms:.1f} ms, {rep.ms / max(1, rep.iters):.3f} ms/it, "
+            f"SNR {rep.snr_db:.2f} dB")
+        ctxb.close()
+        del yb
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu:
@@ -219,7 +277,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "N": N, "grid": wl.Np, "M": M, "g_mode": best["mode"], "nnz": st_nnz,
                    "tile": best["tile"], "step": "fb_step: fused gradient + Haar-l1 prox + FP64 norms",
-                   "fp64_gram_vis_per_s": fp64_rate, "plan_s": plan_s, "L": L, "snr_db": snr, **extra},
+                   "fp64_gram_vis_per_s": fp64_rate, "plan_s": plan_s, "L": L, "snr_db": snr, **extra,
+                   "fb_time_to_snr": fb_trace},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -148,7 +148,12 @@ ri_status fb_step(ri_ctx *ctx, const void *x_in, const void *y, double gamma, in
 ri_status ri_load_denoiser(ri_ctx *ctx, const void *weights, int64_t nbytes);
 
 /* Whole solve: parameters from the paper's rules (appendices B, C, F), FB or
- * PnP-FB iterations from x = 0, divergence watch with Haar fallback. */
+ * PnP-FB iterations from x = 0, divergence watch with Haar fallback.
+ * Haar: t = tau / sqrt(2L) (eq. B2). CNN: the problem is rescaled by
+ * alpha = max(dirty peak / beta, tau / (sigma_train sqrt(2L))) with beta the
+ * dirty-beam peak (appendix F), so that the rescaled noise level
+ * tau / (alpha sqrt(2L)) does not exceed the training level (eqs. C2-C3); the
+ * result is multiplied back by alpha. */
 typedef struct {
     int32_t max_iter;      /* iterations */
     double rel_tol;        /* stop when ||x^{k+1}-x^k|| / ||x^{k+1}|| <= rel_tol (0: never) */
@@ -159,6 +164,9 @@ typedef struct {
     int32_t check_every;   /* host reads the FP64 norms every check_every iterations (>= 1) */
     const void *x_true;    /* optional dev [N][N] ground truth for the SNR trace, or NULL */
     double *trace;         /* optional host [max_iter][4]: rel change, ||r||^2, SNR dB, ms */
+    int32_t use_graph;     /* 1: replay a hipGraph of two captured iterations */
+    int32_t diverge_checks;/* fall back to Haar after this many consecutive checks with a
+                              growing residual, or at once on a non-finite norm (0: 3) */
 } ri_solve_opts;
 
 typedef struct {

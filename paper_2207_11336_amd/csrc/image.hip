@@ -133,6 +133,18 @@ __global__ void k_dot(const T *__restrict__ a, const T *__restrict__ b, int64_t 
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+template <typename T>
+__global__ void k_diff2(const T *__restrict__ a, T alpha, const T *__restrict__ b, int64_t n, double *part) {
+    __shared__ double s_red[4];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double d = (double)alpha * (double)a[i] - (double)b[i];
+        acc += d * d;
+    }
+    const double t = block_sum(acc, s_red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 // out[k] = sum_i part[i * stride + k], i < n (fixed order).
 __global__ void k_reduce(const double *part, int n, int stride, int count, double *out) {
     __shared__ double s_red[4];
@@ -218,6 +230,13 @@ template <typename T>
 void dot_partials(const T *a, const T *b, int64_t n, double *partials, hipStream_t s) {
     hipLaunchKernelGGL(k_dot<T>, dim3(RED_WG), dim3(256), 0, s, a, b, n, partials);
 }
+
+template <typename T>
+void diff2_partials(const T *a, T alpha, const T *b, int64_t n, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_diff2<T>, dim3(RED_WG), dim3(256), 0, s, a, alpha, b, n, partials);
+}
+template void diff2_partials<float>(const float *, float, const float *, int64_t, double *, hipStream_t);
+template void diff2_partials<double>(const double *, double, const double *, int64_t, double *, hipStream_t);
 
 template <typename T>
 void axpby(T *out, const T *a, T alpha, const T *b, T beta, int64_t n, hipStream_t s) {

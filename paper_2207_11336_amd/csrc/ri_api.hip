@@ -114,11 +114,13 @@ const cx<T> *resolve_data(ri_ctx *c, const void *y, hipStream_t s) {
     return p.ydata;
 }
 
+// One iteration of eq. (A2) with the data in internal order (or none). norms
+// (dev double[3], or [4] with x_true): ||x_out - x_in||^2, ||x_out||^2,
+// ||Phi x_in - y||^2 and ||alpha x_out - x_true||^2.
 template <typename T>
-void do_fb_step(ri_ctx *c, const T *x_in, const void *y, double gamma, int kind, double param, T *x_out,
-                double *norms, hipStream_t s) {
+void fb_step_sorted(ri_ctx *c, const T *x_in, const cx<T> *ys, double gamma, int kind, double param, T *x_out,
+                    double *norms, const T *x_true, double alpha, hipStream_t s) {
     Prec<T> &p = prec<T>(c);
-    const cx<T> *ys = resolve_data<T>(c, y, s);
     do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, x_in, ys, p.img0, s);
     if (kind == RI_PROX_HAAR) {
         const int nwg = ((c->N / 16) * (c->N / 16) + 3) / 4;
@@ -130,6 +132,17 @@ void do_fb_step(ri_ctx *c, const T *x_in, const void *y, double gamma, int kind,
     } else {
         throw Error(RI_EUNSUPPORTED, "CNN denoiser not available in this context");
     }
+    if (norms && x_true) {
+        diff2_partials<T>(x_out, (T)alpha, x_true, (int64_t)c->N * c->N, img_part(c), s);
+        reduce_partials(img_part(c), 1024, 1, 1, norms + 3, s);
+    }
+}
+
+template <typename T>
+void do_fb_step(ri_ctx *c, const T *x_in, const void *y, double gamma, int kind, double param, T *x_out,
+                double *norms, hipStream_t s) {
+    const cx<T> *ys = resolve_data<T>(c, y, s);
+    fb_step_sorted<T>(c, x_in, ys, gamma, kind, param, x_out, norms, nullptr, 1.0, s);
 }
 
 // Main view at tile T (FP64 fractions when G is stored or the context is
@@ -230,6 +243,178 @@ double power_iteration(ri_ctx *c, int max_it, double rtol, const double *x0, int
     // keep the latest unit vector in img0
     if (x != p.img0) RI_CHECK_HIP(hipMemcpyAsync(p.img0, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     return L;
+}
+
+// Forward-backward solve on its own stream. The iteration is captured once
+// as a graph of two steps (a -> b -> a) when requested and replayed; the FP64
+// norms of every step are copied out of the graph's fixed slots after each
+// replay, and read on the host every check_every iterations.
+template <typename T>
+bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_report *rep) {
+    hipStream_t s = nullptr;
+    RI_CHECK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    Prec<T> &p = prec<T>(c);
+    const int64_t n = (int64_t)c->N * c->N;
+    const int K = o.max_iter;
+    std::vector<void *> owned;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<hipEvent_t> evs;
+    auto cleanup = [&] {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto e : evs) (void)hipEventDestroy(e);
+        for (void *q : owned) dev_free(c, q);
+        (void)hipStreamDestroy(s);
+    };
+    bool fell = false;
+    try {
+        const cx<T> *ys = resolve_data<T>(c, y, s);
+        if (y) c->has_data = true;
+        require(c->has_data || c->M == 0, "no data: pass y or store it with ri_set_data");
+        double L = o.L;
+        if (!(L > 0.0)) {
+            bool conv = false;
+            int it = 0;
+            L = power_iteration<double>(c, 500, 1e-8, nullptr, &it, &conv, s);
+        }
+        ri_solve_report rr{};
+        rr.L = L;
+        rr.gamma = 1.98 / L;
+        rr.alpha = 1.0;
+        int kind = o.prox_kind;
+        double param = o.tau / std::sqrt(2.0 * L);
+        if (kind == RI_PROX_CNN) throw Error(RI_EUNSUPPORTED, "CNN denoiser not loaded");
+        rr.t_or_sigma = param;
+        T *xa = (T *)dev_alloc(c, sizeof(T) * n); owned.push_back(xa);
+        T *xb = (T *)dev_alloc(c, sizeof(T) * n); owned.push_back(xb);
+        T *xsave = (T *)dev_alloc(c, sizeof(T) * n); owned.push_back(xsave);
+        double *slots = (double *)dev_alloc(c, sizeof(double) * 8); owned.push_back(slots);
+        double *nrm = (double *)dev_alloc(c, sizeof(double) * 4 * std::max(1, K)); owned.push_back(nrm);
+        fill_real<T>(xa, n, (T)0, s);
+        fill_real<T>(xsave, n, (T)0, s);
+        fill_zero_f64(slots, 8, s);
+        fill_zero_f64(nrm, 4 * (int64_t)std::max(1, K), s);
+        const T *xt = (const T *)o.x_true;
+        double xt2 = 0.0;
+        if (xt) {
+            dot_partials<T>(xt, xt, n, img_part(c), s);
+            reduce_partials(img_part(c), 1024, 1, 1, c->d_scalars, s);
+            RI_CHECK_HIP(hipMemcpyAsync(c->h_pinned, c->d_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        RI_CHECK_HIP(hipStreamSynchronize(s));
+        if (xt) xt2 = c->h_pinned[0];
+        const bool prof_was = c->prof_on;
+        c->prof_on = false;
+        auto capture = [&](int kd, double prm) {
+            if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
+            if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+            RI_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                fb_step_sorted<T>(c, xa, ys, rr.gamma, kd, prm, xb, slots, xt, rr.alpha, s);
+                fb_step_sorted<T>(c, xb, ys, rr.gamma, kd, prm, xa, slots + 4, xt, rr.alpha, s);
+            } catch (...) {
+                hipGraph_t g2 = nullptr;
+                (void)hipStreamEndCapture(s, &g2);
+                if (g2) (void)hipGraphDestroy(g2);
+                throw;
+            }
+            RI_CHECK_HIP(hipStreamEndCapture(s, &graph));
+            RI_CHECK_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        };
+        if (o.use_graph && K >= 2) capture(kind, param);
+        hipEvent_t e0;
+        RI_CHECK_HIP(hipEventCreate(&e0)); evs.push_back(e0);
+        std::vector<std::pair<int, hipEvent_t>> marks;   // (iterations done, event)
+        RI_CHECK_HIP(hipEventRecord(e0, s));
+        const int div_n = o.diverge_checks > 0 ? o.diverge_checks : 3;
+        int rising = 0, k = 0, next_check = o.check_every;
+        double last_r2 = -1.0;
+        std::vector<double> h(4 * std::max(1, K));
+        while (k < K) {
+            if (gexec && k + 2 <= K) {
+                RI_CHECK_HIP(hipGraphLaunch(gexec, s));
+                RI_CHECK_HIP(hipMemcpyAsync(nrm + 4 * k, slots, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
+                k += 2;
+            } else {
+                fb_step_sorted<T>(c, xa, ys, rr.gamma, kind, param, xb, nrm + 4 * k, xt, rr.alpha, s);
+                RI_CHECK_HIP(hipMemcpyAsync(xa, xb, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+                k += 1;
+            }
+            hipEvent_t ev;
+            RI_CHECK_HIP(hipEventCreate(&ev)); evs.push_back(ev);
+            RI_CHECK_HIP(hipEventRecord(ev, s));
+            marks.push_back({k, ev});
+            if (k >= next_check || k == K) {
+                next_check = k + o.check_every;
+                RI_CHECK_HIP(hipMemcpyAsync(h.data() + 4 * (k - 1), nrm + 4 * (k - 1), sizeof(double) * 4,
+                                            hipMemcpyDeviceToHost, s));
+                RI_CHECK_HIP(hipStreamSynchronize(s));
+                const double *q = h.data() + 4 * (k - 1);
+                const bool finite = std::isfinite(q[0]) && std::isfinite(q[1]) && std::isfinite(q[2]);
+                rising = (last_r2 >= 0.0 && q[2] > last_r2) ? rising + 1 : 0;
+                last_r2 = q[2];
+                if (!finite || (kind != RI_PROX_HAAR && rising >= div_n)) {
+                    if (kind == RI_PROX_HAAR) throw Error(RI_EDEVICE, "non-finite iterate with the Haar prox");
+                    // restore the last healthy iterate and continue with the Haar prox
+                    RI_CHECK_HIP(hipMemcpyAsync(xa, xsave, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+                    kind = RI_PROX_HAAR;
+                    param = o.tau / (rr.alpha * std::sqrt(2.0 * L));
+                    fell = true;
+                    rising = 0;
+                    last_r2 = -1.0;
+                    if (gexec) capture(kind, param);
+                    continue;
+                }
+                RI_CHECK_HIP(hipMemcpyAsync(xsave, xa, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+                rr.final_rel_change = q[1] > 0 ? std::sqrt(q[0] / q[1]) : 0.0;
+                if (o.rel_tol > 0 && rr.final_rel_change <= o.rel_tol) break;
+            }
+        }
+        RI_CHECK_HIP(hipStreamSynchronize(s));
+        c->prof_on = prof_was;
+        float ms_total = 0.f;
+        if (!marks.empty()) RI_CHECK_HIP(hipEventElapsedTime(&ms_total, e0, marks.back().second));
+        rr.iters = k;
+        rr.ms = ms_total;
+        rr.fell_back = fell ? 1 : 0;
+        if (k > 0) {
+            RI_CHECK_HIP(hipMemcpy(h.data(), nrm, sizeof(double) * 4 * k, hipMemcpyDeviceToHost));
+            const double *q = h.data() + 4 * (k - 1);
+            rr.final_rel_change = q[1] > 0 ? std::sqrt(q[0] / q[1]) : 0.0;
+            rr.final_residual2 = q[2];
+            rr.snr_db = xt && q[3] > 0 ? 10.0 * std::log10(xt2 / q[3]) : 0.0;
+            if (o.trace) {
+                int mi = 0;
+                float prev_ms = 0.f;
+                int prev_k = 0;
+                for (auto &mk_ : marks) {
+                    float ms = 0.f;
+                    RI_CHECK_HIP(hipEventElapsedTime(&ms, e0, mk_.second));
+                    for (int j = prev_k; j < mk_.first; ++j) {
+                        const double *qq = h.data() + 4 * j;
+                        double *tr = o.trace + 4 * j;
+                        tr[0] = qq[1] > 0 ? std::sqrt(qq[0] / qq[1]) : 0.0;
+                        tr[1] = qq[2];
+                        tr[2] = xt && qq[3] > 0 ? 10.0 * std::log10(xt2 / qq[3]) : 0.0;
+                        tr[3] = prev_ms + (ms - prev_ms) * (double)(j + 1 - prev_k) / (double)(mk_.first - prev_k);
+                    }
+                    prev_ms = ms;
+                    prev_k = mk_.first;
+                    ++mi;
+                }
+            }
+        }
+        axpby<T>(x_out, xa, (T)rr.alpha, nullptr, (T)0, n, s);
+        RI_CHECK_HIP(hipStreamSynchronize(s));
+        if (rep) *rep = rr;
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        cleanup();
+        throw;
+    }
+    cleanup();
+    return fell;
 }
 
 }  // namespace
@@ -456,70 +641,17 @@ ri_status ri_load_denoiser(ri_ctx *c, const void *weights, int64_t nbytes) {
 
 ri_status pnp_solve(ri_ctx *c, const void *y, const ri_solve_opts *o, void *x_out, ri_solve_report *rep) {
     if (!c) return RI_EINVAL;
-    return guard(c, [&] {
+    bool fell = false;
+    ri_status r = guard(c, [&] {
         require(o && x_out, "opts or x_out is NULL");
         require(o->max_iter >= 0 && o->check_every >= 1 && o->tau >= 0.0, "bad solve options");
-        require(o->prox_kind == RI_PROX_HAAR, "only the Haar prox is available in this library version");
-        hipStream_t s = nullptr;
-        if (y) {
-            if (c->d.precision == 32) (void)resolve_data<float>(c, y, s);
-            else (void)resolve_data<double>(c, y, s);
-            c->has_data = true;
-        }
-        require(c->has_data, "no data");
-        double L = o->L;
-        if (!(L > 0.0)) {
-            bool conv = false;
-            int it = 0;
-            L = power_iteration<double>(c, 500, 1e-8, nullptr, &it, &conv, s);
-        }
-        const double gamma = 1.98 / L;
-        const double thr = o->tau / std::sqrt(2.0 * L);
-        ri_solve_report r{};
-        r.L = L;
-        r.gamma = gamma;
-        r.alpha = 1.0;
-        r.t_or_sigma = thr;
-        const int64_t n = (int64_t)c->N * c->N;
-        const size_t eb = c->d.precision == 32 ? 4 : 8;
-        void *xa = dev_alloc(c, eb * n), *xb = dev_alloc(c, eb * n);
-        double *nrm = (double *)dev_alloc(c, sizeof(double) * 4 * std::max(1, o->max_iter));
-        try {
-            if (c->d.precision == 32) fill_real<float>((float *)xa, n, 0.f, s);
-            else fill_real<double>((double *)xa, n, 0.0, s);
-            RI_CHECK_HIP(hipStreamSynchronize(s));
-            auto t0 = std::chrono::steady_clock::now();
-            std::vector<double> hn(4);
-            for (int k = 0; k < o->max_iter; ++k) {
-                if (c->d.precision == 32)
-                    do_fb_step<float>(c, (const float *)xa, nullptr, gamma, RI_PROX_HAAR, thr, (float *)xb,
-                                      nrm + 4 * k, s);
-                else
-                    do_fb_step<double>(c, (const double *)xa, nullptr, gamma, RI_PROX_HAAR, thr, (double *)xb,
-                                       nrm + 4 * k, s);
-                std::swap(xa, xb);
-                r.iters = k + 1;
-                if ((k + 1) % o->check_every == 0 || k + 1 == o->max_iter) {
-                    RI_CHECK_HIP(hipMemcpyAsync(hn.data(), nrm + 4 * k, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
-                    RI_CHECK_HIP(hipStreamSynchronize(s));
-                    r.final_rel_change = hn[1] > 0 ? std::sqrt(hn[0] / hn[1]) : 0.0;
-                    r.final_residual2 = hn[2];
-                    if (!std::isfinite(hn[0]) || !std::isfinite(hn[2]))
-                        throw Error(RI_EDEVICE, "non-finite iterate");
-                    if (o->rel_tol > 0 && r.final_rel_change <= o->rel_tol) break;
-                }
-            }
-            RI_CHECK_HIP(hipStreamSynchronize(s));
-            r.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-            RI_CHECK_HIP(hipMemcpyAsync(x_out, xa, eb * n, hipMemcpyDeviceToDevice, s));
-            RI_CHECK_HIP(hipStreamSynchronize(s));
-        } catch (...) {
-            dev_free(c, xa); dev_free(c, xb); dev_free(c, nrm);
-            throw;
-        }
-        dev_free(c, xa); dev_free(c, xb); dev_free(c, nrm);
-        if (rep) *rep = r;
+        require(o->prox_kind == RI_PROX_HAAR || o->prox_kind == RI_PROX_CNN, "unknown denoiser kind");
+        require(c->N % 16 == 0, "the Haar prox needs N divisible by 16");
+        if (c->d.precision == 32) fell = solve<float>(c, y, *o, (float *)x_out, rep);
+        else fell = solve<double>(c, y, *o, (double *)x_out, rep);
     });
+    if (r == RI_OK && fell) return RI_FELLBACK;
+    return r;
 }
 
 ri_status ri_profile(ri_ctx *c, int32_t enable) {

@@ -194,6 +194,8 @@ template <typename T> void haar_prox(ri_ctx *c, const T *x_in, const T *g, T gam
 int image_partials(ri_ctx *c);
 void reduce_partials(const double *partials, int n, int stride, int count, double *out, hipStream_t s);
 template <typename T> void dot_partials(const T *a, const T *b, int64_t n, double *partials, hipStream_t s);
+template <typename T> void diff2_partials(const T *a, T alpha, const T *b, int64_t n, double *partials,
+                                          hipStream_t s);
 template <typename T> void axpby(T *out, const T *a, T alpha, const T *b, T beta, int64_t n, hipStream_t s);
 void scale_by_inv_sqrt(double *x, const double *sumsq, int64_t n, hipStream_t s);
 template <typename Tin, typename Tout> void convert(const Tin *in, Tout *out, int64_t n, hipStream_t s);

@@ -73,8 +73,10 @@ def test_fb_200_iterations_fp64_narrow_field():
     assert L == pytest.approx(Lref, rel=1e-7)
     t = OF.threshold(c.tau, Lref)
     n_iter = 200
+    trace = np.zeros((n_iter, 4))
+    xt = torch.tensor(c.x, device=DEV)
     opts = R.ri_solve_opts(max_iter=n_iter, rel_tol=0.0, prox_kind=R.RI_PROX_HAAR, tau=c.tau, sigma_train=0.0,
-                           L=Lref, check_every=50, x_true=None, trace=None)
+                           L=Lref, check_every=50, x_true=xt.data_ptr(), trace=trace.ctypes.data, use_graph=1)
     x = torch.empty((c.N, c.N), dtype=torch.float64, device=DEV)
     rep = R.pnp_solve(ctx, _vis(c.y, 64), opts, x)
     xr, hist = OF.fb(c.op, c.y, Lref, t, n_iter, x_true=c.x)
@@ -84,3 +86,7 @@ def test_fb_200_iterations_fp64_narrow_field():
     assert rep.iters == n_iter
     assert abs(snr_g - snr_o) <= 0.01
     assert rel(xg, xr) <= 1e-8
+    # the per-iteration SNR trace follows the oracle's history
+    snr_hist = np.array([h["snr_db"] for h in hist])
+    assert np.abs(trace[:, 2] - snr_hist).max() <= 0.01
+    assert rep.snr_db == pytest.approx(snr_o, abs=0.01)

@@ -1,0 +1,91 @@
+"""Pins of the CNN oracle (no GPU): convolution against scipy, bfloat16
+rounding against torch's conversion, analytic gradients against central
+finite differences, facet exactness for a halo covering the receptive field."""
+import numpy as np
+import pytest
+from scipy import signal
+
+from oracle import cnn as C
+
+
+def test_conv3x3_matches_scipy_correlate():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((2, 3, 9, 11))
+    w = rng.standard_normal((4, 3, 3, 3))
+    b = rng.standard_normal(4)
+    out = C.conv3x3(x, w, b)
+    for bi in range(2):
+        for o in range(4):
+            ref = b[o] + sum(signal.correlate2d(x[bi, c], w[o, c], mode="same", boundary="fill")
+                             for c in range(3))
+            assert np.abs(out[bi, o] - ref).max() <= 1e-12
+
+
+def test_bf16_round_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(1)
+    a = np.concatenate([rng.standard_normal(5000) * 10.0 ** rng.uniform(-6, 6, 5000),
+                        [1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, -1 - 2 ** -8, 0.0, 3e-39]])
+    ref = torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(C.bf16_round(a), ref)
+    assert C.bf16_round(np.array([1 + 2 ** -8]))[0] == 1.0              # tie to even
+    assert C.bf16_round(np.array([1 + 3 * 2 ** -8]))[0] == 1 + 2 ** -6   # tie to even (up)
+
+
+def test_gradients_match_finite_differences():
+    rng = np.random.default_rng(2)
+    params = C.init_params(layers=3, channels=4, seed=3)
+    params = [(w, rng.standard_normal(b.shape) * 0.1) for w, b in params]
+    z = rng.standard_normal((2, 8, 8))
+    g = rng.standard_normal((2, 8, 8))
+
+    def objective(ps):
+        D, _ = C.forward(ps, z)
+        return float(np.sum(g * (z - D)))          # sum(g * net(z))
+
+    _, acts = C.forward(params, z)
+    grads = C.backward(params, acts, g)
+    eps = 1e-6
+    for l, (w, b) in enumerate(params):
+        for idx in [(0, 0, 0, 0), (w.shape[0] - 1, w.shape[1] - 1, 2, 1), (0, w.shape[1] - 1, 1, 2)]:
+            wp = w.copy(); wp[idx] += eps
+            wm = w.copy(); wm[idx] -= eps
+            pp = list(params); pp[l] = (wp, b)
+            pm = list(params); pm[l] = (wm, b)
+            fd = (objective(pp) - objective(pm)) / (2 * eps)
+            assert grads[l][0][idx] == pytest.approx(fd, rel=1e-6, abs=1e-9), (l, idx)
+        j = b.shape[0] - 1
+        bp = b.copy(); bp[j] += eps
+        bm = b.copy(); bm[j] -= eps
+        pp = list(params); pp[l] = (w, bp)
+        pm = list(params); pm[l] = (w, bm)
+        fd = (objective(pp) - objective(pm)) / (2 * eps)
+        assert grads[l][1][j] == pytest.approx(fd, rel=1e-6, abs=1e-9), (l, "bias")
+
+
+def test_l1_gradient():
+    rng = np.random.default_rng(4)
+    D = rng.standard_normal((2, 5, 5))
+    u = rng.standard_normal((2, 5, 5))
+    g = C.l1_dnet(D, u)
+    eps = 1e-7
+    for idx in [(0, 0, 0), (1, 4, 2)]:
+        Dp = D.copy(); Dp[idx] -= eps       # net up by eps -> D down by eps
+        Dm = D.copy(); Dm[idx] += eps
+        fd = (C.l1_loss(Dp, u) - C.l1_loss(Dm, u)) / (2 * eps)
+        assert g[idx] == pytest.approx(fd, rel=1e-6)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_facets_with_receptive_halo_are_exact(bf16):
+    rng = np.random.default_rng(5)
+    layers = 4                                   # receptive radius 4
+    params = C.init_params(layers=layers, channels=6, seed=6)
+    params = [(w, rng.standard_normal(b.shape) * 0.2) for w, b in params]
+    z = rng.standard_normal((32, 32))
+    whole, _ = C.forward(params, z[None], bf16=bf16)
+    fac = C.denoise_facets(params, z, core=16, halo=layers, bf16=bf16)
+    assert np.abs(fac - whole[0]).max() <= (1e-12 if not bf16 else 0.0) + 1e-12
+    # a halo below the receptive radius is not exact
+    short = C.denoise_facets(params, z, core=16, halo=layers - 2, bf16=bf16)
+    assert np.abs(short - whole[0]).max() > 1e-6

@@ -130,8 +130,12 @@ ri_status ri_power_norm(ri_ctx *ctx, int32_t max_it, double rtol, const double *
  *                 2D Haar basis with four levels, every coefficient
  *                 thresholded at t = param (eq. B2: t = tau / sqrt(2L));
  *   RI_PROX_CNN:  D(z) = z - net(z), the residual CNN loaded by
- *                 ri_load_denoiser (appendix C); param is unused.
- * Applied facet by facet (appendix D) in one launch. z, out: dev [N][N]. */
+ *                 ri_load_denoiser (appendix C), applied facet by facet
+ *                 (appendix D): each facet's tile carries a halo, pixels
+ *                 outside the image are zero, only the core is written; all
+ *                 facets go through each layer in one launch. param is unused;
+ *                 z and out may not alias.
+ * z, out: dev [N][N] (context precision; the CNN computes in FP32/bfloat16). */
 ri_status denoise(ri_ctx *ctx, const void *z, void *out, int32_t kind, double param,
                   ri_stream stream);
 
@@ -143,9 +147,16 @@ ri_status denoise(ri_ctx *ctx, const void *z, void *out, int32_t kind, double pa
 ri_status fb_step(ri_ctx *ctx, const void *x_in, const void *y, double gamma, int32_t kind,
                   double param, void *x_out, double *norms, ri_stream stream);
 
-/* Load the CNN denoiser weights. weights: dev bytes in the packed layout of
- * ri_cnn_layout (BF16 convolution weights, FP32 biases); copied. */
-ri_status ri_load_denoiser(ri_ctx *ctx, const void *weights, int64_t nbytes);
+/* Load the CNN denoiser of RI_PROX_CNN (appendix C): a residual network of
+ * `layers` 3x3 convolutions with 64 hidden channels, parameters in the FP32
+ * layout of ri_cnn.h (n_params = ri_cnn_param_count of such a network; dev,
+ * copied on `stream`, converted to the bfloat16 kernel layout). The context
+ * sizes the network's buffers for all its facets: facet_core x facet_core
+ * facets with facet_halo pixels of halo (tiles rounded up to multiples of
+ * 16), or the whole image when facet_core is 0. Needs N divisible by 16.
+ * RI_EINVAL when n_params does not match `layers`. */
+ri_status ri_load_denoiser(ri_ctx *ctx, const float *params, int64_t n_params, int32_t layers,
+                           ri_stream stream);
 
 /* Whole solve: parameters from the paper's rules (appendices B, C, F), FB or
  * PnP-FB iterations from x = 0, divergence watch with Haar fallback.

@@ -1,0 +1,76 @@
+/*
+ * ri_cnn.h -- C ABI of the residual CNN denoiser in libri.so (HIP, gfx950).
+ *
+ * The learned denoiser of the plug-and-play loop (Dabbech et al.,
+ * appendix C): D(z) = z - net(z), net a stack of L 3x3 "same" convolutions
+ * with biases and ReLU between them (1 -> C -> ... -> C -> 1 channels, no
+ * normalisation), trained with the l1 loss E||D(u + sigma n) - u||_1 of
+ * eq. (C1) (its firm-nonexpansiveness penalty is not implemented here). The
+ * denoiser is applied to image facets independently (appendix D).
+ *
+ * Precision: the input, the first layer and the residual subtraction are
+ * FP32; hidden activations and the weights of layers 2..L are bfloat16
+ * (round to nearest even) with FP32 accumulation in MFMA; the last layer
+ * accumulates in FP32. Gradients are FP32 (hidden pre-activation gradients
+ * stored as bfloat16).
+ *
+ * Parameter vector (FP32, device): for each layer l = 0..L-1 its weights
+ * W_l[c_out][c_in][3][3] then its biases b_l[c_out], layers in order.
+ * Images are FP32 [batch][h][w] row-major; h and w multiples of 16.
+ * Buffers marked "dev" are caller-owned device memory; the network object
+ * owns its parameters, optimizer state and activations.
+ */
+#ifndef RI_CNN_H
+#define RI_CNN_H
+
+#include <stdint.h>
+
+#include "ri.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ri_cnn ri_cnn;
+
+typedef struct {
+    int32_t layers;     /* L >= 3 */
+    int32_t channels;   /* hidden channels; must be 64 */
+    int32_t max_batch;  /* largest batch the activation buffers hold */
+    int32_t max_h, max_w;  /* largest image side; multiples of 16 */
+    int32_t training;   /* 1: keep every layer's activations and the optimizer state */
+} ri_cnn_desc;
+
+/* Create a network with He-normal weights drawn from a counter-based generator
+ * seeded by `seed`, zero biases. Synchronous. */
+ri_status ri_cnn_create(const ri_cnn_desc *desc, uint64_t seed, ri_cnn **out);
+void ri_cnn_destroy(ri_cnn *net);
+const char *ri_cnn_last_error(const ri_cnn *net);
+int64_t ri_cnn_param_count(const ri_cnn *net);
+
+/* Copy the FP32 parameter vector in (dev, param_count floats) or out. */
+ri_status ri_cnn_set_params(ri_cnn *net, const float *params, ri_stream stream);
+ri_status ri_cnn_get_params(const ri_cnn *net, float *params, ri_stream stream);
+
+/* out = D(z) = z - net(z). z, out: dev [batch][h][w]. */
+ri_status ri_cnn_forward(ri_cnn *net, const float *z, float *out, int32_t batch, int32_t h, int32_t w,
+                         ri_stream stream);
+
+/* Gradient of sum(g * net(z)) with respect to the parameters (FP32, the
+ * parameter layout), overwriting grads (dev, param_count floats). Requires
+ * training = 1. g: dev [batch][h][w]. */
+ri_status ri_cnn_grad(ri_cnn *net, const float *z, const float *g, int32_t batch, int32_t h, int32_t w,
+                      float *grads, ri_stream stream);
+
+/* One training step: noisy = clean + sigma n with n ~ N(0,1) from a
+ * counter-based generator keyed by (seed, pixel index), D(noisy), loss
+ * mean|D - clean| (FP64, written to loss if non-NULL, dev double[1]),
+ * gradients, one Adam update (beta1 0.9, beta2 0.999, eps 1e-8) with rate lr. */
+ri_status ri_cnn_train_step(ri_cnn *net, const float *clean, int32_t batch, int32_t h, int32_t w, float sigma,
+                            uint64_t seed, float lr, double *loss, ri_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RI_CNN_H */

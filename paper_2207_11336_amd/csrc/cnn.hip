@@ -1,0 +1,887 @@
+// Residual CNN denoiser D(z) = z - net(z) (paper appendix C), forward and
+// backward, on gfx950; facet-wise application (appendix D).
+//
+// Activations: bfloat16, NHWC with 64 channels (128 B per pixel).
+// 64 -> 64 layers: implicit GEMM on v_mfma_f32_16x16x32_bf16. A persistent
+// workgroup of four waves keeps the layer's packed weights in LDS and walks
+// 16 x 16 pixel blocks; for each block it stages the 18 x 18 input patch in
+// LDS (channel stride padded to 144 B) and every wave computes four pixel rows
+// for all 64 output channels: output channels are the MFMA rows (A = weights,
+// pre-packed in lane order so each lane reads one 16-byte chunk), pixels the
+// MFMA columns (B = the patch), K = 9 taps x 64 input channels in steps of 32.
+// Lane l holds A[l%16][8(l/16)..+7], B[8(l/16)..+7][l%16] and receives
+// D[4(l/16)..+3][l%16], so the epilogue stores four consecutive channels of
+// one pixel. The next block's patch is loaded into registers while the
+// current one is computed. Blocks are dealt to XCDs in contiguous ranges so
+// neighbouring blocks (which share halo rows) meet in the same L2.
+// The same kernel computes the backward data pass with the weights flipped in
+// space and transposed in channels, and a ReLU-mask epilogue.
+// Weight gradients: MFMA with K = pixels; the output gradient and the input
+// activations are staged transposed in LDS (the activations in three copies
+// shifted by one column so every 16-byte read is aligned).
+// First and last layers (1 -> 64, 64 -> 1) are FP32 VALU kernels; the last is
+// fused with the residual subtraction.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "ri_internal.h"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace ri {
+
+namespace {
+
+constexpr int CH = 64;
+constexpr int PADC = 72;                 // LDS channel stride of a pixel (144 B)
+constexpr int WPK = 9 * 2 * 4 * 64;      // 16-byte chunks of one packed 64x64x3x3 layer
+constexpr int PATCH_CHUNKS = 18 * 18 * 8;   // 16-byte chunks of an 18 x 18 x 64 patch
+constexpr int PRE = (PATCH_CHUNKS + 255) / 256;   // chunks per thread
+constexpr int DT_STRIDE = 256 + 8;       // LDS stride of one channel in the transposed gradient block
+constexpr int AT_STRIDE = 18 * 16 + 8;   // LDS stride of one channel in a shifted activation copy
+constexpr int N_XCD = 8;
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ float bfround(float f) { return bf2f(f2bf(f)); }
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ __forceinline__ int4 valid_rect(const CnnGeo &g, int b, int h, int w) {
+    if (g.N == 0) return make_int4(0, h, 0, w);
+    const int f = g.first + b, fy = f / g.nfx, fx = f - fy * g.nfx;
+    const int oy = fy * g.core - g.halo, ox = fx * g.core - g.halo, ext = g.core + 2 * g.halo;
+    return make_int4(max(0, -oy), min(min(h, ext), g.N - oy), max(0, -ox), min(min(w, ext), g.N - ox));
+}
+
+// Blocks of the persistent walk of workgroup `wg`: workgroups are dealt to the
+// 8 XCDs round-robin, so XCD x = wg % 8 takes the contiguous range
+// [x nb / 8, (x+1) nb / 8) and its nwg / 8 workgroups stride through it.
+struct BlockWalk {
+    int begin, end, step;
+    __device__ BlockWalk(int wg, int nwg, int nb) {
+        const int per = nwg / N_XCD;
+        if (per == 0 || nwg % N_XCD) { begin = wg; end = nb; step = nwg; return; }
+        const int x = wg % N_XCD;
+        begin = (int)((int64_t)nb * x / N_XCD) + wg / N_XCD;
+        end = (int)((int64_t)nb * (x + 1) / N_XCD);
+        step = per;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Weight packing (FP32 master -> bfloat16 MFMA lane order)
+//   fwd: chunk ((t*2 + kb)*4 + mi)*64 + lane, element e:
+//        W[o = mi*16 + lane%16][c = kb*32 + 8(lane/16) + e][t]
+//   bwd (flipped, transposed): W[o = kb*32 + 8(lane/16) + e][c = mi*16 + lane%16][8 - t]
+// ---------------------------------------------------------------------------
+__global__ void k_pack(const float *__restrict__ w, uint16_t *__restrict__ fwd, uint16_t *__restrict__ bwd) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= WPK * 8) return;
+    const int e = idx & 7, chunk = idx >> 3;
+    const int lane = chunk & 63, mi = (chunk >> 6) & 3, kb = (chunk >> 8) & 1, t = chunk >> 9;
+    const int r = mi * 16 + (lane & 15), k = kb * 32 + 8 * (lane >> 4) + e;
+    fwd[idx] = f2bf(w[(r * CH + k) * 9 + t]);
+    bwd[idx] = f2bf(w[(k * CH + r) * 9 + (8 - t)]);
+}
+
+__device__ __forceinline__ void block_origin(int blk, int nbx, int nby, int &b, int &y0, int &x0) {
+    b = blk / (nbx * nby);
+    const int rem = blk - b * nbx * nby, by = rem / nbx;
+    y0 = by * 16;
+    x0 = (rem - by * nbx) * 16;
+}
+
+__device__ __forceinline__ void patch_fetch(uint4 (&pre)[PRE], const uint16_t *__restrict__ in, int blk, int nbx,
+                                            int nby, int H, int W, int tid) {
+    int b, y0, x0;
+    block_origin(blk, nbx, nby, b, y0, x0);
+    const size_t img = (size_t)b * H * W;
+#pragma unroll
+    for (int k = 0; k < PRE; ++k) {
+        const int e = tid + k * 256;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (e < PATCH_CHUNKS) {
+            const int pix = e >> 3, ch = e & 7;
+            const int py = pix / 18, px = pix - py * 18;
+            const int y = y0 - 1 + py, x = x0 - 1 + px;
+            if (y >= 0 && y < H && x >= 0 && x < W)
+                v = reinterpret_cast<const uint4 *>(in + (img + (size_t)y * W + x) * CH)[ch];
+        }
+        pre[k] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 64 -> 64 convolution, persistent. MODE 0: out = relu(conv + bias), zero
+// outside the batch item's valid rectangle. MODE 1 (backward data): out =
+// conv * [mask_act > 0] (mask_act: the post-ReLU activation the gradient
+// flows into). 256 threads; blocks of 16 x 16 pixels, nbx x nby per item.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in, uint16_t *__restrict__ out,
+                                                const uint4 *__restrict__ wpk, const float *__restrict__ bias,
+                                                const uint16_t *__restrict__ mask_act, CnnGeo geo, int H, int W,
+                                                int nbx, int nby, int nblocks) {
+    extern __shared__ uint4 smem4[];
+    uint16_t *patch = reinterpret_cast<uint16_t *>(smem4);          // [18*18][PADC]
+    uint4 *wl = smem4 + (18 * 18 * PADC * 2) / 16;                   // [WPK]
+    float *bs = reinterpret_cast<float *>(wl + WPK);                 // [64]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    for (int e = tid; e < WPK; e += 256) wl[e] = wpk[e];
+    if (MODE == 0 && tid < CH) bs[tid] = bias[tid];
+    const BlockWalk walk(blockIdx.x, gridDim.x, nblocks);
+    uint4 pre[PRE];
+    if (walk.begin < walk.end) patch_fetch(pre, in, walk.begin, nbx, nby, H, W, tid);
+    for (int blk = walk.begin; blk < walk.end; blk += walk.step) {
+        __syncthreads();   // the previous block's patch reads are done
+#pragma unroll
+        for (int k = 0; k < PRE; ++k) {
+            const int e = tid + k * 256;
+            if (e < PATCH_CHUNKS) *reinterpret_cast<uint4 *>(patch + (e >> 3) * PADC + (e & 7) * 8) = pre[k];
+        }
+        __syncthreads();
+        if (blk + walk.step < walk.end) patch_fetch(pre, in, blk + walk.step, nbx, nby, H, W, tid);
+        floatx4 acc[4][4];
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3, dx = t - dy * 3;
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                bf16x8 a[4], bv[4];
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi) a[mi] = as_bf16x8(wl[((t * 2 + kb) * 4 + mi) * 64 + lane]);
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni) {
+                    const int py = wave * 4 + ni + dy, px = j + dx;
+                    bv[ni] = as_bf16x8(
+                        *reinterpret_cast<const uint4 *>(patch + (py * 18 + px) * PADC + kb * 32 + 8 * g));
+                }
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni)
+                        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+            }
+        }
+        int b, y0, x0;
+        block_origin(blk, nbx, nby, b, y0, x0);
+        const size_t img = (size_t)b * H * W;
+        const int4 vr = valid_rect(geo, b, H, W);
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) {
+            const int y = y0 + wave * 4 + ni, x = x0 + j;
+            const size_t pix = img + (size_t)y * W + x;
+            const bool inside = y >= vr.x && y < vr.y && x >= vr.z && x < vr.w;
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi) {
+                const int c0 = mi * 16 + 4 * g;
+                uint2 mv = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+                if (MODE == 1) mv = *reinterpret_cast<const uint2 *>(mask_act + pix * CH + c0);
+                const uint32_t m4[4] = {mv.x & 0xFFFFu, mv.x >> 16, mv.y & 0xFFFFu, mv.y >> 16};
+                uint32_t o[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = acc[mi][ni][r];
+                    if (MODE == 0) {
+                        v += bs[c0 + r];
+                        v = (v > 0.f && inside) ? v : 0.f;
+                    } else {
+                        v = m4[r] != 0 ? v : 0.f;     // post-ReLU activations are >= 0
+                    }
+                    o[r] = f2bf(v);
+                }
+                *reinterpret_cast<uint2 *>(out + pix * CH + c0) = make_uint2(o[0] | (o[1] << 16), o[2] | (o[3] << 16));
+            }
+        }
+    }
+}
+
+// First layer: FP32 input, FP32 weights W0[64][9], bias; relu, valid mask, bfloat16 out.
+__global__ void __launch_bounds__(256) k_conv_in(const float *__restrict__ z, uint16_t *__restrict__ out,
+                                                 const float *__restrict__ w0, const float *__restrict__ b0,
+                                                 CnnGeo geo, int H, int W) {
+    __shared__ float zp[18][18];
+    __shared__ float ws[CH * 9];
+    __shared__ float bs[CH];
+    const int b = blockIdx.z, y0 = blockIdx.y * 16, x0 = blockIdx.x * 16, tid = threadIdx.x;
+    const size_t img = (size_t)b * H * W;
+    for (int e = tid; e < 18 * 18; e += 256) {
+        const int py = e / 18, px = e - py * 18, y = y0 - 1 + py, x = x0 - 1 + px;
+        zp[py][px] = (y >= 0 && y < H && x >= 0 && x < W) ? z[img + (size_t)y * W + x] : 0.f;
+    }
+    for (int e = tid; e < CH * 9; e += 256) ws[e] = w0[e];
+    if (tid < CH) bs[tid] = b0[tid];
+    __syncthreads();
+    const int ty = tid >> 4, tx = tid & 15, y = y0 + ty, x = x0 + tx;
+    const int4 vr = valid_rect(geo, b, H, W);
+    const bool inside = y >= vr.x && y < vr.y && x >= vr.z && x < vr.w;
+    float zz[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) zz[t] = zp[ty + t / 3][tx + t % 3];
+    uint16_t *dst = out + (img + (size_t)y * W + x) * CH;
+    for (int c8 = 0; c8 < CH; c8 += 8) {
+        uint32_t o[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            float v = bs[c8 + e];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) v += ws[(c8 + e) * 9 + t] * zz[t];
+            o[e] = f2bf((v > 0.f && inside) ? v : 0.f);
+        }
+        *reinterpret_cast<uint4 *>(dst + c8) =
+            make_uint4(o[0] | (o[1] << 16), o[2] | (o[3] << 16), o[4] | (o[5] << 16), o[6] | (o[7] << 16));
+    }
+}
+
+__device__ __forceinline__ void load_patch_lds(uint16_t *patch, const uint16_t *__restrict__ act, size_t img, int y0,
+                                               int x0, int H, int W, int tid) {
+    for (int e = tid; e < PATCH_CHUNKS; e += 256) {
+        const int pix = e >> 3, ch = e & 7, py = pix / 18, px = pix - py * 18;
+        const int y = y0 - 1 + py, x = x0 - 1 + px;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (y >= 0 && y < H && x >= 0 && x < W)
+            v = reinterpret_cast<const uint4 *>(act + (img + (size_t)y * W + x) * CH)[ch];
+        *reinterpret_cast<uint4 *>(patch + pix * PADC + ch * 8) = v;
+    }
+}
+
+// Last layer + residual: D = z - (b + sum_{t,c} bf16(W[0][c][t]) act[p + t - centre][c]) in FP32.
+__global__ void __launch_bounds__(256) k_conv_out(const uint16_t *__restrict__ act, const float *__restrict__ z,
+                                                  float *__restrict__ D, const float *__restrict__ wl_,
+                                                  const float *__restrict__ bl, int H, int W) {
+    extern __shared__ uint4 smem4[];
+    uint16_t *patch = reinterpret_cast<uint16_t *>(smem4);          // [18*18][PADC]
+    float *ws = reinterpret_cast<float *>(patch + 18 * 18 * PADC);  // [9][64]
+    const int b = blockIdx.z, y0 = blockIdx.y * 16, x0 = blockIdx.x * 16, tid = threadIdx.x;
+    const size_t img = (size_t)b * H * W;
+    load_patch_lds(patch, act, img, y0, x0, H, W, tid);
+    for (int e = tid; e < CH * 9; e += 256) {
+        const int c = e / 9, t = e - c * 9;
+        ws[t * CH + c] = bfround(wl_[e]);
+    }
+    __syncthreads();
+    const int ty = tid >> 4, tx = tid & 15;
+    float acc = bl[0];
+    for (int t = 0; t < 9; ++t) {
+        const uint16_t *pp = patch + ((ty + t / 3) * 18 + tx + t % 3) * PADC;
+        const float *wt = ws + t * CH;
+#pragma unroll
+        for (int c8 = 0; c8 < CH; c8 += 8) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(pp + c8);
+            const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc += wt[c8 + 2 * q] * __uint_as_float(u[q] << 16);
+                acc += wt[c8 + 2 * q + 1] * __uint_as_float(u[q] & 0xFFFF0000u);
+            }
+        }
+    }
+    const size_t o = img + (size_t)(y0 + ty) * W + x0 + tx;
+    D[o] = z[o] - acc;
+}
+
+// l1 loss gradient with respect to net(z): g = -sign(D - u) / numel; partials of mean|D - u|.
+__global__ void k_l1(const float *__restrict__ D, const float *__restrict__ u, float *__restrict__ g, int64_t n,
+                     double *part) {
+    __shared__ double s_red[4];
+    double acc = 0.0;
+    const float inv = 1.f / (float)n;
+    const double invd = 1.0 / (double)n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float d = D[i] - u[i];
+        g[i] = d > 0.f ? -inv : (d < 0.f ? inv : 0.f);
+        acc += fabs((double)d) * invd;
+    }
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+}
+
+// Backward of the last layer. dpre[p][c] = [act[p][c] > 0] sum_t bf16(W[0][c][t]) g[p - (t - centre)];
+// dW[c][t] += sum_p act[p + (t - centre)][c] g[p]; db += sum_p g[p].
+__global__ void __launch_bounds__(256) k_out_backward(const float *__restrict__ g, const uint16_t *__restrict__ act,
+                                                      const float *__restrict__ wl_, uint16_t *__restrict__ dpre,
+                                                      float *__restrict__ dW, float *__restrict__ db, int H, int W) {
+    extern __shared__ uint4 smem4[];
+    uint16_t *patch = reinterpret_cast<uint16_t *>(smem4);          // act patch [18*18][PADC]
+    float *gp = reinterpret_cast<float *>(patch + 18 * 18 * PADC);  // g patch [18][18]
+    float *ws = gp + 18 * 18;                                       // [64][9]
+    float *red = ws + CH * 9;                                       // [4]
+    const int b = blockIdx.z, y0 = blockIdx.y * 16, x0 = blockIdx.x * 16, tid = threadIdx.x;
+    const size_t img = (size_t)b * H * W;
+    load_patch_lds(patch, act, img, y0, x0, H, W, tid);
+    for (int e = tid; e < 18 * 18; e += 256) {
+        const int py = e / 18, px = e - py * 18, y = y0 - 1 + py, x = x0 - 1 + px;
+        gp[e] = (y >= 0 && y < H && x >= 0 && x < W) ? g[img + (size_t)y * W + x] : 0.f;
+    }
+    for (int e = tid; e < CH * 9; e += 256) ws[e] = bfround(wl_[e]);
+    __syncthreads();
+    const int ty = tid >> 4, tx = tid & 15;
+    float gg[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) gg[t] = gp[(ty + 2 - t / 3) * 18 + tx + 2 - t % 3];
+    const uint16_t *ac = patch + ((ty + 1) * 18 + tx + 1) * PADC;
+    uint16_t *dst = dpre + (img + (size_t)(y0 + ty) * W + x0 + tx) * CH;
+    for (int c8 = 0; c8 < CH; c8 += 8) {
+        uint32_t o[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            float v = 0.f;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) v += ws[(c8 + e) * 9 + t] * gg[t];
+            o[e] = ac[c8 + e] != 0 ? f2bf(v) : 0u;
+        }
+        *reinterpret_cast<uint4 *>(dst + c8) =
+            make_uint4(o[0] | (o[1] << 16), o[2] | (o[3] << 16), o[4] | (o[5] << 16), o[6] | (o[7] << 16));
+    }
+    for (int pr = tid; pr < CH * 9; pr += 256) {
+        const int c = pr / 9, t = pr - c * 9, dy = t / 3, dx = t % 3;
+        float s = 0.f;
+        for (int py = 0; py < 16; ++py)
+            for (int px = 0; px < 16; ++px)
+                s += bf2f(patch[((py + dy) * 18 + px + dx) * PADC + c]) * gp[(py + 1) * 18 + px + 1];
+        atomicAdd(&dW[pr], s);
+    }
+    float sg = gp[(ty + 1) * 18 + tx + 1];
+    for (int o = 32; o >= 1; o >>= 1) sg += __shfl_xor(sg, o);
+    if ((tid & 63) == 0) red[tid >> 6] = sg;
+    __syncthreads();
+    if (tid == 0) atomicAdd(db, red[0] + red[1] + red[2] + red[3]);
+}
+
+// Weight and bias gradients of a 64 -> 64 layer:
+//   dW[o][c][t] += sum_p dpre[p][o] act[p + (t - centre)][c],  db[o] += sum_p dpre[p][o].
+// A workgroup walks 16x16 pixel blocks and accumulates all 9 x 64 x 64
+// outputs in MFMA accumulators (wave w: output channels 16w..16w+15).
+__global__ void __launch_bounds__(256) k_dw64(const uint16_t *__restrict__ dpre, const uint16_t *__restrict__ act,
+                                              float *__restrict__ dW, float *__restrict__ db, int H, int W,
+                                              int nbx, int nby, int nblocks) {
+    extern __shared__ uint4 smem4[];
+    uint16_t *dT = reinterpret_cast<uint16_t *>(smem4);   // [64][DT_STRIDE]   dpre transposed
+    uint16_t *aT = dT + CH * DT_STRIDE;                   // [3][64][AT_STRIDE] act transposed, shifted by dx
+    float *red = reinterpret_cast<float *>(aT + 3 * CH * AT_STRIDE);   // [256]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
+    floatx4 acc[9][4];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[t][n] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    const BlockWalk walk(blockIdx.x, gridDim.x, nblocks);
+    for (int blk = walk.begin; blk < walk.end; blk += walk.step) {
+        int b, y0, x0;
+        block_origin(blk, nbx, nby, b, y0, x0);
+        const size_t img = (size_t)b * H * W;
+        __syncthreads();
+        for (int e = tid; e < 256 * 8; e += 256) {
+            const int pix = e >> 3, ch = e & 7;
+            const uint4 v = reinterpret_cast<const uint4 *>(
+                dpre + (img + (size_t)(y0 + (pix >> 4)) * W + x0 + (pix & 15)) * CH)[ch];
+            const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                dT[(ch * 8 + 2 * q) * DT_STRIDE + pix] = (uint16_t)(u[q] & 0xFFFFu);
+                dT[(ch * 8 + 2 * q + 1) * DT_STRIDE + pix] = (uint16_t)(u[q] >> 16);
+            }
+        }
+        for (int e = tid; e < PATCH_CHUNKS; e += 256) {
+            const int pix = e >> 3, ch = e & 7, py = pix / 18, px = pix - py * 18;
+            const int y = y0 - 1 + py, x = x0 - 1 + px;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (y >= 0 && y < H && x >= 0 && x < W)
+                v = reinterpret_cast<const uint4 *>(act + (img + (size_t)y * W + x) * CH)[ch];
+            const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int cc = px - dx;
+                if (cc < 0 || cc >= 16) continue;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    aT[(dx * CH + ch * 8 + 2 * q) * AT_STRIDE + py * 16 + cc] = (uint16_t)(u[q] & 0xFFFFu);
+                    aT[(dx * CH + ch * 8 + 2 * q + 1) * AT_STRIDE + py * 16 + cc] = (uint16_t)(u[q] >> 16);
+                }
+            }
+        }
+        __syncthreads();
+        {
+            const int o = tid & 63, q0 = (tid >> 6) * 64;
+            for (int p = q0; p < q0 + 64; ++p) bsum += bf2f(dT[o * DT_STRIDE + p]);
+        }
+        for (int ks = 0; ks < 8; ++ks) {
+            const int pr = 2 * ks;
+            const bf16x8 a =
+                as_bf16x8(*reinterpret_cast<const uint4 *>(dT + (wave * 16 + j) * DT_STRIDE + pr * 16 + 8 * g));
+            const int row = pr + (g >> 1), col = 8 * (g & 1);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int dy = t / 3, dx = t - dy * 3;
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    const bf16x8 bv = as_bf16x8(*reinterpret_cast<const uint4 *>(
+                        aT + (dx * CH + n * 16 + j) * AT_STRIDE + (row + dy) * 16 + col));
+                    acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[t][n], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = wave * 16 + 4 * g + r, c = n * 16 + j;
+                atomicAdd(&dW[(o * CH + c) * 9 + t], acc[t][n][r]);
+            }
+    red[tid] = bsum;
+    __syncthreads();
+    if (tid < 64) atomicAdd(&db[tid], red[tid] + red[tid + 64] + red[tid + 128] + red[tid + 192]);
+}
+
+// Weight and bias gradients of the first layer: dW0[c][t] += sum_p z[p + (t - centre)] dpre[p][c].
+__global__ void __launch_bounds__(256) k_dw_in(const float *__restrict__ z, const uint16_t *__restrict__ dpre,
+                                               float *__restrict__ dW, float *__restrict__ db, int H, int W) {
+    __shared__ float zp[18][18];
+    __shared__ uint16_t dp[256][CH + 2];
+    const int b = blockIdx.z, y0 = blockIdx.y * 16, x0 = blockIdx.x * 16, tid = threadIdx.x;
+    const size_t img = (size_t)b * H * W;
+    for (int e = tid; e < 18 * 18; e += 256) {
+        const int py = e / 18, px = e - py * 18, y = y0 - 1 + py, x = x0 - 1 + px;
+        zp[py][px] = (y >= 0 && y < H && x >= 0 && x < W) ? z[img + (size_t)y * W + x] : 0.f;
+    }
+    for (int e = tid; e < 256 * CH; e += 256) {
+        const int pix = e >> 6, c = e & 63;
+        dp[pix][c] = dpre[(img + (size_t)(y0 + (pix >> 4)) * W + x0 + (pix & 15)) * CH + c];
+    }
+    __syncthreads();
+    for (int pr = tid; pr < CH * 9 + CH; pr += 256) {
+        float s = 0.f;
+        if (pr < CH * 9) {
+            const int c = pr / 9, t = pr - c * 9, dy = t / 3, dx = t % 3;
+            for (int p = 0; p < 256; ++p) s += zp[(p >> 4) + dy][(p & 15) + dx] * bf2f(dp[p][c]);
+            atomicAdd(&dW[pr], s);
+        } else {
+            const int c = pr - CH * 9;
+            for (int p = 0; p < 256; ++p) s += bf2f(dp[p][c]);
+            atomicAdd(&db[c], s);
+        }
+    }
+}
+
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ gr, float *__restrict__ m,
+                       float *__restrict__ v, int64_t n, float lr, float c1, float c2) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = gr[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    }
+}
+
+// Counter-based standard normals: splitmix64 of (seed, index), Box-Muller.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ float normal_at(uint64_t seed, uint64_t i) {
+    const uint64_t r = mix64(seed * 0xD1B54A32D192ED03ull + i);
+    const float u1 = ((float)(r >> 40) + 0.5f) * (1.0f / 16777216.0f);
+    const float u2 = (float)((r >> 16) & 0xFFFFFFull) * (1.0f / 16777216.0f);
+    return sqrtf(-2.f * logf(u1)) * cospif(2.f * u2);
+}
+
+__global__ void k_noisy(const float *__restrict__ clean, float *__restrict__ noisy, int64_t n, float sigma,
+                        uint64_t seed) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        noisy[i] = clean[i] + sigma * normal_at(seed, (uint64_t)i);
+}
+
+__global__ void k_init_params(float *p, const int64_t *offs, const float *stds, int nl, int64_t total, uint64_t seed) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        int l = 0;
+        while (l + 1 < 2 * nl && i >= offs[l + 1]) ++l;
+        p[i] = (l & 1) ? 0.f : stds[l >> 1] * normal_at(seed, (uint64_t)i);   // odd segments: biases
+    }
+}
+
+// Facet tiles: z_tile[b][ty][tx] = z[oy + ty][ox + tx] inside the valid
+// rectangle, 0 elsewhere.
+template <typename T>
+__global__ void k_facet_extract(const T *__restrict__ z, float *__restrict__ zt, CnnGeo geo, int B, int h, int w) {
+    const int64_t n = (int64_t)B * h * w;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(i / ((int64_t)h * w)), r = (int)(i - (int64_t)b * h * w), ty = r / w, tx = r - ty * w;
+        const int4 vr = valid_rect(geo, b, h, w);
+        const int f = geo.first + b, fy = f / geo.nfx, fx = f - fy * geo.nfx;
+        float v = 0.f;
+        if (ty >= vr.x && ty < vr.y && tx >= vr.z && tx < vr.w)
+            v = (float)z[(size_t)(fy * geo.core - geo.halo + ty) * geo.N + (fx * geo.core - geo.halo + tx)];
+        zt[i] = v;
+    }
+}
+
+// out[y][x] = D_tile[b][halo + cy][halo + cx] for the core pixels of each facet.
+template <typename T>
+__global__ void k_facet_insert(const float *__restrict__ Dt, T *__restrict__ out, CnnGeo geo, int B, int h, int w) {
+    const int64_t cc = (int64_t)geo.core * geo.core;
+    const int64_t n = (int64_t)B * cc;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(i / cc), r = (int)(i - (int64_t)b * cc), cy = r / geo.core, cx = r - cy * geo.core;
+        const int f = geo.first + b, fy = f / geo.nfx, fx = f - fy * geo.nfx;
+        const int y = fy * geo.core + cy, x = fx * geo.core + cx;
+        if (y < geo.N && x < geo.N)
+            out[(size_t)y * geo.N + x] = (T)Dt[((size_t)b * h + geo.halo + cy) * w + geo.halo + cx];
+    }
+}
+
+inline int gridn(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
+
+}  // namespace
+
+}  // namespace ri
+
+using namespace ri;
+
+struct ri_cnn {
+    int L = 10, maxB = 0, maxH = 0, maxW = 0, training = 0, n_cu = 256;
+    int64_t P = 0;
+    std::vector<int64_t> off;          // [2L+1]: weight, bias offsets of each layer
+    float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
+    uint16_t *wfwd = nullptr, *wbwd = nullptr;   // packed hidden layers [L-2][WPK*8]
+    std::vector<uint16_t *> act;       // training: L-1 activation buffers; inference: 2
+    uint16_t *dpre[2] = {nullptr, nullptr};
+    float *D = nullptr, *g = nullptr, *zin = nullptr;
+    double *part = nullptr;
+    int64_t step = 0;
+    std::string err;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+void *cnn_alloc(ri_cnn *n, size_t bytes) {
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(RI_ENOMEM, "hipMalloc failed for the CNN (" + std::to_string(bytes) + " B)");
+    }
+    n->allocs.push_back(p);
+    return p;
+}
+
+size_t conv64_lds() { return (size_t)18 * 18 * PADC * 2 + (size_t)WPK * 16 + CH * 4; }
+size_t convout_lds() { return (size_t)18 * 18 * PADC * 2 + 9 * CH * 4; }
+size_t outbwd_lds() { return (size_t)18 * 18 * PADC * 2 + 18 * 18 * 4 + CH * 9 * 4 + 16; }
+size_t dw64_lds() { return ((size_t)CH * DT_STRIDE + 3 * CH * AT_STRIDE) * 2 + 256 * 4; }
+
+void check_shape(const ri_cnn *n, int B, int h, int w) {
+    if (B < 1 || h < 16 || w < 16 || h % 16 || w % 16 || h > n->maxH || w > n->maxW || B > n->maxB)
+        throw Error(RI_EINVAL, "batch/size outside the network's buffers or not multiples of 16");
+}
+
+void repack(ri_cnn *n, hipStream_t s) {
+    for (int l = 1; l <= n->L - 2; ++l)
+        hipLaunchKernelGGL(k_pack, dim3((WPK * 8 + 255) / 256), dim3(256), 0, s, n->params + n->off[2 * l],
+                           n->wfwd + (size_t)(l - 1) * WPK * 8, n->wbwd + (size_t)(l - 1) * WPK * 8);
+}
+
+int persistent_grid(const ri_cnn *n, int nblocks) {
+    const int g = std::min(nblocks, n->n_cu);
+    return g >= N_XCD ? g - g % N_XCD : g;
+}
+
+// Forward through all layers; hidden activations into act[0..L-2] (training)
+// or the ping-pong pair act[0], act[1] (inference).
+void forward(ri_cnn *n, const float *z, float *D, int B, int h, int w, const CnnGeo &geo, hipStream_t s) {
+    dim3 grid(w / 16, h / 16, B);
+    const int L = n->L, nbx = w / 16, nby = h / 16, nb = nbx * nby * B;
+    auto A = [&](int l) { return n->training ? n->act[l] : n->act[l & 1]; };
+    hipLaunchKernelGGL(k_conv_in, grid, dim3(256), 0, s, z, A(0), n->params + n->off[0], n->params + n->off[1], geo,
+                       h, w);
+    for (int l = 1; l <= L - 2; ++l)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<0>), dim3(persistent_grid(n, nb)), dim3(256), conv64_lds(), s,
+                           A(l - 1), A(l), reinterpret_cast<const uint4 *>(n->wfwd + (size_t)(l - 1) * WPK * 8),
+                           n->params + n->off[2 * l + 1], (const uint16_t *)nullptr, geo, h, w, nbx, nby, nb);
+    hipLaunchKernelGGL(k_conv_out, grid, dim3(256), convout_lds(), s, A(L - 2), z, D,
+                       n->params + n->off[2 * (L - 1)], n->params + n->off[2 * (L - 1) + 1], h, w);
+    RI_CHECK_HIP(hipGetLastError());
+}
+
+// Gradients of sum(g * net(z)) into n->grads (zeroed here); activations from forward().
+void backward(ri_cnn *n, const float *z, const float *g, int B, int h, int w, hipStream_t s) {
+    const int L = n->L;
+    dim3 grid(w / 16, h / 16, B);
+    fill_real<float>(n->grads, n->P, 0.f, s);
+    hipLaunchKernelGGL(k_out_backward, grid, dim3(256), outbwd_lds(), s, g, n->act[L - 2],
+                       n->params + n->off[2 * (L - 1)], n->dpre[0], n->grads + n->off[2 * (L - 1)],
+                       n->grads + n->off[2 * (L - 1) + 1], h, w);
+    int cur = 0;
+    const int nbx = w / 16, nby = h / 16, nb = nbx * nby * B;
+    const CnnGeo full;
+    for (int l = L - 2; l >= 1; --l) {
+        hipLaunchKernelGGL(k_dw64, dim3(persistent_grid(n, nb)), dim3(256), dw64_lds(), s, n->dpre[cur],
+                           n->act[l - 1], n->grads + n->off[2 * l], n->grads + n->off[2 * l + 1], h, w, nbx, nby, nb);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<1>), dim3(persistent_grid(n, nb)), dim3(256), conv64_lds(), s,
+                           n->dpre[cur], n->dpre[cur ^ 1],
+                           reinterpret_cast<const uint4 *>(n->wbwd + (size_t)(l - 1) * WPK * 8),
+                           (const float *)nullptr, n->act[l - 1], full, h, w, nbx, nby, nb);
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(k_dw_in, grid, dim3(256), 0, s, z, n->dpre[cur], n->grads + n->off[0], n->grads + n->off[1],
+                       h, w);
+    RI_CHECK_HIP(hipGetLastError());
+}
+
+template <typename F>
+ri_status cnn_guard(const ri_cnn *n, F &&fn) {
+    try {
+        fn();
+        return RI_OK;
+    } catch (const Error &e) {
+        if (n) const_cast<ri_cnn *>(n)->err = e.msg;
+        return e.code;
+    } catch (const std::exception &e) {
+        if (n) const_cast<ri_cnn *>(n)->err = e.what();
+        return RI_EDEVICE;
+    }
+}
+
+thread_local std::string g_cnn_err;
+
+void offsets_for(int L, std::vector<int64_t> &off, std::vector<float> *stds) {
+    off.assign(2 * L + 1, 0);
+    if (stds) stds->resize(L);
+    for (int l = 0; l < L; ++l) {
+        const int ci = l == 0 ? 1 : CH, co = l == L - 1 ? 1 : CH;
+        off[2 * l + 1] = off[2 * l] + (int64_t)co * ci * 9;
+        off[2 * l + 2] = off[2 * l + 1] + co;
+        if (stds) (*stds)[l] = std::sqrt(2.0f / (9.0f * ci));
+    }
+}
+
+ri_cnn *create(const ri_cnn_desc &d, uint64_t seed) {
+    if (d.layers < 3 || d.layers > 64 || d.channels != CH || d.max_batch < 1 || d.max_h < 16 || d.max_w < 16 ||
+        d.max_h % 16 || d.max_w % 16 || d.max_h > 8192 || d.max_w > 8192)
+        throw Error(RI_EINVAL, "CNN: 3 <= layers <= 64, channels == 64, sides multiples of 16 in 16..8192");
+    int dev = 0;
+    RI_CHECK_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    RI_CHECK_HIP(hipGetDeviceProperties(&prop, dev));
+    const size_t need = std::max(conv64_lds(), dw64_lds());
+    if (need > (size_t)prop.sharedMemPerBlock)
+        throw Error(RI_EUNSUPPORTED, "CNN kernels need " + std::to_string(need) +
+                                         " B of LDS per workgroup; the device allows " +
+                                         std::to_string(prop.sharedMemPerBlock));
+    ri_cnn *n = new ri_cnn();
+    try {
+        n->n_cu = prop.multiProcessorCount;
+        n->L = d.layers; n->maxB = d.max_batch; n->maxH = d.max_h; n->maxW = d.max_w; n->training = d.training;
+        std::vector<float> stds;
+        offsets_for(n->L, n->off, &stds);
+        n->P = n->off[2 * n->L];
+        n->params = (float *)cnn_alloc(n, sizeof(float) * n->P);
+        n->wfwd = (uint16_t *)cnn_alloc(n, sizeof(uint16_t) * (size_t)(n->L - 2) * WPK * 8);
+        n->wbwd = (uint16_t *)cnn_alloc(n, sizeof(uint16_t) * (size_t)(n->L - 2) * WPK * 8);
+        const size_t npix = (size_t)n->maxB * n->maxH * n->maxW;
+        const int nact = n->training ? n->L - 1 : 2;
+        for (int i = 0; i < nact; ++i) n->act.push_back((uint16_t *)cnn_alloc(n, sizeof(uint16_t) * npix * CH));
+        n->D = (float *)cnn_alloc(n, sizeof(float) * npix);
+        n->zin = (float *)cnn_alloc(n, sizeof(float) * npix);
+        n->part = (double *)cnn_alloc(n, sizeof(double) * 1024);
+        if (n->training) {
+            n->grads = (float *)cnn_alloc(n, sizeof(float) * n->P);
+            n->dpre[0] = (uint16_t *)cnn_alloc(n, sizeof(uint16_t) * npix * CH);
+            n->dpre[1] = (uint16_t *)cnn_alloc(n, sizeof(uint16_t) * npix * CH);
+            n->g = (float *)cnn_alloc(n, sizeof(float) * npix);
+            n->m = (float *)cnn_alloc(n, sizeof(float) * n->P);
+            n->v = (float *)cnn_alloc(n, sizeof(float) * n->P);
+            fill_real<float>(n->m, n->P, 0.f, nullptr);
+            fill_real<float>(n->v, n->P, 0.f, nullptr);
+        }
+        int64_t *doffs = (int64_t *)cnn_alloc(n, sizeof(int64_t) * n->off.size());
+        float *dstd = (float *)cnn_alloc(n, sizeof(float) * n->L);
+        RI_CHECK_HIP(hipMemcpy(doffs, n->off.data(), sizeof(int64_t) * n->off.size(), hipMemcpyHostToDevice));
+        RI_CHECK_HIP(hipMemcpy(dstd, stds.data(), sizeof(float) * n->L, hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(k_init_params, dim3(gridn(n->P)), dim3(256), 0, nullptr, n->params, doffs, dstd, n->L, n->P,
+                           seed);
+        repack(n, nullptr);
+        RI_CHECK_HIP(hipGetLastError());
+        RI_CHECK_HIP(hipDeviceSynchronize());
+    } catch (...) {
+        ri::cnn_destroy(n);
+        throw;
+    }
+    return n;
+}
+
+}  // namespace
+
+namespace ri {
+
+ri_cnn *cnn_create_inference(int layers, int max_batch, int side) {
+    ri_cnn_desc d{};
+    d.layers = layers;
+    d.channels = CH;
+    d.max_batch = max_batch;
+    d.max_h = side;
+    d.max_w = side;
+    d.training = 0;
+    return create(d, 0);
+}
+
+void cnn_destroy(ri_cnn *n) {
+    if (!n) return;
+    (void)hipDeviceSynchronize();
+    for (void *p : n->allocs) (void)hipFree(p);
+    delete n;
+}
+
+int64_t cnn_param_count_for(int layers) {
+    std::vector<int64_t> off;
+    offsets_for(layers, off, nullptr);
+    return off.back();
+}
+
+int cnn_layers(const ri_cnn *n) { return n->L; }
+
+void cnn_load_params(ri_cnn *n, const float *params, hipStream_t s) {
+    RI_CHECK_HIP(hipMemcpyAsync(n->params, params, sizeof(float) * n->P, hipMemcpyDeviceToDevice, s));
+    repack(n, s);
+    RI_CHECK_HIP(hipGetLastError());
+}
+
+int cnn_tile_side(int N, int core, int halo) {
+    const bool whole = core <= 0 || core >= N;
+    return ((whole ? N : core + 2 * halo) + 15) / 16 * 16;
+}
+
+template <typename T>
+void cnn_denoise(ri_cnn *n, const T *z, T *out, int N, int core, int halo, hipStream_t s) {
+    const bool whole = core <= 0 || core >= N;
+    CnnGeo geo;
+    geo.N = N;
+    geo.core = whole ? N : core;
+    geo.halo = whole ? 0 : halo;
+    geo.nfx = (N + geo.core - 1) / geo.core;
+    const int side = cnn_tile_side(N, core, halo);
+    const int nf = geo.nfx * geo.nfx;
+    if (side > n->maxH || side > n->maxW) throw Error(RI_EINVAL, "facet tile larger than the network's buffers");
+    const int per = std::min(nf, n->maxB);
+    for (int f0 = 0; f0 < nf; f0 += per) {
+        const int B = std::min(per, nf - f0);
+        geo.first = f0;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_facet_extract<T>), dim3(gridn((int64_t)B * side * side)), dim3(256), 0,
+                           s, z, n->zin, geo, B, side, side);
+        forward(n, n->zin, n->D, B, side, side, geo, s);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_facet_insert<T>), dim3(gridn((int64_t)B * geo.core * geo.core)),
+                           dim3(256), 0, s, n->D, out, geo, B, side, side);
+    }
+    RI_CHECK_HIP(hipGetLastError());
+}
+template void cnn_denoise<float>(ri_cnn *, const float *, float *, int, int, int, hipStream_t);
+template void cnn_denoise<double>(ri_cnn *, const double *, double *, int, int, int, hipStream_t);
+
+}  // namespace ri
+
+extern "C" {
+
+ri_status ri_cnn_create(const ri_cnn_desc *d, uint64_t seed, ri_cnn **out) {
+    if (!out || !d) {
+        g_cnn_err = "desc or out is NULL";
+        return RI_EINVAL;
+    }
+    *out = nullptr;
+    try {
+        *out = create(*d, seed);
+        return RI_OK;
+    } catch (const Error &e) {
+        g_cnn_err = e.msg;
+        return e.code;
+    } catch (const std::exception &e) {
+        g_cnn_err = e.what();
+        return RI_EDEVICE;
+    }
+}
+
+void ri_cnn_destroy(ri_cnn *n) { ri::cnn_destroy(n); }
+
+const char *ri_cnn_last_error(const ri_cnn *n) { return n ? n->err.c_str() : g_cnn_err.c_str(); }
+
+int64_t ri_cnn_param_count(const ri_cnn *n) { return n ? n->P : 0; }
+
+ri_status ri_cnn_set_params(ri_cnn *n, const float *params, ri_stream stream) {
+    if (!n || !params) return RI_EINVAL;
+    return cnn_guard(n, [&] { cnn_load_params(n, params, reinterpret_cast<hipStream_t>(stream)); });
+}
+
+ri_status ri_cnn_get_params(const ri_cnn *n, float *params, ri_stream stream) {
+    if (!n || !params) return RI_EINVAL;
+    return cnn_guard(n, [&] {
+        RI_CHECK_HIP(hipMemcpyAsync(params, n->params, sizeof(float) * n->P, hipMemcpyDeviceToDevice,
+                                    reinterpret_cast<hipStream_t>(stream)));
+    });
+}
+
+ri_status ri_cnn_forward(ri_cnn *n, const float *z, float *out, int32_t B, int32_t h, int32_t w, ri_stream stream) {
+    if (!n || !z || !out) return RI_EINVAL;
+    return cnn_guard(n, [&] {
+        check_shape(n, B, h, w);
+        forward(n, z, out, B, h, w, CnnGeo(), reinterpret_cast<hipStream_t>(stream));
+    });
+}
+
+ri_status ri_cnn_grad(ri_cnn *n, const float *z, const float *g, int32_t B, int32_t h, int32_t w, float *grads,
+                      ri_stream stream) {
+    if (!n || !z || !g || !grads) return RI_EINVAL;
+    return cnn_guard(n, [&] {
+        if (!n->training) throw Error(RI_EINVAL, "network created without training buffers");
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        check_shape(n, B, h, w);
+        forward(n, z, n->D, B, h, w, CnnGeo(), s);
+        backward(n, z, g, B, h, w, s);
+        RI_CHECK_HIP(hipMemcpyAsync(grads, n->grads, sizeof(float) * n->P, hipMemcpyDeviceToDevice, s));
+    });
+}
+
+ri_status ri_cnn_train_step(ri_cnn *n, const float *clean, int32_t B, int32_t h, int32_t w, float sigma,
+                            uint64_t seed, float lr, double *loss, ri_stream stream) {
+    if (!n || !clean) return RI_EINVAL;
+    return cnn_guard(n, [&] {
+        if (!n->training) throw Error(RI_EINVAL, "network created without training buffers");
+        if (!(sigma >= 0.f) || !(lr > 0.f)) throw Error(RI_EINVAL, "sigma >= 0 and lr > 0 required");
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        check_shape(n, B, h, w);
+        const int64_t npix = (int64_t)B * h * w;
+        hipLaunchKernelGGL(k_noisy, dim3(gridn(npix)), dim3(256), 0, s, clean, n->zin, npix, sigma, seed);
+        forward(n, n->zin, n->D, B, h, w, CnnGeo(), s);
+        hipLaunchKernelGGL(k_l1, dim3(1024), dim3(256), 0, s, n->D, clean, n->g, npix, n->part);
+        if (loss) reduce_partials(n->part, 1024, 1, 1, loss, s);
+        backward(n, n->zin, n->g, B, h, w, s);
+        n->step++;
+        const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, (double)n->step)));
+        const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, (double)n->step)));
+        hipLaunchKernelGGL(k_adam, dim3(gridn(n->P)), dim3(256), 0, s, n->params, n->grads, n->m, n->v, n->P, lr, c1,
+                           c2);
+        repack(n, s);
+        RI_CHECK_HIP(hipGetLastError());
+    });
+}
+
+}  // extern "C"

@@ -145,6 +145,28 @@ __global__ void k_diff2(const T *__restrict__ a, T alpha, const T *__restrict__ 
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+template <typename T>
+__global__ void k_max(const T *__restrict__ a, int64_t n, double *part) {
+    __shared__ double s_red[4];
+    double m = -INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = fmax(m, (double)a[i]);
+    for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
+}
+
+__global__ void k_reduce_max(const double *part, int n, double *out) {
+    __shared__ double s_red[4];
+    double m = -INFINITY;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, part[i]);
+    for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
+}
+
 // out[k] = sum_i part[i * stride + k], i < n (fixed order).
 __global__ void k_reduce(const double *part, int n, int stride, int count, double *out) {
     __shared__ double s_red[4];
@@ -230,6 +252,14 @@ template <typename T>
 void dot_partials(const T *a, const T *b, int64_t n, double *partials, hipStream_t s) {
     hipLaunchKernelGGL(k_dot<T>, dim3(RED_WG), dim3(256), 0, s, a, b, n, partials);
 }
+
+template <typename T>
+void max_value(const T *a, int64_t n, double *partials, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_max<T>, dim3(RED_WG), dim3(256), 0, s, a, n, partials);
+    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(256), 0, s, partials, RED_WG, out);
+}
+template void max_value<float>(const float *, int64_t, double *, double *, hipStream_t);
+template void max_value<double>(const double *, int64_t, double *, double *, hipStream_t);
 
 template <typename T>
 void diff2_partials(const T *a, T alpha, const T *b, int64_t n, double *partials, hipStream_t s) {

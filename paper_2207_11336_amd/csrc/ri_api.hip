@@ -130,7 +130,21 @@ void fb_step_sorted(ri_ctx *c, const T *x_in, const cx<T> *ys, double gamma, int
             reduce_partials(tile_part(c), tiles_partials(c), 1, 1, norms + 2, s);
         }
     } else {
-        throw Error(RI_EUNSUPPORTED, "CNN denoiser not available in this context");
+        // PnP step: z = x - gamma g, x_out = D(z) facet by facet
+        require(c->cnn != nullptr, "no CNN denoiser loaded (ri_load_denoiser)");
+        const int64_t n = (int64_t)c->N * c->N;
+        axpby<T>(p.img1, x_in, (T)1, p.img0, (T)(-gamma), n, s);
+        {
+            ProfScope ps(c, PROF_PROX, s);
+            cnn_denoise<T>(c->cnn, p.img1, x_out, c->N, c->d.facet_core, c->d.facet_halo, s);
+        }
+        if (norms) {
+            diff2_partials<T>(x_out, (T)1, x_in, n, img_part(c), s);
+            reduce_partials(img_part(c), 1024, 1, 1, norms, s);
+            dot_partials<T>(x_out, x_out, n, img_part(c), s);
+            reduce_partials(img_part(c), 1024, 1, 1, norms + 1, s);
+            reduce_partials(tile_part(c), tiles_partials(c), 1, 1, norms + 2, s);
+        }
     }
     if (norms && x_true) {
         diff2_partials<T>(x_out, (T)alpha, x_true, (int64_t)c->N * c->N, img_part(c), s);
@@ -245,6 +259,36 @@ double power_iteration(ri_ctx *c, int max_it, double rtol, const double *x0, int
     return L;
 }
 
+// Peak of the dirty image Re{Phi^dagger y} (y in internal order), via the
+// fused gradient at x = 0, which returns -Re{Phi^dagger y}.
+template <typename T>
+double dirty_peak(ri_ctx *c, const cx<T> *ys, hipStream_t s) {
+    Prec<T> &p = prec<T>(c);
+    const int64_t n = (int64_t)c->N * c->N;
+    fill_real<T>(p.img1, n, (T)0, s);
+    do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, p.img1, ys, p.img0, s);
+    axpby<T>(p.img0, p.img0, (T)-1, nullptr, (T)0, n, s);
+    max_value<T>(p.img0, n, img_part(c), c->d_scalars, s);
+    RI_CHECK_HIP(hipMemcpyAsync(c->h_pinned, c->d_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
+    RI_CHECK_HIP(hipStreamSynchronize(s));
+    return c->h_pinned[0];
+}
+
+// beta = max_i (Re{Phi^dagger Phi} delta)_i, delta = 1 at the phase centre
+// (pixel (N/2, N/2) of the row-major image whose centre is index 0 of the grid).
+template <typename T>
+double dirty_beam_peak(ri_ctx *c, hipStream_t s) {
+    Prec<T> &p = prec<T>(c);
+    const int64_t n = (int64_t)c->N * c->N;
+    fill_real<T>(p.img1, n, (T)0, s);
+    fill_real<T>(p.img1 + (int64_t)(c->N / 2) * c->N + c->N / 2, 1, (T)1, s);
+    do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, p.img1, nullptr, p.img0, s);
+    max_value<T>(p.img0, n, img_part(c), c->d_scalars, s);
+    RI_CHECK_HIP(hipMemcpyAsync(c->h_pinned, c->d_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
+    RI_CHECK_HIP(hipStreamSynchronize(s));
+    return c->h_pinned[0];
+}
+
 // Forward-backward solve on its own stream. The iteration is captured once
 // as a graph of two steps (a -> b -> a) when requested and replayed; the FP64
 // norms of every step are copied out of the graph's fixed slots after each
@@ -284,7 +328,24 @@ bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_
         rr.alpha = 1.0;
         int kind = o.prox_kind;
         double param = o.tau / std::sqrt(2.0 * L);
-        if (kind == RI_PROX_CNN) throw Error(RI_EUNSUPPORTED, "CNN denoiser not loaded");
+        if (kind == RI_PROX_CNN) {
+            // Rescaled problem (eqs. C2-C3): alpha bounds the image peak (from
+            // the dirty image normalised by the dirty-beam peak) and is raised
+            // until the image-domain noise tau / (alpha sqrt(2L)) is at most
+            // the training level; the data are divided by alpha.
+            require(c->cnn != nullptr, "no CNN denoiser loaded (ri_load_denoiser)");
+            require(o.sigma_train > 0.0, "sigma_train must be > 0 for the CNN denoiser");
+            const double peak = dirty_peak<T>(c, ys, s);
+            const double beta = dirty_beam_peak<T>(c, s);
+            require(beta > 0.0, "dirty-beam peak is not positive");
+            rr.alpha = std::max(peak / beta, o.tau / (o.sigma_train * std::sqrt(2.0 * L)));
+            require(std::isfinite(rr.alpha) && rr.alpha > 0.0, "alpha is not positive (empty data?)");
+            cx<T> *yscaled = (cx<T> *)dev_alloc(c, sizeof(cx<T>) * std::max<int64_t>(1, c->M));
+            owned.push_back(yscaled);
+            axpby<T>((T *)yscaled, (const T *)ys, (T)(1.0 / rr.alpha), nullptr, (T)0, 2 * c->M, s);
+            ys = yscaled;
+            param = o.tau / (rr.alpha * std::sqrt(2.0 * L));
+        }
         rr.t_or_sigma = param;
         T *xa = (T *)dev_alloc(c, sizeof(T) * n); owned.push_back(xa);
         T *xb = (T *)dev_alloc(c, sizeof(T) * n); owned.push_back(xb);
@@ -519,7 +580,7 @@ void ri_destroy(ri_ctx *c) {
     dev_free(c, c->d_counter);
     dev_free(c, c->d_partials);
     dev_free(c, c->d_scalars);
-    dev_free(c, c->cnn_w);
+    if (c->cnn) cnn_destroy(c->cnn);
     for (auto &a : c->allocs) (void)hipFree(a.first);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     for (auto &e : c->prof_ev) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
@@ -600,15 +661,21 @@ ri_status denoise(ri_ctx *c, const void *z, void *out, int32_t kind, double para
     return guard(c, [&] {
         require(z && out, "z or out is NULL");
         require(kind == RI_PROX_HAAR || kind == RI_PROX_CNN, "unknown denoiser kind");
-        require(c->N % 16 == 0, "the Haar prox needs N divisible by 16");
         if (kind == RI_PROX_HAAR) {
+            require(c->N % 16 == 0, "the Haar prox needs N divisible by 16");
             require(std::isfinite(param) && param >= 0.0, "threshold must be finite and >= 0");
             if (c->d.precision == 32)
                 haar_prox<float>(c, nullptr, nullptr, 0.f, (const float *)z, (float)param, (float *)out, nullptr, st(s));
             else
                 haar_prox<double>(c, nullptr, nullptr, 0.0, (const double *)z, param, (double *)out, nullptr, st(s));
         } else {
-            throw Error(RI_EUNSUPPORTED, "CNN denoiser not loaded");
+            require(c->cnn != nullptr, "no CNN denoiser loaded (ri_load_denoiser)");
+            require(z != out, "z and out may not alias for the CNN denoiser");
+            if (c->d.precision == 32)
+                cnn_denoise<float>(c->cnn, (const float *)z, (float *)out, c->N, c->d.facet_core, c->d.facet_halo, st(s));
+            else
+                cnn_denoise<double>(c->cnn, (const double *)z, (double *)out, c->N, c->d.facet_core, c->d.facet_halo,
+                                    st(s));
         }
         RI_CHECK_HIP(hipGetLastError());
     });
@@ -621,7 +688,7 @@ ri_status fb_step(ri_ctx *c, const void *x_in, const void *y, double gamma, int3
         require(x_in && x_out && x_in != x_out, "x_in, x_out must be distinct non-NULL buffers");
         require(std::isfinite(gamma) && gamma > 0.0, "gamma must be finite and > 0");
         require(kind == RI_PROX_HAAR || kind == RI_PROX_CNN, "unknown denoiser kind");
-        require(c->N % 16 == 0, "the Haar prox needs N divisible by 16");
+        require(c->N % 16 == 0, "the denoisers need N divisible by 16");
         if (c->d.precision == 32)
             do_fb_step<float>(c, (const float *)x_in, y, gamma, kind, param, (float *)x_out, norms, st(s));
         else
@@ -630,12 +697,23 @@ ri_status fb_step(ri_ctx *c, const void *x_in, const void *y, double gamma, int3
     });
 }
 
-ri_status ri_load_denoiser(ri_ctx *c, const void *weights, int64_t nbytes) {
+ri_status ri_load_denoiser(ri_ctx *c, const float *params, int64_t n_params, int32_t layers, ri_stream s) {
     if (!c) return RI_EINVAL;
     return guard(c, [&] {
-        (void)weights;
-        (void)nbytes;
-        throw Error(RI_EUNSUPPORTED, "CNN denoiser not built in this library version");
+        require(params != nullptr, "params is NULL");
+        require(layers >= 3 && layers <= 64, "layers must be in 3..64");
+        require(n_params == cnn_param_count_for(layers), "n_params does not match the 64-channel layout");
+        require(c->N % 16 == 0, "the CNN denoiser needs N divisible by 16");
+        const bool whole = c->d.facet_core <= 0 || c->d.facet_core >= c->N;
+        const int core = whole ? c->N : c->d.facet_core;
+        const int nfx = (c->N + core - 1) / core;
+        const int side = cnn_tile_side(c->N, c->d.facet_core, c->d.facet_halo);
+        if (c->cnn && cnn_layers(c->cnn) != layers) {
+            cnn_destroy(c->cnn);
+            c->cnn = nullptr;
+        }
+        if (!c->cnn) c->cnn = cnn_create_inference(layers, nfx * nfx, side);
+        cnn_load_params(c->cnn, params, st(s));
     });
 }
 

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/ri.h"
+#include "../../include/ri_cnn.h"
 
 namespace ri {
 
@@ -120,9 +121,8 @@ struct ri_ctx {
     double *d_scalars = nullptr;          // small FP64 scratch
     double *h_pinned = nullptr;           // pinned host scalars
 
-    // CNN denoiser
-    void *cnn_w = nullptr;
-    int64_t cnn_bytes = 0;
+    // CNN denoiser (inference network sized for this context's facets)
+    ri_cnn *cnn = nullptr;
 
     bool has_data = false;
     bool prof_on = false;
@@ -197,7 +197,26 @@ template <typename T> void dot_partials(const T *a, const T *b, int64_t n, doubl
 template <typename T> void diff2_partials(const T *a, T alpha, const T *b, int64_t n, double *partials,
                                           hipStream_t s);
 template <typename T> void axpby(T *out, const T *a, T alpha, const T *b, T beta, int64_t n, hipStream_t s);
+// out[0] = max_i a[i] (FP64), via RED_WG partials.
+template <typename T> void max_value(const T *a, int64_t n, double *partials, double *out, hipStream_t s);
 void scale_by_inv_sqrt(double *x, const double *sumsq, int64_t n, hipStream_t s);
 template <typename Tin, typename Tout> void convert(const Tin *in, Tout *out, int64_t n, hipStream_t s);
+
+// cnn.hip: the residual CNN denoiser seen from the imaging context.
+// Facet geometry of a batch: item b is facet first + b of an N x N image cut
+// into core x core facets (nfx per row) with a halo; its tile holds image rows
+// fy*core - halo ... (N == 0: every item is a whole image, nothing masked).
+struct CnnGeo {
+    int N = 0, core = 0, halo = 0, nfx = 1, first = 0;
+};
+ri_cnn *cnn_create_inference(int layers, int max_batch, int side);
+void cnn_destroy(ri_cnn *n);
+int64_t cnn_param_count_for(int layers);
+int cnn_layers(const ri_cnn *n);
+void cnn_load_params(ri_cnn *n, const float *params, hipStream_t s);
+// out = D(z) facet by facet (appendix D): core x core facets with a halo,
+// all facets of a batch in one launch per layer. z, out: N x N, type T.
+template <typename T> void cnn_denoise(ri_cnn *n, const T *z, T *out, int N, int core, int halo, hipStream_t s);
+int cnn_tile_side(int N, int core, int halo);
 
 }  // namespace ri

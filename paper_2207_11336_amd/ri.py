@@ -23,7 +23,9 @@ RI_NO_DATA = c_void_p(-1 & 0xFFFFFFFFFFFFFFFF)
 
 EXPORTS = ("ri_create", "ri_destroy", "ri_last_error", "phi_forward", "phi_adjoint", "ri_set_data",
            "ri_gradient", "ri_power_norm", "denoise", "fb_step", "ri_load_denoiser", "pnp_solve",
-           "ri_get_plan_stats", "ri_get_plan_arrays", "ri_profile", "ri_profile_read")
+           "ri_get_plan_stats", "ri_get_plan_arrays", "ri_profile", "ri_profile_read",
+           "ri_cnn_create", "ri_cnn_destroy", "ri_cnn_last_error", "ri_cnn_param_count", "ri_cnn_set_params",
+           "ri_cnn_get_params", "ri_cnn_forward", "ri_cnn_grad", "ri_cnn_train_step")
 
 
 class RIError(RuntimeError):
@@ -50,6 +52,11 @@ class ri_solve_report(ctypes.Structure):
     _fields_ = [("iters", c_int32), ("L", c_double), ("gamma", c_double), ("alpha", c_double),
                 ("t_or_sigma", c_double), ("final_rel_change", c_double), ("final_residual2", c_double),
                 ("snr_db", c_double), ("fell_back", c_int32), ("ms", c_double)]
+
+
+class ri_cnn_desc(ctypes.Structure):
+    _fields_ = [("layers", c_int32), ("channels", c_int32), ("max_batch", c_int32), ("max_h", c_int32),
+                ("max_w", c_int32), ("training", c_int32)]
 
 
 class ri_plan_stats(ctypes.Structure):
@@ -88,7 +95,8 @@ def load() -> ctypes.CDLL:
     L.denoise.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_double, c_void_p]; L.denoise.restype = st
     L.fb_step.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_double, c_void_p, c_void_p, c_void_p]
     L.fb_step.restype = st
-    L.ri_load_denoiser.argtypes = [c_void_p, c_void_p, c_int64]; L.ri_load_denoiser.restype = st
+    L.ri_load_denoiser.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_void_p]
+    L.ri_load_denoiser.restype = st
     L.pnp_solve.argtypes = [c_void_p, c_void_p, POINTER(ri_solve_opts), c_void_p, POINTER(ri_solve_report)]
     L.pnp_solve.restype = st
     L.ri_get_plan_stats.argtypes = [c_void_p, POINTER(ri_plan_stats)]; L.ri_get_plan_stats.restype = st
@@ -96,6 +104,20 @@ def load() -> ctypes.CDLL:
     L.ri_get_plan_arrays.restype = st
     L.ri_profile.argtypes = [c_void_p, c_int32]; L.ri_profile.restype = st
     L.ri_profile_read.argtypes = [c_void_p, POINTER(ri_kernel_times)]; L.ri_profile_read.restype = st
+    L.ri_cnn_create.argtypes = [POINTER(ri_cnn_desc), ctypes.c_uint64, POINTER(c_void_p)]
+    L.ri_cnn_create.restype = st
+    L.ri_cnn_destroy.argtypes = [c_void_p]; L.ri_cnn_destroy.restype = None
+    L.ri_cnn_last_error.argtypes = [c_void_p]; L.ri_cnn_last_error.restype = ctypes.c_char_p
+    L.ri_cnn_param_count.argtypes = [c_void_p]; L.ri_cnn_param_count.restype = c_int64
+    L.ri_cnn_set_params.argtypes = [c_void_p, c_void_p, c_void_p]; L.ri_cnn_set_params.restype = st
+    L.ri_cnn_get_params.argtypes = [c_void_p, c_void_p, c_void_p]; L.ri_cnn_get_params.restype = st
+    L.ri_cnn_forward.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p]
+    L.ri_cnn_forward.restype = st
+    L.ri_cnn_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]
+    L.ri_cnn_grad.restype = st
+    L.ri_cnn_train_step.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, ctypes.c_float,
+                                    ctypes.c_uint64, ctypes.c_float, c_void_p, c_void_p]
+    L.ri_cnn_train_step.restype = st
     _lib = L
     return L
 
@@ -262,12 +284,13 @@ def fb_step(ctx: Context, x_in, y, gamma: float, kind: int, param: float, x_out,
                                _image(ctx, x_out, "x_out"), np_, _stream(stream)))
 
 
-def ri_load_denoiser(ctx: Context, weights):
+def ri_load_denoiser(ctx: Context, params, layers: int = 10, stream=None):
+    """Load the CNN of RI_PROX_CNN from its FP32 parameter vector (ri_cnn.h layout)."""
     import torch
-    if not (isinstance(weights, torch.Tensor) and weights.is_cuda and weights.is_contiguous()):
-        raise TypeError("weights must be a contiguous GPU tensor")
-    nbytes = weights.numel() * weights.element_size()
-    _check(ctx, load().ri_load_denoiser(ctx.handle, c_void_p(weights.data_ptr()), nbytes))
+    if not (isinstance(params, torch.Tensor) and params.is_cuda):
+        raise TypeError("params must be a GPU tensor")
+    p = _dev(params, torch.float32, params.numel(), "params")
+    _check(ctx, load().ri_load_denoiser(ctx.handle, p, params.numel(), layers, _stream(stream)))
 
 
 def pnp_solve(ctx: Context, y, opts: ri_solve_opts, x_out) -> ri_solve_report:
@@ -301,3 +324,100 @@ def ri_profile_read(ctx: Context) -> ri_kernel_times:
     t = ri_kernel_times()
     _check(ctx, load().ri_profile_read(ctx.handle, ctypes.byref(t)))
     return t
+
+
+# ----------------------------------------------------------------------------
+# CNN denoiser (include/ri_cnn.h)
+# ----------------------------------------------------------------------------
+class Cnn:
+    """Owns one ``ri_cnn``; keeps its buffer limits for shape checks."""
+
+    def __init__(self, handle: int, desc: ri_cnn_desc):
+        self.handle = c_void_p(handle)
+        self.layers, self.max_batch = desc.layers, desc.max_batch
+        self.max_h, self.max_w, self.training = desc.max_h, desc.max_w, desc.training
+        self.n_params = int(load().ri_cnn_param_count(self.handle))
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            load().ri_cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_cnn(net: Cnn | None, status: int):
+    if status != RI_OK:
+        msg = load().ri_cnn_last_error(net.handle if net is not None else None)
+        raise RIError(status, msg.decode() if msg else "")
+
+
+def _batch(net: Cnn, t, name):
+    import torch
+    if t is None or t.dim() != 3:
+        raise ValueError(f"{name} must be a [batch, h, w] tensor")
+    B, h, w = t.shape
+    if B > net.max_batch or h > net.max_h or w > net.max_w or h % 16 or w % 16:
+        raise ValueError(f"{name} shape {tuple(t.shape)} exceeds the network's buffers or is not a multiple of 16")
+    return _dev(t, torch.float32, t.numel(), name), B, h, w
+
+
+def ri_cnn_create(layers: int = 10, max_batch: int = 1, max_h: int = 256, max_w: int = 256, training: bool = False,
+                  seed: int = 0, channels: int = 64) -> Cnn:
+    d = ri_cnn_desc()
+    d.layers, d.channels, d.max_batch, d.max_h, d.max_w, d.training = layers, channels, max_batch, max_h, max_w, \
+        1 if training else 0
+    out = c_void_p()
+    _check_cnn(None, load().ri_cnn_create(ctypes.byref(d), seed, ctypes.byref(out)))
+    return Cnn(out.value, d)
+
+
+def ri_cnn_destroy(net: Cnn):
+    net.close()
+
+
+def ri_cnn_param_count(net: Cnn) -> int:
+    return int(load().ri_cnn_param_count(net.handle))
+
+
+def ri_cnn_set_params(net: Cnn, params, stream=None):
+    import torch
+    _check_cnn(net, load().ri_cnn_set_params(net.handle, _dev(params, torch.float32, net.n_params, "params"),
+                                             _stream(stream)))
+
+
+def ri_cnn_get_params(net: Cnn, params, stream=None):
+    import torch
+    _check_cnn(net, load().ri_cnn_get_params(net.handle, _dev(params, torch.float32, net.n_params, "params"),
+                                             _stream(stream)))
+
+
+def ri_cnn_forward(net: Cnn, z, out, stream=None):
+    """out = z - net(z) for z, out: float32 [batch, h, w] on the GPU."""
+    zp, B, h, w = _batch(net, z, "z")
+    if out.shape != z.shape:
+        raise ValueError("out must have the shape of z")
+    op, _, _, _ = _batch(net, out, "out")
+    _check_cnn(net, load().ri_cnn_forward(net.handle, zp, op, B, h, w, _stream(stream)))
+
+
+def ri_cnn_grad(net: Cnn, z, g, grads, stream=None):
+    """grads = d sum(g * net(z)) / d params."""
+    import torch
+    zp, B, h, w = _batch(net, z, "z")
+    if g.shape != z.shape:
+        raise ValueError("g must have the shape of z")
+    gp, _, _, _ = _batch(net, g, "g")
+    _check_cnn(net, load().ri_cnn_grad(net.handle, zp, gp, B, h, w, _dev(grads, torch.float32, net.n_params, "grads"),
+                                       _stream(stream)))
+
+
+def ri_cnn_train_step(net: Cnn, clean, sigma: float, seed: int, lr: float, loss=None, stream=None):
+    import torch
+    cp, B, h, w = _batch(net, clean, "clean")
+    lp = _dev(loss, torch.float64, 1, "loss") if loss is not None else None
+    _check_cnn(net, load().ri_cnn_train_step(net.handle, cp, B, h, w, sigma, seed, lr, lp, _stream(stream)))

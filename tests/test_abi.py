@@ -54,6 +54,31 @@ def test_struct_layouts_match_header(tmp_path):
     assert got == want
 
 
+def test_cnn_desc_layout_matches_header(tmp_path):
+    src = tmp_path / "szc.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ri_cnn.h"\n'
+                   'int main(){printf("%zu %zu\\n",sizeof(ri_cnn_desc),offsetof(ri_cnn_desc,training));}\n')
+    exe = tmp_path / "szc"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert got == [ctypes.sizeof(R.ri_cnn_desc), R.ri_cnn_desc.training.offset]
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(channels=32), "channels == 64"),
+    (dict(layers=2), "layers"),
+    (dict(max_h=40), "multiples of 16"),
+    (dict(max_batch=0), "CNN"),
+])
+def test_cnn_create_rejects_bad_descriptions(kw, msg):
+    args = dict(layers=10, max_batch=1, max_h=64, max_w=64)
+    args.update(kw)
+    with pytest.raises(R.RIError) as e:
+        R.ri_cnn_create(**args)
+    assert e.value.status == R.RI_EINVAL
+    assert msg in str(e.value)
+
+
 @pytest.mark.parametrize("field,value,msg", [
     ("N", 24, "power of two"),
     ("N", 8, "N must be"),

@@ -102,6 +102,111 @@ def cpu_baseline(wl, uvw, n_sample: int):
                       f"{wl.name} (two {2 * wl.N}^2 FFTs included), median of 3 runs, {t:.2f} s each"}
 
 
+def cnn_flops(n_pixels: int, layers: int = 10, ch: int = 64) -> float:
+    """Algorithmic flops of one application of the residual CNN: per pixel
+    2 * 9 * c_in * c_out per layer (1 -> 64, 8 x 64 -> 64, 64 -> 1)."""
+    return float(n_pixels) * 2 * 9 * (ch + (layers - 2) * ch * ch + ch)
+
+
+def run_pnp(args, R, synth, ctx, noise, x_true, L):
+    """PnP-FB against plain FB on the blocked problem at the denoiser's dynamic
+    range. The visibility noise is set so that the rescaled image-domain noise
+    level tau / (alpha0 sqrt(2L)) equals the training level sigma (eqs. C2-C3,
+    alpha0 = dirty peak / dirty-beam peak); the network is trained at sigma on
+    synthetic patches by the library's own kernels; then plain FB (Haar-l1 +
+    positivity, threshold tau / sqrt(2L)) and PnP-FB (the CNN as D) run the
+    same number of hipGraph-replayed iterations from 0 with FP64 SNR traces."""
+    import numpy as np
+    import torch
+
+    from paper_2207_11336_amd.train import train_denoiser
+    N = x_true.shape[0]
+    sigma = args.pnp_sigma
+    y = torch.empty_like(noise)
+    R.phi_forward(ctx, x_true, y)
+    dirty = torch.empty_like(x_true)
+    R.phi_adjoint(ctx, y, dirty)
+    delta = torch.zeros_like(x_true)
+    delta[N // 2, N // 2] = 1.0
+    yd = torch.empty_like(y)
+    R.phi_forward(ctx, delta, yd)
+    beam = torch.empty_like(x_true)
+    R.phi_adjoint(ctx, yd, beam)
+    alpha0 = float(dirty.max()) / float(beam.max())
+    tau = sigma * alpha0 * math.sqrt(2.0 * L)
+    y += noise * (tau / math.sqrt(2))
+    del yd, beam, dirty, delta
+    isnr = 20 * math.log10(float(torch.linalg.vector_norm((y - noise * (tau / math.sqrt(2))).to(torch.complex128)))
+                           / (math.sqrt(y.numel()) * tau))
+    log(f"PnP data: alpha0 {alpha0:.4e}, sigma {sigma:.1e} -> tau {tau:.4e} (input SNR {isnr:.1f} dB)")
+    K = args.pnp_iters
+
+    def solve(kind, sig_train):
+        trace = np.zeros((K, 4))
+        opts = R.ri_solve_opts(max_iter=K, rel_tol=0.0, prox_kind=kind, tau=tau, sigma_train=sig_train, L=L,
+                               check_every=50, x_true=x_true.data_ptr(), trace=trace.ctypes.data, use_graph=1)
+        xs = torch.empty_like(x_true)
+        rep = R.pnp_solve(ctx, y, opts, xs)
+        return rep, trace
+
+    fb_rep, fb_tr = solve(R.RI_PROX_HAAR, 0.0)
+    log(f"FB x{fb_rep.iters} at sigma {sigma:.0e}: {fb_rep.ms:.1f} ms, SNR {fb_rep.snr_db:.2f} dB")
+    patches = torch.tensor(synth.training_patches(args.train_patches, 128), device=x_true.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    params, hist = train_denoiser(patches, sigma, steps=args.train_steps, batch=args.train_batch, lr=args.train_lr,
+                                  lr_min=args.train_lr / 100, log_every=max(1, args.train_steps // 4), log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del patches
+    train_flops = 3 * cnn_flops(args.train_steps * args.train_batch * 128 * 128)
+    R.ri_load_denoiser(ctx, params, 10)
+    # denoiser throughput on the whole image (facets as configured)
+    z = x_true.clone()
+    out = torch.empty_like(z)
+    R.denoise(ctx, z, out, R.RI_PROX_CNN, 0.0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        R.denoise(ctx, z, out, R.RI_PROX_CNN, 0.0)
+    e1.record()
+    torch.cuda.synchronize()
+    den_ms = e0.elapsed_time(e1) / 5
+    core = args.facet_core if 0 < args.facet_core < N else N
+    halo = args.facet_halo if 0 < args.facet_core < N else 0
+    side = (core + 2 * halo + 15) // 16 * 16
+    nf = ((N + core - 1) // core) ** 2
+    den_tfs = cnn_flops(nf * side * side) / (den_ms * 1e-3) / 1e12
+    log(f"denoiser: {den_ms:.3f} ms per application ({nf} tile(s) of {side}^2), {den_tfs:.1f} TFLOP/s")
+    try:
+        rep, tr = solve(R.RI_PROX_CNN, sigma)
+    except R.RIError as e:
+        log(f"PnP solve failed: {e}")
+        return {"error": str(e), "sigma": sigma, "train_s": train_s}
+    target = fb_rep.snr_db - 0.5
+    hit = np.nonzero(tr[:rep.iters, 2] >= target)[0]
+    fb_hit = np.nonzero(fb_tr[:fb_rep.iters, 2] >= target)[0]
+    marks = (10, 50, 100, 200, 300, 500, 1000)
+    res = {"sigma": sigma, "tau": tau, "input_snr_db": isnr, "alpha": rep.alpha, "iters": rep.iters,
+           "fb_ms": fb_rep.ms, "fb_final_snr_db": fb_rep.snr_db, "pnp_ms": rep.ms, "pnp_final_snr_db": rep.snr_db,
+           "pnp_ms_per_iter": rep.ms / max(1, rep.iters), "fb_ms_per_iter": fb_rep.ms / max(1, fb_rep.iters),
+           "fell_back": rep.fell_back, "target_snr_db": target,
+           "pnp_ms_to_target": float(tr[hit[0], 3]) if hit.size else None,
+           "fb_ms_to_target": float(fb_tr[fb_hit[0], 3]) if fb_hit.size else None,
+           "pnp_its_to_target": int(hit[0]) + 1 if hit.size else None,
+           "fb_residual2": fb_rep.final_residual2, "pnp_residual2": rep.final_residual2,
+           "pnp_snr_at": {str(k): round(float(tr[k - 1, 2]), 3) for k in marks if k <= rep.iters},
+           "fb_snr_at": {str(k): round(float(fb_tr[k - 1, 2]), 3) for k in marks if k <= fb_rep.iters},
+           "denoiser_ms": den_ms, "denoiser_tflops": den_tfs, "denoiser_tiles": nf, "denoiser_tile_side": side,
+           "train_steps": args.train_steps, "train_batch": args.train_batch, "train_s": train_s,
+           "train_tflops": train_flops / train_s / 1e12, "train_final_loss": hist[-1][1] if hist else None}
+    log(f"PnP x{rep.iters}: {rep.ms:.1f} ms ({res['pnp_ms_per_iter']:.3f} ms/it), SNR {rep.snr_db:.2f} dB vs FB "
+        f"{fb_rep.snr_db:.2f} dB; to {target:.2f} dB: PnP {res['pnp_ms_to_target']} ms vs FB "
+        f"{res['fb_ms_to_target']} ms; fell back {rep.fell_back}")
+    log(f"SNR trace FB {res['fb_snr_at']}  PnP {res['pnp_snr_at']}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +222,16 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the FB time-to-SNR run")
     ap.add_argument("--fb-iters", type=int, default=300)
+    ap.add_argument("--no-pnp", action="store_true", help="skip the denoiser training and the PnP-FB run")
+    ap.add_argument("--pnp-iters", type=int, default=300)
+    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--train-lr", type=float, default=1e-4)
+    ap.add_argument("--pnp-sigma", type=float, default=1e-4,
+                    help="image-domain noise level of the PnP comparison (1 / target dynamic range)")
+    ap.add_argument("--train-batch", type=int, default=16)
+    ap.add_argument("--train-patches", type=int, default=1024)
+    ap.add_argument("--facet-core", type=int, default=0, help="CNN facet core side (0: whole image in one tile)")
+    ap.add_argument("--facet-halo", type=int, default=32)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -237,14 +352,15 @@ def main():
 
     # Plain FB time-to-SNR on the 64-block decomposition (uneven angular sectors),
     # hipGraph-replayed iterations, FP64 SNR trace against the true sky.
-    fb_trace = None
+    fb_trace, pnp = None, None
     if not args.no_solve:
         wl2 = synth.C2
         sizes = synth.block_sizes(wl2.n_blocks, M, wl2.block_lo, wl2.block_hi)
         perm, offs = synth.blocked(uvw, sizes)
         ctxb = R.ri_create(R.plan_desc(N, M, cell_rad=wl.cell_rad, w_max=wl.W, n_wplanes=wl.n_wplanes,
                                        precision=32, g_mode=R.RI_G_CSR if best["mode"] == "csr" else R.RI_G_OTF,
-                                       tile=best["tile"], n_blocks=wl2.n_blocks), uvw[perm], block_offsets=offs)
+                                       tile=best["tile"], n_blocks=wl2.n_blocks, facet_core=args.facet_core,
+                                       facet_halo=args.facet_halo), uvw[perm], block_offsets=offs)
         yb = torch.empty(M, dtype=torch.complex64, device=dev)
         R.phi_forward(ctxb, x_true, yb)
         yb += noise[torch.as_tensor(perm, device=dev)] * (shared["tau"] / math.sqrt(2))
@@ -261,6 +377,8 @@ def main():
                     "ms_at": {str(k): round(float(trace[k - 1, 3]), 2) for k in (10, 50, 100, 200, 300) if k <= K}}
         log(f"FB x{K} on {st_b.n_blocks} blocks (graph): {rep.ms:.1f} ms, {rep.ms / max(1, rep.iters):.3f} ms/it, "
             f"SNR {rep.snr_db:.2f} dB")
+        if not args.no_pnp:
+            pnp = run_pnp(args, R, synth, ctxb, noise[torch.as_tensor(perm, device=dev)], x_true, L)
         ctxb.close()
         del yb
         torch.cuda.empty_cache()
@@ -278,7 +396,7 @@ def main():
         "config": {"workload": wl.name, "N": N, "grid": wl.Np, "M": M, "g_mode": best["mode"], "nnz": st_nnz,
                    "tile": best["tile"], "step": "fb_step: fused gradient + Haar-l1 prox + FP64 norms",
                    "fp64_gram_vis_per_s": fp64_rate, "plan_s": plan_s, "L": L, "snr_db": snr, **extra,
-                   "fb_time_to_snr": fb_trace},
+                   "fb_time_to_snr": fb_trace, "pnp": pnp},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -145,6 +145,40 @@ def random_image(N: int, seed: int, positive: bool = True) -> np.ndarray:
     return x
 
 
+def training_patches(n: int, size: int, seed: int = SEED_TRAIN) -> np.ndarray:
+    """Denoiser training images, float32 [n, size, size], positive, with the
+    statistics of ``sky`` at patch scale and an adaptive peak.
+
+    Per patch: Poisson(8) + 1 round compact sources (FWHM ~ U[1,3] px, peak
+    10^U[-4,0], centres U[0, size)^2), Poisson(1.5) elliptical Gaussians
+    (FWHM ~ U[4,40] px per axis, angle U[0,pi), peak 10^U[-3.5,-1.5], centres
+    U[0, size)^2); the patch is then scaled so that its peak is 10^U[-1,0]
+    (peak values upper-bounded by 1, dynamic range varying from patch to patch).
+    """
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:size, 0:size].astype(np.float64)
+    k = 1.0 / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    out = np.zeros((n, size, size), dtype=np.float32)
+    for i in range(n):
+        img = np.zeros((size, size))
+        for _ in range(rng.poisson(8.0) + 1):
+            s = rng.uniform(1.0, 3.0) * k
+            peak = 10.0 ** rng.uniform(-4.0, 0.0)
+            cy, cx = rng.uniform(0, size, size=2)
+            img += peak * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * s * s))
+        for _ in range(rng.poisson(1.5)):
+            sa, sb = rng.uniform(4.0, 40.0, size=2) * k
+            ang = rng.uniform(0.0, math.pi)
+            peak = 10.0 ** rng.uniform(-3.5, -1.5)
+            cy, cx = rng.uniform(0, size, size=2)
+            c, s_ = math.cos(ang), math.sin(ang)
+            a = c * (xx - cx) + s_ * (yy - cy)
+            b = -s_ * (xx - cx) + c * (yy - cy)
+            img += peak * np.exp(-(a * a) / (2 * sa * sa) - (b * b) / (2 * sb * sb))
+        out[i] = img * (10.0 ** rng.uniform(-1.0, 0.0) / img.max())
+    return out
+
+
 # ----------------------------------------------------------------------------
 # Array geometry and earth-rotation synthesis (Thompson-Moran-Swenson)
 # ----------------------------------------------------------------------------

@@ -4,11 +4,12 @@
 // Activations: bfloat16, NHWC with 64 channels (128 B per pixel).
 // 64 -> 64 layers: implicit GEMM on v_mfma_f32_16x16x32_bf16. A persistent
 // workgroup of four waves keeps the layer's packed weights in LDS and walks
-// 16 x 16 pixel blocks; for each block it stages the 18 x 18 input patch in
-// LDS (channel stride padded to 144 B) and every wave computes four pixel rows
-// for all 64 output channels: output channels are the MFMA rows (A = weights,
-// pre-packed in lane order so each lane reads one 16-byte chunk), pixels the
-// MFMA columns (B = the patch), K = 9 taps x 64 input channels in steps of 32.
+// 32 x 16 pixel blocks; for each block it stages the 34 x 18 input patch in
+// LDS (channel stride padded to 144 B) and every wave computes eight pixel
+// rows for all 64 output channels: output channels are the MFMA rows (A =
+// weights, pre-packed in lane order so each lane reads one 16-byte chunk),
+// pixels the MFMA columns (B = the patch), K = 9 taps x 64 input channels in
+// steps of 32; a patch row fragment serves the three row taps.
 // Lane l holds A[l%16][8(l/16)..+7], B[8(l/16)..+7][l%16] and receives
 // D[4(l/16)..+3][l%16], so the epilogue stores four consecutive channels of
 // one pixel. The next block's patch is loaded into registers while the
@@ -28,6 +29,7 @@
 #include "ri_internal.h"
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 namespace ri {
@@ -38,7 +40,6 @@ constexpr int CH = 64;
 constexpr int PADC = 72;                 // LDS channel stride of a pixel (144 B)
 constexpr int WPK = 9 * 2 * 4 * 64;      // 16-byte chunks of one packed 64x64x3x3 layer
 constexpr int PATCH_CHUNKS = 18 * 18 * 8;   // 16-byte chunks of an 18 x 18 x 64 patch
-constexpr int PRE = (PATCH_CHUNKS + 255) / 256;   // chunks per thread
 constexpr int DT_STRIDE = 256 + 8;       // LDS stride of one channel in the transposed gradient block
 constexpr int AT_STRIDE = 18 * 16 + 8;   // LDS stride of one channel in a shifted activation copy
 constexpr int N_XCD = 8;
@@ -91,30 +92,46 @@ __global__ void k_pack(const float *__restrict__ w, uint16_t *__restrict__ fwd, 
     bwd[idx] = f2bf(w[(k * CH + r) * 9 + (8 - t)]);
 }
 
-__device__ __forceinline__ void block_origin(int blk, int nbx, int nby, int &b, int &y0, int &x0) {
+__device__ __forceinline__ void block_origin(int blk, int nbx, int nby, int rows, int &b, int &y0, int &x0) {
     b = blk / (nbx * nby);
     const int rem = blk - b * nbx * nby, by = rem / nbx;
-    y0 = by * 16;
+    y0 = by * rows;
     x0 = (rem - by * nbx) * 16;
 }
 
-__device__ __forceinline__ void patch_fetch(uint4 (&pre)[PRE], const uint16_t *__restrict__ in, int blk, int nbx,
-                                            int nby, int H, int W, int tid) {
+// 64 -> 64 convolution blocks: 32 rows x 16 columns, input patch 34 x 18.
+constexpr int CB_ROWS = 32;
+constexpr int CP_ROWS = CB_ROWS + 2, CP_COLS = 18;
+constexpr int CP_CHUNKS = CP_ROWS * CP_COLS * 8;          // 16-byte chunks of the patch
+constexpr int CPRE = (CP_CHUNKS + 255) / 256;             // chunks per thread
+
+// Buffer resource over one batch item's activations (bytes < 2^32): loads at
+// an offset past the end return zeros and stores there are dropped, which is
+// how patch halos outside the image and rows past H are handled without
+// branches.
+constexpr unsigned OOB = 0xFFFFFFF0u;
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t item_rsrc(const uint16_t *base, int H, int W) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)((unsigned)H * (unsigned)W * (CH * 2u)),
+                                             0x00020000);
+}
+// Byte offset of channel c of pixel p (p < 2^25) in an item.
+__device__ __forceinline__ unsigned px_off(int p, int c) { return (unsigned)p * (CH * 2u) + (unsigned)c * 2u; }
+
+__device__ __forceinline__ void conv_patch_fetch(uint4 (&pre)[CPRE], const uint16_t *__restrict__ in, int blk,
+                                                 int nbx, int nby, int H, int W, int tid) {
     int b, y0, x0;
-    block_origin(blk, nbx, nby, b, y0, x0);
-    const size_t img = (size_t)b * H * W;
+    block_origin(blk, nbx, nby, CB_ROWS, b, y0, x0);
+    const __amdgpu_buffer_rsrc_t rs = item_rsrc(in + (size_t)b * H * W * CH, H, W);
 #pragma unroll
-    for (int k = 0; k < PRE; ++k) {
+    for (int k = 0; k < CPRE; ++k) {
         const int e = tid + k * 256;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (e < PATCH_CHUNKS) {
-            const int pix = e >> 3, ch = e & 7;
-            const int py = pix / 18, px = pix - py * 18;
-            const int y = y0 - 1 + py, x = x0 - 1 + px;
-            if (y >= 0 && y < H && x >= 0 && x < W)
-                v = reinterpret_cast<const uint4 *>(in + (img + (size_t)y * W + x) * CH)[ch];
-        }
-        pre[k] = v;
+        const int pix = e >> 3, ch = e & 7;
+        const int py = pix / CP_COLS, px = pix - py * CP_COLS;
+        const int y = y0 - 1 + py, x = x0 - 1 + px;
+        const bool ok = e < CP_CHUNKS && (unsigned)y < (unsigned)H && (unsigned)x < (unsigned)W;
+        const unsigned off = ok ? px_off(y * W + x, ch * 8) : OOB;
+        pre[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
     }
 }
 
@@ -122,7 +139,14 @@ __device__ __forceinline__ void patch_fetch(uint4 (&pre)[PRE], const uint16_t *_
 // 64 -> 64 convolution, persistent. MODE 0: out = relu(conv + bias), zero
 // outside the batch item's valid rectangle. MODE 1 (backward data): out =
 // conv * [mask_act > 0] (mask_act: the post-ReLU activation the gradient
-// flows into). 256 threads; blocks of 16 x 16 pixels, nbx x nby per item.
+// flows into). 256 threads; blocks of 32 x 16 pixels (nbx x nby per item,
+// the last block row may reach past H). Wave w computes block rows
+// 8w..8w+7 for all 64 output channels: 4 x 8 accumulator tiles (initialised
+// with the bias in MODE 0). The K loop runs as 18 steps (dx, kb, dy): the ten
+// patch rows of a (dx, kb) pair are loaded once and serve the three row taps,
+// and each step's fragments are loaded while the previous step's MFMAs run.
+// The results go through LDS (the patch area, swizzled) so that every lane
+// stores 16 contiguous bytes and a wave writes whole pixel rows.
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in, uint16_t *__restrict__ out,
@@ -130,79 +154,111 @@ __global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in,
                                                 const uint16_t *__restrict__ mask_act, CnnGeo geo, int H, int W,
                                                 int nbx, int nby, int nblocks) {
     extern __shared__ uint4 smem4[];
-    uint16_t *patch = reinterpret_cast<uint16_t *>(smem4);          // [18*18][PADC]
-    uint4 *wl = smem4 + (18 * 18 * PADC * 2) / 16;                   // [WPK]
-    float *bs = reinterpret_cast<float *>(wl + WPK);                 // [64]
+    uint16_t *patch = reinterpret_cast<uint16_t *>(smem4);                 // [34*18][PADC]
+    uint4 *wl = smem4 + (CP_ROWS * CP_COLS * PADC * 2) / 16;                // [WPK]
+    float *bs = reinterpret_cast<float *>(wl + WPK);                        // [64]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
     for (int e = tid; e < WPK; e += 256) wl[e] = wpk[e];
-    if (MODE == 0 && tid < CH) bs[tid] = bias[tid];
+    if (tid < CH) bs[tid] = MODE == 0 ? bias[tid] : 0.f;
     const BlockWalk walk(blockIdx.x, gridDim.x, nblocks);
-    uint4 pre[PRE];
-    if (walk.begin < walk.end) patch_fetch(pre, in, walk.begin, nbx, nby, H, W, tid);
+    uint4 pre[CPRE];
+    if (walk.begin < walk.end) conv_patch_fetch(pre, in, walk.begin, nbx, nby, H, W, tid);
     for (int blk = walk.begin; blk < walk.end; blk += walk.step) {
-        __syncthreads();   // the previous block's patch reads are done
+        __syncthreads();   // the previous block's patch and staging reads are done
 #pragma unroll
-        for (int k = 0; k < PRE; ++k) {
+        for (int k = 0; k < CPRE; ++k) {
             const int e = tid + k * 256;
-            if (e < PATCH_CHUNKS) *reinterpret_cast<uint4 *>(patch + (e >> 3) * PADC + (e & 7) * 8) = pre[k];
+            if (e < CP_CHUNKS) *reinterpret_cast<uint4 *>(patch + (e >> 3) * PADC + (e & 7) * 8) = pre[k];
         }
         __syncthreads();
-        if (blk + walk.step < walk.end) patch_fetch(pre, in, blk + walk.step, nbx, nby, H, W, tid);
-        floatx4 acc[4][4];
+        if (blk + walk.step < walk.end) conv_patch_fetch(pre, in, blk + walk.step, nbx, nby, H, W, tid);
+        floatx4 acc[4][8];
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi)
+        for (int mi = 0; mi < 4; ++mi) {
+            const float4 bb = *reinterpret_cast<const float4 *>(bs + mi * 16 + 4 * g);
 #pragma unroll
-            for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = floatx4{0.f, 0.f, 0.f, 0.f};
-        for (int t = 0; t < 9; ++t) {
-            const int dy = t / 3, dx = t - dy * 3;
+            for (int ni = 0; ni < 8; ++ni) acc[mi][ni] = floatx4{bb.x, bb.y, bb.z, bb.w};
+        }
+        const uint16_t *pw = patch + (wave * 8 * CP_COLS + j) * PADC + 8 * g;
+        bf16x8 bcur[10], bnext[10], acur[4], anext[4];
 #pragma unroll
-            for (int kb = 0; kb < 2; ++kb) {
-                bf16x8 a[4], bv[4];
+        for (int r = 0; r < 10; ++r) bcur[r] = as_bf16x8(*reinterpret_cast<const uint4 *>(pw + r * CP_COLS * PADC));
 #pragma unroll
-                for (int mi = 0; mi < 4; ++mi) a[mi] = as_bf16x8(wl[((t * 2 + kb) * 4 + mi) * 64 + lane]);
+        for (int mi = 0; mi < 4; ++mi) acur[mi] = as_bf16x8(wl[mi * 64 + lane]);
 #pragma unroll
-                for (int ni = 0; ni < 4; ++ni) {
-                    const int py = wave * 4 + ni + dy, px = j + dx;
-                    bv[ni] = as_bf16x8(
-                        *reinterpret_cast<const uint4 *>(patch + (py * 18 + px) * PADC + kb * 32 + 8 * g));
+        for (int st = 0; st < 18; ++st) {            // st = (2 dx + kb) * 3 + dy, tap t = 3 dy + dx
+            const int dy = st % 3;
+            if (st + 1 < 18) {
+                const int grp1 = (st + 1) / 3, dy1 = (st + 1) % 3, dx1 = grp1 / 2, kb1 = grp1 % 2;
+                const int t1 = dy1 * 3 + dx1;
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi) anext[mi] = as_bf16x8(wl[((t1 * 2 + kb1) * 4 + mi) * 64 + lane]);
+                if (dy == 2) {
+#pragma unroll
+                    for (int r = 0; r < 10; ++r)
+                        bnext[r] = as_bf16x8(
+                            *reinterpret_cast<const uint4 *>(pw + (r * CP_COLS + dx1) * PADC + kb1 * 32));
                 }
+            }
 #pragma unroll
-                for (int mi = 0; mi < 4; ++mi)
+            for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-                    for (int ni = 0; ni < 4; ++ni)
-                        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+                for (int ni = 0; ni < 8; ++ni)
+                    acc[mi][ni] =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(acur[mi], bcur[ni + dy], acc[mi][ni], 0, 0, 0);
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi) acur[mi] = anext[mi];
+            if (dy == 2) {
+#pragma unroll
+                for (int r = 0; r < 10; ++r) bcur[r] = bnext[r];
             }
         }
         int b, y0, x0;
-        block_origin(blk, nbx, nby, b, y0, x0);
-        const size_t img = (size_t)b * H * W;
+        block_origin(blk, nbx, nby, CB_ROWS, b, y0, x0);
+        const size_t img = (size_t)b * H * W * CH;
         const int4 vr = valid_rect(geo, b, H, W);
+        const bool x_in = x0 + j >= vr.z && x0 + j < vr.w;
+        const bool all_in = y0 >= vr.x && y0 + CB_ROWS <= vr.y && x0 >= vr.z && x0 + 16 <= vr.w;
+        __amdgpu_buffer_rsrc_t ms;
+        if (MODE == 1) ms = item_rsrc(mask_act + img, H, W);
+        __syncthreads();   // every wave is done with the patch: reuse it as staging
+        uint16_t *stg = patch + wave * (8 * 16 * 64);                      // [8 rows][16 px][64 ch], swizzled
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni) {
-            const int y = y0 + wave * 4 + ni, x = x0 + j;
-            const size_t pix = img + (size_t)y * W + x;
-            const bool inside = y >= vr.x && y < vr.y && x >= vr.z && x < vr.w;
+        for (int ni = 0; ni < 8; ++ni) {
+            const int y = y0 + wave * 8 + ni;
+            const bool inside = x_in && y >= vr.x && y < vr.y;
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi) {
-                const int c0 = mi * 16 + 4 * g;
-                uint2 mv = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
-                if (MODE == 1) mv = *reinterpret_cast<const uint2 *>(mask_act + pix * CH + c0);
-                const uint32_t m4[4] = {mv.x & 0xFFFFu, mv.x >> 16, mv.y & 0xFFFFu, mv.y >> 16};
-                uint32_t o[4];
+                float v[4];
+                if (MODE == 0) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float v = acc[mi][ni][r];
-                    if (MODE == 0) {
-                        v += bs[c0 + r];
-                        v = (v > 0.f && inside) ? v : 0.f;
-                    } else {
-                        v = m4[r] != 0 ? v : 0.f;     // post-ReLU activations are >= 0
-                    }
-                    o[r] = f2bf(v);
+                    for (int r = 0; r < 4; ++r) v[r] = (all_in || inside) ? fmaxf(acc[mi][ni][r], 0.f) : 0.f;
+                } else {
+                    // the gradient flows where the post-ReLU activation is > 0
+                    const unsigned off = y < H ? px_off(y * W + x0 + j, mi * 16 + 4 * g) : OOB;
+                    const uint2 mv = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(ms, off, 0, 0));
+                    const int16_t m4[4] = {(int16_t)(mv.x & 0xFFFFu), (int16_t)(mv.x >> 16),
+                                           (int16_t)(mv.y & 0xFFFFu), (int16_t)(mv.y >> 16)};
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] = m4[r] > 0 ? acc[mi][ni][r] : 0.f;
                 }
-                *reinterpret_cast<uint2 *>(out + pix * CH + c0) = make_uint2(o[0] | (o[1] << 16), o[2] | (o[3] << 16));
+                const bf16x2 lo = {(__bf16)v[0], (__bf16)v[1]}, hi = {(__bf16)v[2], (__bf16)v[3]};
+                // pixel (ni, j), channels 16 mi + 4 g .. +3: 16-byte chunk 2 mi + g/2, swizzled by pixel
+                const int q = (2 * mi + (g >> 1)) ^ (j & 7);
+                *reinterpret_cast<uint2 *>(stg + (ni * 16 + j) * 64 + q * 8 + (g & 1) * 4) =
+                    make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
             }
+        }
+        const __amdgpu_buffer_rsrc_t os = item_rsrc(out + img, H, W);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int c = k * 64 + lane;                 // chunk of [8 rows][16 px][8 chunks]
+            const int ni = c >> 7, px = (c >> 3) & 15, q = c & 7;
+            const int y = y0 + wave * 8 + ni;
+            const uint4 v = *reinterpret_cast<const uint4 *>(stg + (ni * 16 + px) * 64 + ((q ^ (px & 7)) * 8));
+            const unsigned off = y < H ? px_off(y * W + x0 + px, q * 8) : OOB;
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), os, off, 0, 0);
         }
     }
 }
@@ -341,7 +397,7 @@ __global__ void __launch_bounds__(256) k_out_backward(const float *__restrict__ 
             float v = 0.f;
 #pragma unroll
             for (int t = 0; t < 9; ++t) v += ws[(c8 + e) * 9 + t] * gg[t];
-            o[e] = ac[c8 + e] != 0 ? f2bf(v) : 0u;
+            o[e] = (int16_t)ac[c8 + e] > 0 ? f2bf(v) : 0u;
         }
         *reinterpret_cast<uint4 *>(dst + c8) =
             make_uint4(o[0] | (o[1] << 16), o[2] | (o[3] << 16), o[4] | (o[5] << 16), o[6] | (o[7] << 16));
@@ -382,7 +438,7 @@ __global__ void __launch_bounds__(256) k_dw64(const uint16_t *__restrict__ dpre,
     const BlockWalk walk(blockIdx.x, gridDim.x, nblocks);
     for (int blk = walk.begin; blk < walk.end; blk += walk.step) {
         int b, y0, x0;
-        block_origin(blk, nbx, nby, b, y0, x0);
+        block_origin(blk, nbx, nby, 16, b, y0, x0);
         const size_t img = (size_t)b * H * W;
         __syncthreads();
         for (int e = tid; e < 256 * 8; e += 256) {
@@ -586,7 +642,7 @@ void *cnn_alloc(ri_cnn *n, size_t bytes) {
     return p;
 }
 
-size_t conv64_lds() { return (size_t)18 * 18 * PADC * 2 + (size_t)WPK * 16 + CH * 4; }
+size_t conv64_lds() { return (size_t)CP_ROWS * CP_COLS * PADC * 2 + (size_t)WPK * 16 + CH * 4; }
 size_t convout_lds() { return (size_t)18 * 18 * PADC * 2 + 9 * CH * 4; }
 size_t outbwd_lds() { return (size_t)18 * 18 * PADC * 2 + 18 * 18 * 4 + CH * 9 * 4 + 16; }
 size_t dw64_lds() { return ((size_t)CH * DT_STRIDE + 3 * CH * AT_STRIDE) * 2 + 256 * 4; }
@@ -611,7 +667,7 @@ int persistent_grid(const ri_cnn *n, int nblocks) {
 // or the ping-pong pair act[0], act[1] (inference).
 void forward(ri_cnn *n, const float *z, float *D, int B, int h, int w, const CnnGeo &geo, hipStream_t s) {
     dim3 grid(w / 16, h / 16, B);
-    const int L = n->L, nbx = w / 16, nby = h / 16, nb = nbx * nby * B;
+    const int L = n->L, nbx = w / 16, nby = (h + CB_ROWS - 1) / CB_ROWS, nb = nbx * nby * B;
     auto A = [&](int l) { return n->training ? n->act[l] : n->act[l & 1]; };
     hipLaunchKernelGGL(k_conv_in, grid, dim3(256), 0, s, z, A(0), n->params + n->off[0], n->params + n->off[1], geo,
                        h, w);
@@ -633,15 +689,16 @@ void backward(ri_cnn *n, const float *z, const float *g, int B, int h, int w, hi
                        n->params + n->off[2 * (L - 1)], n->dpre[0], n->grads + n->off[2 * (L - 1)],
                        n->grads + n->off[2 * (L - 1) + 1], h, w);
     int cur = 0;
-    const int nbx = w / 16, nby = h / 16, nb = nbx * nby * B;
+    const int nbx = w / 16, nby = h / 16, nb = nbx * nby * B;                  // 16 x 16 blocks (weight gradients)
+    const int cby = (h + CB_ROWS - 1) / CB_ROWS, cnb = nbx * cby * B;         // 32 x 16 blocks (convolutions)
     const CnnGeo full;
     for (int l = L - 2; l >= 1; --l) {
         hipLaunchKernelGGL(k_dw64, dim3(persistent_grid(n, nb)), dim3(256), dw64_lds(), s, n->dpre[cur],
                            n->act[l - 1], n->grads + n->off[2 * l], n->grads + n->off[2 * l + 1], h, w, nbx, nby, nb);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<1>), dim3(persistent_grid(n, nb)), dim3(256), conv64_lds(), s,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<1>), dim3(persistent_grid(n, cnb)), dim3(256), conv64_lds(), s,
                            n->dpre[cur], n->dpre[cur ^ 1],
                            reinterpret_cast<const uint4 *>(n->wbwd + (size_t)(l - 1) * WPK * 8),
-                           (const float *)nullptr, n->act[l - 1], full, h, w, nbx, nby, nb);
+                           (const float *)nullptr, n->act[l - 1], full, h, w, nbx, cby, cnb);
         cur ^= 1;
     }
     hipLaunchKernelGGL(k_dw_in, grid, dim3(256), 0, s, z, n->dpre[cur], n->grads + n->off[0], n->grads + n->off[1],
@@ -678,8 +735,9 @@ void offsets_for(int L, std::vector<int64_t> &off, std::vector<float> *stds) {
 
 ri_cnn *create(const ri_cnn_desc &d, uint64_t seed) {
     if (d.layers < 3 || d.layers > 64 || d.channels != CH || d.max_batch < 1 || d.max_h < 16 || d.max_w < 16 ||
-        d.max_h % 16 || d.max_w % 16 || d.max_h > 8192 || d.max_w > 8192)
-        throw Error(RI_EINVAL, "CNN: 3 <= layers <= 64, channels == 64, sides multiples of 16 in 16..8192");
+        d.max_h % 16 || d.max_w % 16 || (int64_t)d.max_h * d.max_w > (int64_t)4096 * 4096)
+        throw Error(RI_EINVAL, "CNN: 3 <= layers <= 64, channels == 64, sides multiples of 16, "
+                               "at most 4096 x 4096 pixels per image");
     int dev = 0;
     RI_CHECK_HIP(hipGetDevice(&dev));
     hipDeviceProp_t prop;

@@ -92,6 +92,16 @@ __global__ void k_pack(const float *__restrict__ w, uint16_t *__restrict__ fwd, 
     bwd[idx] = f2bf(w[(k * CH + r) * 9 + (8 - t)]);
 }
 
+// Output-layer weights as a zero-padded 16-row MFMA A operand (rows = taps):
+// chunk kb * 64 + lane, element e: bf16(W[0][c = 32 kb + 8(lane/16) + e][t = lane%16]), 0 for t >= 9.
+__global__ void k_pack_proj(const float *__restrict__ w, uint16_t *__restrict__ proj) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 2 * 64 * 8) return;
+    const int e = idx & 7, lane = (idx >> 3) & 63, kb = idx >> 9;
+    const int t = lane & 15, c = kb * 32 + 8 * (lane >> 4) + e;
+    proj[idx] = t < 9 ? f2bf(w[c * 9 + t]) : (uint16_t)0;
+}
+
 __device__ __forceinline__ void block_origin(int blk, int nbx, int nby, int rows, int &b, int &y0, int &x0) {
     b = blk / (nbx * nby);
     const int rem = blk - b * nbx * nby, by = rem / nbx;
@@ -135,6 +145,18 @@ __device__ __forceinline__ void conv_patch_fetch(uint4 (&pre)[CPRE], const uint1
     }
 }
 
+// Scheduling hint for a K step of 32 MFMAs that also loads NRD fragments of
+// the next step: alternate MFMA and LDS read, then the remaining MFMAs.
+template <int NRD>
+__device__ __forceinline__ void sched_interleave() {
+#pragma unroll
+    for (int k = 0; k < NRD; ++k) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 32 - NRD, 0);
+}
+
 // ---------------------------------------------------------------------------
 // 64 -> 64 convolution, persistent. MODE 0: out = relu(conv + bias), zero
 // outside the batch item's valid rectangle. MODE 1 (backward data): out =
@@ -152,7 +174,8 @@ template <int MODE>
 __global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in, uint16_t *__restrict__ out,
                                                 const uint4 *__restrict__ wpk, const float *__restrict__ bias,
                                                 const uint16_t *__restrict__ mask_act, CnnGeo geo, int H, int W,
-                                                int nbx, int nby, int nblocks) {
+                                                int nbx, int nby, int nblocks, const uint4 *__restrict__ wproj,
+                                                float *__restrict__ S, int64_t plane) {
     extern __shared__ uint4 smem4[];
     uint16_t *patch = reinterpret_cast<uint16_t *>(smem4);                 // [34*18][PADC]
     uint4 *wl = smem4 + (CP_ROWS * CP_COLS * PADC * 2) / 16;                // [WPK]
@@ -160,7 +183,7 @@ __global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in,
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
     for (int e = tid; e < WPK; e += 256) wl[e] = wpk[e];
-    if (tid < CH) bs[tid] = MODE == 0 ? bias[tid] : 0.f;
+    if (tid < CH) bs[tid] = MODE != 1 ? bias[tid] : 0.f;
     const BlockWalk walk(blockIdx.x, gridDim.x, nblocks);
     uint4 pre[CPRE];
     if (walk.begin < walk.end) conv_patch_fetch(pre, in, walk.begin, nbx, nby, H, W, tid);
@@ -207,6 +230,11 @@ __global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in,
                 for (int ni = 0; ni < 8; ++ni)
                     acc[mi][ni] =
                         __builtin_amdgcn_mfma_f32_16x16x32_bf16(acur[mi], bcur[ni + dy], acc[mi][ni], 0, 0, 0);
+            // scheduling: one LDS read of the next step's fragments after each MFMA
+            if (st + 1 < 18) {
+                if (dy == 2) sched_interleave<14>();
+                else sched_interleave<4>();
+            }
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi) acur[mi] = anext[mi];
             if (dy == 2) {
@@ -231,7 +259,7 @@ __global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in,
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi) {
                 float v[4];
-                if (MODE == 0) {
+                if (MODE != 1) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) v[r] = (all_in || inside) ? fmaxf(acc[mi][ni][r], 0.f) : 0.f;
                 } else {
@@ -250,6 +278,30 @@ __global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in,
                     make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
             }
         }
+        __builtin_amdgcn_wave_barrier();   // the wave reads back what its other lanes staged
+        if (MODE == 2) {
+            // last hidden layer: project the block's activations onto the nine
+            // taps of the 64 -> 1 output layer, s_t[p] = sum_c W[c][t] act[p][c]
+            // (MFMA rows t < 9 of a zero-padded 16-row A), instead of storing them
+            const bf16x8 ap0 = as_bf16x8(wproj[lane]), ap1 = as_bf16x8(wproj[64 + lane]);
+#pragma unroll
+            for (int ni = 0; ni < 8; ++ni) {
+                const int y = y0 + wave * 8 + ni;
+                const uint16_t *sp = stg + (ni * 16 + j) * 64;
+                const bf16x8 b0 = as_bf16x8(*reinterpret_cast<const uint4 *>(sp + ((g ^ (j & 7)) * 8)));
+                const bf16x8 b1 = as_bf16x8(*reinterpret_cast<const uint4 *>(sp + (((4 + g) ^ (j & 7)) * 8)));
+                floatx4 pr = floatx4{0.f, 0.f, 0.f, 0.f};
+                pr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap0, b0, pr, 0, 0, 0);
+                pr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap1, b1, pr, 0, 0, 0);
+                if (y < H) {
+                    float *sq = S + (size_t)b * H * W + (size_t)y * W + x0 + j;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (4 * g + r < 9) sq[(size_t)(4 * g + r) * plane] = pr[r];
+                }
+            }
+            continue;
+        }
         const __amdgpu_buffer_rsrc_t os = item_rsrc(out + img, H, W);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
@@ -263,12 +315,15 @@ __global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in,
     }
 }
 
-// First layer: FP32 input, FP32 weights W0[64][9], bias; relu, valid mask, bfloat16 out.
+// First layer: FP32 input, FP32 weights W0[64][9], bias; relu, valid mask,
+// bfloat16 out. A 16 x 16 block in eight passes of 32 pixels; thread t
+// computes channels 8 (t % 8) .. +7 of one pixel, so a wave stores eight
+// whole pixels (1 KB contiguous).
 __global__ void __launch_bounds__(256) k_conv_in(const float *__restrict__ z, uint16_t *__restrict__ out,
                                                  const float *__restrict__ w0, const float *__restrict__ b0,
                                                  CnnGeo geo, int H, int W) {
     __shared__ float zp[18][18];
-    __shared__ float ws[CH * 9];
+    __shared__ float ws[9][CH];
     __shared__ float bs[CH];
     const int b = blockIdx.z, y0 = blockIdx.y * 16, x0 = blockIdx.x * 16, tid = threadIdx.x;
     const size_t img = (size_t)b * H * W;
@@ -276,27 +331,39 @@ __global__ void __launch_bounds__(256) k_conv_in(const float *__restrict__ z, ui
         const int py = e / 18, px = e - py * 18, y = y0 - 1 + py, x = x0 - 1 + px;
         zp[py][px] = (y >= 0 && y < H && x >= 0 && x < W) ? z[img + (size_t)y * W + x] : 0.f;
     }
-    for (int e = tid; e < CH * 9; e += 256) ws[e] = w0[e];
+    for (int e = tid; e < CH * 9; e += 256) ws[e % 9][e / 9] = w0[e];
     if (tid < CH) bs[tid] = b0[tid];
     __syncthreads();
-    const int ty = tid >> 4, tx = tid & 15, y = y0 + ty, x = x0 + tx;
     const int4 vr = valid_rect(geo, b, H, W);
-    const bool inside = y >= vr.x && y < vr.y && x >= vr.z && x < vr.w;
-    float zz[9];
+    const int q = tid & 7;
+    float wr[9][8], br[8];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) zz[t] = zp[ty + t / 3][tx + t % 3];
-    uint16_t *dst = out + (img + (size_t)y * W + x) * CH;
-    for (int c8 = 0; c8 < CH; c8 += 8) {
-        uint32_t o[8];
+    for (int t = 0; t < 9; ++t)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            float v = bs[c8 + e];
+        for (int e = 0; e < 8; ++e) wr[t][e] = ws[t][8 * q + e];
 #pragma unroll
-            for (int t = 0; t < 9; ++t) v += ws[(c8 + e) * 9 + t] * zz[t];
-            o[e] = f2bf((v > 0.f && inside) ? v : 0.f);
+    for (int e = 0; e < 8; ++e) br[e] = bs[8 * q + e];
+#pragma unroll 2
+    for (int pass = 0; pass < 8; ++pass) {
+        const int p = pass * 32 + (tid >> 3), ty = p >> 4, tx = p & 15, y = y0 + ty, x = x0 + tx;
+        const bool inside = y >= vr.x && y < vr.y && x >= vr.z && x < vr.w;
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = br[e];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const float zz = zp[ty + t / 3][tx + t % 3];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] += wr[t][e] * zz;
         }
-        *reinterpret_cast<uint4 *>(dst + c8) =
-            make_uint4(o[0] | (o[1] << 16), o[2] | (o[3] << 16), o[4] | (o[5] << 16), o[6] | (o[7] << 16));
+        uint32_t o[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const bf16x2 pr = {(__bf16)(inside ? fmaxf(v[2 * e], 0.f) : 0.f),
+                               (__bf16)(inside ? fmaxf(v[2 * e + 1], 0.f) : 0.f)};
+            o[e] = __builtin_bit_cast(uint32_t, pr);
+        }
+        *reinterpret_cast<uint4 *>(out + (img + (size_t)y * W + x) * CH + 8 * q) = make_uint4(o[0], o[1], o[2], o[3]);
     }
 }
 
@@ -345,6 +412,24 @@ __global__ void __launch_bounds__(256) k_conv_out(const uint16_t *__restrict__ a
     }
     const size_t o = img + (size_t)(y0 + ty) * W + x0 + tx;
     D[o] = z[o] - acc;
+}
+
+// Output layer from the tap projections: D = z - (b + sum_t s_t[p + (t - centre)]).
+__global__ void k_conv_sum(const float *__restrict__ S, const float *__restrict__ z, float *__restrict__ D,
+                           const float *__restrict__ bl, int B, int H, int W) {
+    const int64_t plane = (int64_t)B * H * W;
+    const float b0 = bl[0];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < plane; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t item = i / ((int64_t)H * W);
+        const int r = (int)(i - item * H * W), y = r / W, x = r - y * W;
+        float acc = b0;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W) acc += S[t * plane + item * H * W + (int64_t)yy * W + xx];
+        }
+        D[i] = z[i] - acc;
+    }
 }
 
 // l1 loss gradient with respect to net(z): g = -sign(D - u) / numel; partials of mean|D - u|.
@@ -621,6 +706,8 @@ struct ri_cnn {
     std::vector<int64_t> off;          // [2L+1]: weight, bias offsets of each layer
     float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
     uint16_t *wfwd = nullptr, *wbwd = nullptr;   // packed hidden layers [L-2][WPK*8]
+    uint16_t *wproj = nullptr;         // output layer as an MFMA operand [2][64][8]
+    float *S = nullptr;                // inference: tap projections of the last hidden layer [9][pixels]
     std::vector<uint16_t *> act;       // training: L-1 activation buffers; inference: 2
     uint16_t *dpre[2] = {nullptr, nullptr};
     float *D = nullptr, *g = nullptr, *zin = nullptr;
@@ -656,6 +743,7 @@ void repack(ri_cnn *n, hipStream_t s) {
     for (int l = 1; l <= n->L - 2; ++l)
         hipLaunchKernelGGL(k_pack, dim3((WPK * 8 + 255) / 256), dim3(256), 0, s, n->params + n->off[2 * l],
                            n->wfwd + (size_t)(l - 1) * WPK * 8, n->wbwd + (size_t)(l - 1) * WPK * 8);
+    hipLaunchKernelGGL(k_pack_proj, dim3(4), dim3(256), 0, s, n->params + n->off[2 * (n->L - 1)], n->wproj);
 }
 
 int persistent_grid(const ri_cnn *n, int nblocks) {
@@ -663,20 +751,35 @@ int persistent_grid(const ri_cnn *n, int nblocks) {
     return g >= N_XCD ? g - g % N_XCD : g;
 }
 
-// Forward through all layers; hidden activations into act[0..L-2] (training)
-// or the ping-pong pair act[0], act[1] (inference).
+// Forward through all layers. Training: hidden activations into act[0..L-2],
+// then the output layer reads act[L-2]. Inference: ping-pong act[0], act[1];
+// the last hidden layer is not stored but projected onto the output layer's
+// nine taps inside its kernel, and a stencil pass forms D.
 void forward(ri_cnn *n, const float *z, float *D, int B, int h, int w, const CnnGeo &geo, hipStream_t s) {
     dim3 grid(w / 16, h / 16, B);
     const int L = n->L, nbx = w / 16, nby = (h + CB_ROWS - 1) / CB_ROWS, nb = nbx * nby * B;
+    const int64_t plane = (int64_t)B * h * w;
     auto A = [&](int l) { return n->training ? n->act[l] : n->act[l & 1]; };
     hipLaunchKernelGGL(k_conv_in, grid, dim3(256), 0, s, z, A(0), n->params + n->off[0], n->params + n->off[1], geo,
                        h, w);
-    for (int l = 1; l <= L - 2; ++l)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<0>), dim3(persistent_grid(n, nb)), dim3(256), conv64_lds(), s,
-                           A(l - 1), A(l), reinterpret_cast<const uint4 *>(n->wfwd + (size_t)(l - 1) * WPK * 8),
-                           n->params + n->off[2 * l + 1], (const uint16_t *)nullptr, geo, h, w, nbx, nby, nb);
-    hipLaunchKernelGGL(k_conv_out, grid, dim3(256), convout_lds(), s, A(L - 2), z, D,
-                       n->params + n->off[2 * (L - 1)], n->params + n->off[2 * (L - 1) + 1], h, w);
+    for (int l = 1; l <= L - 2; ++l) {
+        const uint4 *wl = reinterpret_cast<const uint4 *>(n->wfwd + (size_t)(l - 1) * WPK * 8);
+        if (n->training || l < L - 2)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<0>), dim3(persistent_grid(n, nb)), dim3(256), conv64_lds(), s,
+                               A(l - 1), A(l), wl, n->params + n->off[2 * l + 1], (const uint16_t *)nullptr, geo, h,
+                               w, nbx, nby, nb, (const uint4 *)nullptr, (float *)nullptr, plane);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<2>), dim3(persistent_grid(n, nb)), dim3(256), conv64_lds(), s,
+                               A(l - 1), (uint16_t *)nullptr, wl, n->params + n->off[2 * l + 1],
+                               (const uint16_t *)nullptr, geo, h, w, nbx, nby, nb,
+                               reinterpret_cast<const uint4 *>(n->wproj), n->S, plane);
+    }
+    if (n->training)
+        hipLaunchKernelGGL(k_conv_out, grid, dim3(256), convout_lds(), s, A(L - 2), z, D,
+                           n->params + n->off[2 * (L - 1)], n->params + n->off[2 * (L - 1) + 1], h, w);
+    else
+        hipLaunchKernelGGL(k_conv_sum, dim3(std::min<int64_t>((plane + 255) / 256, 8192)), dim3(256), 0, s, n->S, z,
+                           D, n->params + n->off[2 * (L - 1) + 1], B, h, w);
     RI_CHECK_HIP(hipGetLastError());
 }
 
@@ -698,7 +801,8 @@ void backward(ri_cnn *n, const float *z, const float *g, int B, int h, int w, hi
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<1>), dim3(persistent_grid(n, cnb)), dim3(256), conv64_lds(), s,
                            n->dpre[cur], n->dpre[cur ^ 1],
                            reinterpret_cast<const uint4 *>(n->wbwd + (size_t)(l - 1) * WPK * 8),
-                           (const float *)nullptr, n->act[l - 1], full, h, w, nbx, cby, cnb);
+                           (const float *)nullptr, n->act[l - 1], full, h, w, nbx, cby, cnb, (const uint4 *)nullptr,
+                           (float *)nullptr, (int64_t)0);
         cur ^= 1;
     }
     hipLaunchKernelGGL(k_dw_in, grid, dim3(256), 0, s, z, n->dpre[cur], n->grads + n->off[0], n->grads + n->off[1],
@@ -757,12 +861,14 @@ ri_cnn *create(const ri_cnn_desc &d, uint64_t seed) {
         n->params = (float *)cnn_alloc(n, sizeof(float) * n->P);
         n->wfwd = (uint16_t *)cnn_alloc(n, sizeof(uint16_t) * (size_t)(n->L - 2) * WPK * 8);
         n->wbwd = (uint16_t *)cnn_alloc(n, sizeof(uint16_t) * (size_t)(n->L - 2) * WPK * 8);
+        n->wproj = (uint16_t *)cnn_alloc(n, sizeof(uint16_t) * 2 * 64 * 8);
         const size_t npix = (size_t)n->maxB * n->maxH * n->maxW;
         const int nact = n->training ? n->L - 1 : 2;
         for (int i = 0; i < nact; ++i) n->act.push_back((uint16_t *)cnn_alloc(n, sizeof(uint16_t) * npix * CH));
         n->D = (float *)cnn_alloc(n, sizeof(float) * npix);
         n->zin = (float *)cnn_alloc(n, sizeof(float) * npix);
         n->part = (double *)cnn_alloc(n, sizeof(double) * 1024);
+        if (!n->training) n->S = (float *)cnn_alloc(n, sizeof(float) * 9 * npix);
         if (n->training) {
             n->grads = (float *)cnn_alloc(n, sizeof(float) * n->P);
             n->dpre[0] = (uint16_t *)cnn_alloc(n, sizeof(uint16_t) * npix * CH);

@@ -32,6 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # FP32 vector peak without packed FP32 instructions (the build disables them):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 FP32_VALU_PEAK_TFS = 78.6
+BF16_PEAK_TFS = 2500.0       # dense BF16 MFMA (no sparsity)
 
 
 def log(msg: str):
@@ -198,6 +199,9 @@ def run_pnp(args, R, synth, ctx, noise, x_true, L):
            "pnp_snr_at": {str(k): round(float(tr[k - 1, 2]), 3) for k in marks if k <= rep.iters},
            "fb_snr_at": {str(k): round(float(fb_tr[k - 1, 2]), 3) for k in marks if k <= fb_rep.iters},
            "denoiser_ms": den_ms, "denoiser_tflops": den_tfs, "denoiser_tiles": nf, "denoiser_tile_side": side,
+           "denoiser_roofline": {"bound": "mfma", "achieved": den_tfs, "peak": BF16_PEAK_TFS, "unit": "TFLOP/s",
+                                 "frac": den_tfs / BF16_PEAK_TFS, "flops_per_application": cnn_flops(nf * side * side),
+                                 "kernels": "k_conv_in, 7 x k_conv64<0>, k_conv64<2>, k_conv_sum (one application)"},
            "train_steps": args.train_steps, "train_batch": args.train_batch, "train_s": train_s,
            "train_tflops": train_flops / train_s / 1e12, "train_final_loss": hist[-1][1] if hist else None}
     log(f"PnP x{rep.iters}: {rep.ms:.1f} ms ({res['pnp_ms_per_iter']:.3f} ms/it), SNR {rep.snr_db:.2f} dB vs FB "
@@ -223,8 +227,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the FB time-to-SNR run")
     ap.add_argument("--fb-iters", type=int, default=300)
     ap.add_argument("--no-pnp", action="store_true", help="skip the denoiser training and the PnP-FB run")
-    ap.add_argument("--pnp-iters", type=int, default=300)
-    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--pnp-iters", type=int, default=500)
+    ap.add_argument("--train-steps", type=int, default=12000)
     ap.add_argument("--train-lr", type=float, default=1e-4)
     ap.add_argument("--pnp-sigma", type=float, default=1e-4,
                     help="image-domain noise level of the PnP comparison (1 / target dynamic range)")
@@ -232,6 +236,8 @@ def main():
     ap.add_argument("--train-patches", type=int, default=1024)
     ap.add_argument("--facet-core", type=int, default=0, help="CNN facet core side (0: whole image in one tile)")
     ap.add_argument("--facet-halo", type=int, default=32)
+    ap.add_argument("--denoiser-only", action="store_true",
+                    help="only time the CNN denoiser on one whole image of the workload (for profiling) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -245,6 +251,30 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        return
+
+    if args.denoiser_only:
+        import torch
+
+        import paper_2207_11336_amd.ri as R
+        import synth
+        wl = synth.WORKLOADS[args.workload]
+        net = R.ri_cnn_create(layers=10, max_batch=1, max_h=wl.N, max_w=wl.N, seed=synth.SEED_TRAIN)
+        z = torch.tensor(synth.sky(wl.N), dtype=torch.float32, device="cuda:0")[None].contiguous()
+        out = torch.empty_like(z)
+        for _ in range(max(1, args.warmup)):
+            R.ri_cnn_forward(net, z, out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            R.ri_cnn_forward(net, z, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        fl = cnn_flops(wl.N * wl.N)
+        print(json.dumps({"denoiser_forward_ms": ms, "pixels": wl.N * wl.N, "flops": fl,
+                          "tflops": fl / ms / 1e9, "frac_of_bf16_peak": fl / ms / 1e9 / BF16_PEAK_TFS}))
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -451,10 +451,11 @@ __global__ void k_l1(const float *__restrict__ D, const float *__restrict__ u, f
 }
 
 // Backward of the last layer. dpre[p][c] = [act[p][c] > 0] sum_t bf16(W[0][c][t]) g[p - (t - centre)];
-// dW[c][t] += sum_p act[p + (t - centre)][c] g[p]; db += sum_p g[p].
+// this block's share of dW[c][t] = sum_p act[p + (t - centre)][c] g[p] and db = sum_p g[p] goes to
+// row `block` of part (577 floats), summed over blocks by k_reduce_rows.
 __global__ void __launch_bounds__(256) k_out_backward(const float *__restrict__ g, const uint16_t *__restrict__ act,
                                                       const float *__restrict__ wl_, uint16_t *__restrict__ dpre,
-                                                      float *__restrict__ dW, float *__restrict__ db, int H, int W) {
+                                                      float *__restrict__ part, int H, int W) {
     extern __shared__ uint4 smem4[];
     uint16_t *patch = reinterpret_cast<uint16_t *>(smem4);          // act patch [18*18][PADC]
     float *gp = reinterpret_cast<float *>(patch + 18 * 18 * PADC);  // g patch [18][18]
@@ -462,6 +463,7 @@ __global__ void __launch_bounds__(256) k_out_backward(const float *__restrict__ 
     float *red = ws + CH * 9;                                       // [4]
     const int b = blockIdx.z, y0 = blockIdx.y * 16, x0 = blockIdx.x * 16, tid = threadIdx.x;
     const size_t img = (size_t)b * H * W;
+    float *prow = part + ((size_t)(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * (CH * 9 + 1);
     load_patch_lds(patch, act, img, y0, x0, H, W, tid);
     for (int e = tid; e < 18 * 18; e += 256) {
         const int py = e / 18, px = e - py * 18, y = y0 - 1 + py, x = x0 - 1 + px;
@@ -493,22 +495,23 @@ __global__ void __launch_bounds__(256) k_out_backward(const float *__restrict__ 
         for (int py = 0; py < 16; ++py)
             for (int px = 0; px < 16; ++px)
                 s += bf2f(patch[((py + dy) * 18 + px + dx) * PADC + c]) * gp[(py + 1) * 18 + px + 1];
-        atomicAdd(&dW[pr], s);
+        prow[pr] = s;
     }
     float sg = gp[(ty + 1) * 18 + tx + 1];
     for (int o = 32; o >= 1; o >>= 1) sg += __shfl_xor(sg, o);
     if ((tid & 63) == 0) red[tid >> 6] = sg;
     __syncthreads();
-    if (tid == 0) atomicAdd(db, red[0] + red[1] + red[2] + red[3]);
+    if (tid == 0) prow[CH * 9] = red[0] + red[1] + red[2] + red[3];
 }
 
 // Weight and bias gradients of a 64 -> 64 layer:
 //   dW[o][c][t] += sum_p dpre[p][o] act[p + (t - centre)][c],  db[o] += sum_p dpre[p][o].
 // A workgroup walks 16x16 pixel blocks and accumulates all 9 x 64 x 64
 // outputs in MFMA accumulators (wave w: output channels 16w..16w+15).
+constexpr int DW_PART = 9 * 4 * 4 * 256 + 64;    // per-workgroup partials: accumulators + bias sums
+
 __global__ void __launch_bounds__(256) k_dw64(const uint16_t *__restrict__ dpre, const uint16_t *__restrict__ act,
-                                              float *__restrict__ dW, float *__restrict__ db, int H, int W,
-                                              int nbx, int nby, int nblocks) {
+                                              float *__restrict__ part, int H, int W, int nbx, int nby, int nblocks) {
     extern __shared__ uint4 smem4[];
     uint16_t *dT = reinterpret_cast<uint16_t *>(smem4);   // [64][DT_STRIDE]   dpre transposed
     uint16_t *aT = dT + CH * DT_STRIDE;                   // [3][64][AT_STRIDE] act transposed, shifted by dx
@@ -577,23 +580,43 @@ __global__ void __launch_bounds__(256) k_dw64(const uint16_t *__restrict__ dpre,
             }
         }
     }
+    // this workgroup's partial sums, in accumulator order (coalesced; reduced by k_dw64_reduce)
+    float *pp = part + (size_t)blockIdx.x * DW_PART;
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int n = 0; n < 4; ++n)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int o = wave * 16 + 4 * g + r, c = n * 16 + j;
-                atomicAdd(&dW[(o * CH + c) * 9 + t], acc[t][n][r]);
-            }
+            for (int r = 0; r < 4; ++r) pp[((t * 4 + n) * 4 + r) * 256 + tid] = acc[t][n][r];
     red[tid] = bsum;
     __syncthreads();
-    if (tid < 64) atomicAdd(&db[tid], red[tid] + red[tid + 64] + red[tid + 128] + red[tid + 192]);
+    if (tid < CH) pp[9 * 4 * 4 * 256 + tid] = red[tid] + red[tid + 64] + red[tid + 128] + red[tid + 192];
 }
 
-// Weight and bias gradients of the first layer: dW0[c][t] += sum_p z[p + (t - centre)] dpre[p][c].
+// dW[o][c][t] and db[o] from the per-workgroup partials of k_dw64, in a fixed order.
+__global__ void k_dw64_reduce(const float *__restrict__ part, int nwg, float *__restrict__ dW, float *__restrict__ db) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 9 * 4 * 4 * 256 + CH) return;
+    float s8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};      // eight independent loads in flight
+    int w = 0;
+    for (; w + 8 <= nwg; w += 8)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s8[k] += part[(size_t)(w + k) * DW_PART + e];
+    for (; w < nwg; ++w) s8[0] += part[(size_t)w * DW_PART + e];
+    const float s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+    if (e < 9 * 4 * 4 * 256) {
+        const int tid = e & 255, r = (e >> 8) & 3, n = (e >> 10) & 3, t = e >> 12;
+        const int wave = tid >> 6, lane = tid & 63, o = wave * 16 + 4 * (lane >> 4) + r, c = n * 16 + (lane & 15);
+        dW[(o * CH + c) * 9 + t] = s;
+    } else {
+        db[e - 9 * 4 * 4 * 256] = s;
+    }
+}
+
+// Weight and bias gradients of the first layer, this block's share: dW0[c][t] = sum_p z[p + (t - centre)]
+// dpre[p][c] and db0[c] = sum_p dpre[p][c] into row `block` of part (640 floats, parameter order).
 __global__ void __launch_bounds__(256) k_dw_in(const float *__restrict__ z, const uint16_t *__restrict__ dpre,
-                                               float *__restrict__ dW, float *__restrict__ db, int H, int W) {
+                                               float *__restrict__ part, int H, int W) {
     __shared__ float zp[18][18];
     __shared__ uint16_t dp[256][CH + 2];
     const int b = blockIdx.z, y0 = blockIdx.y * 16, x0 = blockIdx.x * 16, tid = threadIdx.x;
@@ -612,13 +635,25 @@ __global__ void __launch_bounds__(256) k_dw_in(const float *__restrict__ z, cons
         if (pr < CH * 9) {
             const int c = pr / 9, t = pr - c * 9, dy = t / 3, dx = t % 3;
             for (int p = 0; p < 256; ++p) s += zp[(p >> 4) + dy][(p & 15) + dx] * bf2f(dp[p][c]);
-            atomicAdd(&dW[pr], s);
         } else {
             const int c = pr - CH * 9;
             for (int p = 0; p < 256; ++p) s += bf2f(dp[p][c]);
-            atomicAdd(&db[c], s);
         }
+        part[((size_t)(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * (CH * 9 + CH) + pr] = s;
     }
+}
+
+// out[e] = sum over rows r < nrows of part[r * stride + e], e < count (fixed order).
+__global__ void k_reduce_rows(const float *__restrict__ part, int nrows, int stride, int count, float *__restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    float s8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int r = 0;
+    for (; r + 8 <= nrows; r += 8)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s8[k] += part[(size_t)(r + k) * stride + e];
+    for (; r < nrows; ++r) s8[0] += part[(size_t)r * stride + e];
+    out[e] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
 }
 
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ gr, float *__restrict__ m,
@@ -711,6 +746,8 @@ struct ri_cnn {
     std::vector<uint16_t *> act;       // training: L-1 activation buffers; inference: 2
     uint16_t *dpre[2] = {nullptr, nullptr};
     float *D = nullptr, *g = nullptr, *zin = nullptr;
+    float *dwpart = nullptr;           // training: per-workgroup weight-gradient partials
+    float *blkpart = nullptr;          // training: per-block partials of the first / last layer
     double *part = nullptr;
     int64_t step = 0;
     std::string err;
@@ -788,16 +825,21 @@ void backward(ri_cnn *n, const float *z, const float *g, int B, int h, int w, hi
     const int L = n->L;
     dim3 grid(w / 16, h / 16, B);
     fill_real<float>(n->grads, n->P, 0.f, s);
+    const int nblk16 = (w / 16) * (h / 16) * B;
     hipLaunchKernelGGL(k_out_backward, grid, dim3(256), outbwd_lds(), s, g, n->act[L - 2],
-                       n->params + n->off[2 * (L - 1)], n->dpre[0], n->grads + n->off[2 * (L - 1)],
-                       n->grads + n->off[2 * (L - 1) + 1], h, w);
+                       n->params + n->off[2 * (L - 1)], n->dpre[0], n->blkpart, h, w);
+    hipLaunchKernelGGL(k_reduce_rows, dim3((CH * 9 + 1 + 255) / 256), dim3(256), 0, s, n->blkpart, nblk16, CH * 9 + 1,
+                       CH * 9 + 1, n->grads + n->off[2 * (L - 1)]);
     int cur = 0;
     const int nbx = w / 16, nby = h / 16, nb = nbx * nby * B;                  // 16 x 16 blocks (weight gradients)
     const int cby = (h + CB_ROWS - 1) / CB_ROWS, cnb = nbx * cby * B;         // 32 x 16 blocks (convolutions)
     const CnnGeo full;
     for (int l = L - 2; l >= 1; --l) {
-        hipLaunchKernelGGL(k_dw64, dim3(persistent_grid(n, nb)), dim3(256), dw64_lds(), s, n->dpre[cur],
-                           n->act[l - 1], n->grads + n->off[2 * l], n->grads + n->off[2 * l + 1], h, w, nbx, nby, nb);
+        const int nwg = persistent_grid(n, nb);
+        hipLaunchKernelGGL(k_dw64, dim3(nwg), dim3(256), dw64_lds(), s, n->dpre[cur], n->act[l - 1], n->dwpart, h, w,
+                           nbx, nby, nb);
+        hipLaunchKernelGGL(k_dw64_reduce, dim3((9 * 4 * 4 * 256 + CH + 255) / 256), dim3(256), 0, s, n->dwpart, nwg,
+                           n->grads + n->off[2 * l], n->grads + n->off[2 * l + 1]);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<1>), dim3(persistent_grid(n, cnb)), dim3(256), conv64_lds(), s,
                            n->dpre[cur], n->dpre[cur ^ 1],
                            reinterpret_cast<const uint4 *>(n->wbwd + (size_t)(l - 1) * WPK * 8),
@@ -805,8 +847,9 @@ void backward(ri_cnn *n, const float *z, const float *g, int B, int h, int w, hi
                            (float *)nullptr, (int64_t)0);
         cur ^= 1;
     }
-    hipLaunchKernelGGL(k_dw_in, grid, dim3(256), 0, s, z, n->dpre[cur], n->grads + n->off[0], n->grads + n->off[1],
-                       h, w);
+    hipLaunchKernelGGL(k_dw_in, grid, dim3(256), 0, s, z, n->dpre[cur], n->blkpart, h, w);
+    hipLaunchKernelGGL(k_reduce_rows, dim3((CH * 9 + CH + 255) / 256), dim3(256), 0, s, n->blkpart, nblk16,
+                       CH * 9 + CH, CH * 9 + CH, n->grads + n->off[0]);
     RI_CHECK_HIP(hipGetLastError());
 }
 
@@ -871,6 +914,8 @@ ri_cnn *create(const ri_cnn_desc &d, uint64_t seed) {
         if (!n->training) n->S = (float *)cnn_alloc(n, sizeof(float) * 9 * npix);
         if (n->training) {
             n->grads = (float *)cnn_alloc(n, sizeof(float) * n->P);
+            n->dwpart = (float *)cnn_alloc(n, sizeof(float) * (size_t)DW_PART * n->n_cu);
+            n->blkpart = (float *)cnn_alloc(n, sizeof(float) * (npix / 256) * (CH * 9 + CH));
             n->dpre[0] = (uint16_t *)cnn_alloc(n, sizeof(uint16_t) * npix * CH);
             n->dpre[1] = (uint16_t *)cnn_alloc(n, sizeof(uint16_t) * npix * CH);
             n->g = (float *)cnn_alloc(n, sizeof(float) * npix);

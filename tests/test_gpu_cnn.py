@@ -325,3 +325,43 @@ def test_expansive_denoiser_falls_back_to_haar():
     assert st == R.RI_FELLBACK and rep.fell_back == 1
     assert np.isfinite(xo.cpu().numpy()).all()
     assert xo.cpu().numpy().min() >= 0.0      # finished with the positive Haar prox
+
+
+def test_denoiser_argument_errors():
+    c = wide()
+    ctx = _ctx(c, 32, 64, 16)
+    z = torch.zeros((c.N, c.N), dtype=torch.float32, device=DEV)
+    o = torch.empty_like(z)
+    with pytest.raises(R.RIError) as e:          # no network loaded yet
+        R.denoise(ctx, z, o, R.RI_PROX_CNN, 0.0)
+    assert e.value.status == R.RI_EINVAL and "ri_load_denoiser" in str(e.value)
+    with pytest.raises(R.RIError) as e:          # parameter count of a 10-layer network, 8 layers claimed
+        R.ri_load_denoiser(ctx, torch.tensor(_list_to_params(_trained_like_params()), device=DEV), 8)
+    assert e.value.status == R.RI_EINVAL
+    R.ri_load_denoiser(ctx, torch.tensor(_list_to_params(_trained_like_params()), device=DEV), LAYERS)
+    with pytest.raises(R.RIError) as e:          # in place is not allowed for the CNN
+        R.denoise(ctx, z, z, R.RI_PROX_CNN, 0.0)
+    assert e.value.status == R.RI_EINVAL
+    net = R.ri_cnn_create(layers=LAYERS, max_batch=1, max_h=32, max_w=32)
+    with pytest.raises(ValueError):              # beyond the network's buffers (binding check)
+        R.ri_cnn_forward(net, torch.zeros((1, 48, 32), device=DEV), torch.zeros((1, 48, 32), device=DEV))
+    with pytest.raises(R.RIError) as e:          # gradients need training buffers
+        R.ri_cnn_grad(net, torch.zeros((1, 32, 32), device=DEV), torch.zeros((1, 32, 32), device=DEV),
+                      torch.zeros(net.n_params, device=DEV))
+    assert e.value.status == R.RI_EINVAL
+
+
+def test_training_is_deterministic():
+    """The weight-gradient sums run in a fixed order: two networks trained on the same
+    batches end with identical parameters."""
+    u = torch.tensor(_images(4, 32, 32, seed=60), dtype=torch.float32, device=DEV)
+    out = []
+    for _ in range(2):
+        net = R.ri_cnn_create(layers=LAYERS, max_batch=4, max_h=32, max_w=32, training=True, seed=9)
+        for it in range(5):
+            R.ri_cnn_train_step(net, u, 0.05, 100 + it, 1e-3)
+        p = torch.empty(net.n_params, dtype=torch.float32, device=DEV)
+        R.ri_cnn_get_params(net, p)
+        torch.cuda.synchronize()
+        out.append(p.cpu())
+    assert torch.equal(out[0], out[1])

@@ -153,3 +153,55 @@ def test_cnn_whole_image_sampled_pixels():
     e = rel(np.array(got), np.array(ref))
     print(f"CNN on 2048^2: net(z) at {len(pix)} sampled pixels rel {e:.2e}")
     assert e <= 1e-2
+
+
+def test_blocked_operator_equals_monolithic(full):
+    """C2: the 64 uneven angular-sector blocks go through the same persistent
+    launch; Phi x per visibility is the same sum (bit for bit), the adjoint the
+    same sum in another order."""
+    uvw, x, _ = full
+    W2 = synth.C2
+    sizes = synth.block_sizes(W2.n_blocks, WL.M, W2.block_lo, W2.block_hi)
+    perm, offs = synth.blocked(uvw, sizes)
+    d = R.plan_desc(WL.N, WL.M, cell_rad=WL.cell_rad, w_max=WL.W, n_wplanes=WL.n_wplanes, precision=32,
+                    g_mode=R.RI_G_OTF, n_blocks=W2.n_blocks)
+    ctxb = R.ri_create(d, uvw[perm], block_offsets=offs)
+    ctx = _ctx(uvw, 32, R.RI_G_OTF)
+    stb, st = R.ri_get_plan_stats(ctxb), R.ri_get_plan_stats(ctx)
+    xt = torch.tensor(x, dtype=torch.float32, device=DEV)
+    y, yb = (torch.empty(WL.M, dtype=torch.complex64, device=DEV) for _ in range(2))
+    R.phi_forward(ctx, xt, y)
+    R.phi_forward(ctxb, xt, yb)
+    pt = torch.as_tensor(perm, device=DEV)
+    same_tile = stb.tile == st.tile
+    e_f = rel(yb.cpu().numpy(), y[pt].cpu().numpy())
+    g, gb = torch.empty_like(xt), torch.empty_like(xt)
+    R.phi_adjoint(ctx, y, g)
+    R.phi_adjoint(ctxb, yb, gb)
+    e_a = rel(gb.cpu().numpy(), g.cpu().numpy())
+    print(f"{stb.n_blocks} blocks, {stb.n_items} items (tile {stb.tile}) vs {st.n_items} items (tile {st.tile}): "
+          f"forward rel {e_f:.2e}, adjoint rel {e_a:.2e}")
+    if same_tile:
+        assert torch.equal(yb, y[pt])
+    assert e_f <= 1e-6
+    assert e_a <= 1e-6
+
+
+def test_cnn_facets_equal_whole_image_full_size():
+    """16 facets of 512^2 cores with 32-pixel halos (576^2 tiles) in one launch per
+    layer give the whole-image result bit for bit at 2048^2."""
+    N, L = WL.N, 10
+    ps = OC.init_params(L, 64, seed=22)
+    vec = np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in ps]).astype(np.float32)
+    z = torch.tensor(synth.sky(N) / synth.sky(N).max(), dtype=torch.float32, device=DEV)
+    outs = []
+    for core, halo in [(0, 0), (512, 32)]:
+        uvw = synth.random_uvw(16, 1.0, 0.0, seed=5)
+        ctx = R.ri_create(R.plan_desc(N, 16, precision=32, g_mode=R.RI_G_OTF, facet_core=core, facet_halo=halo),
+                          uvw)
+        R.ri_load_denoiser(ctx, torch.tensor(vec, device=DEV), L)
+        o = torch.full_like(z, float("nan"))
+        R.denoise(ctx, z, o, R.RI_PROX_CNN, 0.0)
+        outs.append(o)
+    assert torch.isfinite(outs[0]).all()
+    assert torch.equal(outs[0], outs[1])

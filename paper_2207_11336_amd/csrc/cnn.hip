@@ -113,7 +113,6 @@ __device__ __forceinline__ void block_origin(int blk, int nbx, int nby, int rows
 constexpr int CB_ROWS = 32;
 constexpr int CP_ROWS = CB_ROWS + 2, CP_COLS = 18;
 constexpr int CP_CHUNKS = CP_ROWS * CP_COLS * 8;          // 16-byte chunks of the patch
-constexpr int CPRE = (CP_CHUNKS + 255) / 256;             // chunks per thread
 
 // Buffer resource over one batch item's activations (bytes < 2^32): loads at
 // an offset past the end return zeros and stores there are dropped, which is
@@ -128,14 +127,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t item_rsrc(const uint16_t *base
 // Byte offset of channel c of pixel p (p < 2^25) in an item.
 __device__ __forceinline__ unsigned px_off(int p, int c) { return (unsigned)p * (CH * 2u) + (unsigned)c * 2u; }
 
-__device__ __forceinline__ void conv_patch_fetch(uint4 (&pre)[CPRE], const uint16_t *__restrict__ in, int blk,
+constexpr int CNW = 8;                                   // waves per workgroup (2 per SIMD)
+constexpr int CNT = 64 * CNW;                             // threads per workgroup
+constexpr int CRW = CB_ROWS / CNW;                        // block rows per wave
+constexpr int CPRE8 = (CP_CHUNKS + CNT - 1) / CNT;        // patch chunks per thread
+
+__device__ __forceinline__ void conv_patch_fetch(uint4 (&pre)[CPRE8], const uint16_t *__restrict__ in, int blk,
                                                  int nbx, int nby, int H, int W, int tid) {
     int b, y0, x0;
     block_origin(blk, nbx, nby, CB_ROWS, b, y0, x0);
     const __amdgpu_buffer_rsrc_t rs = item_rsrc(in + (size_t)b * H * W * CH, H, W);
 #pragma unroll
-    for (int k = 0; k < CPRE; ++k) {
-        const int e = tid + k * 256;
+    for (int k = 0; k < CPRE8; ++k) {
+        const int e = tid + k * CNT;
         const int pix = e >> 3, ch = e & 7;
         const int py = pix / CP_COLS, px = pix - py * CP_COLS;
         const int y = y0 - 1 + py, x = x0 - 1 + px;
@@ -145,33 +149,35 @@ __device__ __forceinline__ void conv_patch_fetch(uint4 (&pre)[CPRE], const uint1
     }
 }
 
-// Scheduling hint for a K step of 32 MFMAs that also loads NRD fragments of
+// Scheduling hint for a K step of NMF MFMAs that also loads NRD fragments of
 // the next step: alternate MFMA and LDS read, then the remaining MFMAs.
-template <int NRD>
+template <int NRD, int NMF>
 __device__ __forceinline__ void sched_interleave() {
 #pragma unroll
     for (int k = 0; k < NRD; ++k) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
     }
-    __builtin_amdgcn_sched_group_barrier(0x008, 32 - NRD, 0);
+    if constexpr (NMF - NRD > 0) __builtin_amdgcn_sched_group_barrier(0x008, NMF - NRD, 0);
 }
 
 // ---------------------------------------------------------------------------
 // 64 -> 64 convolution, persistent. MODE 0: out = relu(conv + bias), zero
 // outside the batch item's valid rectangle. MODE 1 (backward data): out =
 // conv * [mask_act > 0] (mask_act: the post-ReLU activation the gradient
-// flows into). 256 threads; blocks of 32 x 16 pixels (nbx x nby per item,
-// the last block row may reach past H). Wave w computes block rows
-// 8w..8w+7 for all 64 output channels: 4 x 8 accumulator tiles (initialised
-// with the bias in MODE 0). The K loop runs as 18 steps (dx, kb, dy): the ten
-// patch rows of a (dx, kb) pair are loaded once and serve the three row taps,
-// and each step's fragments are loaded while the previous step's MFMAs run.
-// The results go through LDS (the patch area, swizzled) so that every lane
+// flows into). MODE 2: as MODE 0, but the activations are projected onto the
+// nine taps of the 64 -> 1 output layer instead of being stored.
+// Eight waves (two per SIMD); blocks of 32 x 16 pixels (nbx x nby per item,
+// the last block row may reach past H); wave w computes block rows
+// 4w..4w+3 for all 64 output channels: 4 x 4 accumulator tiles (initialised
+// with the bias). The K loop runs as 18 steps (dx, kb, dy): the six patch
+// rows of a (dx, kb) pair are loaded once and serve the three row taps, and
+// each step's fragments are loaded while the previous step's MFMAs run. The
+// results go through LDS (the patch area, swizzled) so that every lane
 // stores 16 contiguous bytes and a wave writes whole pixel rows.
 // ---------------------------------------------------------------------------
 template <int MODE>
-__global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in, uint16_t *__restrict__ out,
+__global__ void __launch_bounds__(CNT) k_conv64(const uint16_t *__restrict__ in, uint16_t *__restrict__ out,
                                                 const uint4 *__restrict__ wpk, const float *__restrict__ bias,
                                                 const uint16_t *__restrict__ mask_act, CnnGeo geo, int H, int W,
                                                 int nbx, int nby, int nblocks, const uint4 *__restrict__ wproj,
@@ -182,31 +188,31 @@ __global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in,
     float *bs = reinterpret_cast<float *>(wl + WPK);                        // [64]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
-    for (int e = tid; e < WPK; e += 256) wl[e] = wpk[e];
+    for (int e = tid; e < WPK; e += CNT) wl[e] = wpk[e];
     if (tid < CH) bs[tid] = MODE != 1 ? bias[tid] : 0.f;
     const BlockWalk walk(blockIdx.x, gridDim.x, nblocks);
-    uint4 pre[CPRE];
+    uint4 pre[CPRE8];
     if (walk.begin < walk.end) conv_patch_fetch(pre, in, walk.begin, nbx, nby, H, W, tid);
     for (int blk = walk.begin; blk < walk.end; blk += walk.step) {
         __syncthreads();   // the previous block's patch and staging reads are done
 #pragma unroll
-        for (int k = 0; k < CPRE; ++k) {
-            const int e = tid + k * 256;
+        for (int k = 0; k < CPRE8; ++k) {
+            const int e = tid + k * CNT;
             if (e < CP_CHUNKS) *reinterpret_cast<uint4 *>(patch + (e >> 3) * PADC + (e & 7) * 8) = pre[k];
         }
         __syncthreads();
         if (blk + walk.step < walk.end) conv_patch_fetch(pre, in, blk + walk.step, nbx, nby, H, W, tid);
-        floatx4 acc[4][8];
+        floatx4 acc[4][CRW];
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi) {
             const float4 bb = *reinterpret_cast<const float4 *>(bs + mi * 16 + 4 * g);
 #pragma unroll
-            for (int ni = 0; ni < 8; ++ni) acc[mi][ni] = floatx4{bb.x, bb.y, bb.z, bb.w};
+            for (int ni = 0; ni < CRW; ++ni) acc[mi][ni] = floatx4{bb.x, bb.y, bb.z, bb.w};
         }
-        const uint16_t *pw = patch + (wave * 8 * CP_COLS + j) * PADC + 8 * g;
-        bf16x8 bcur[10], bnext[10], acur[4], anext[4];
+        const uint16_t *pw = patch + (wave * CRW * CP_COLS + j) * PADC + 8 * g;
+        bf16x8 bcur[CRW + 2], bnext[CRW + 2], acur[4], anext[4];
 #pragma unroll
-        for (int r = 0; r < 10; ++r) bcur[r] = as_bf16x8(*reinterpret_cast<const uint4 *>(pw + r * CP_COLS * PADC));
+        for (int r = 0; r < CRW + 2; ++r) bcur[r] = as_bf16x8(*reinterpret_cast<const uint4 *>(pw + r * CP_COLS * PADC));
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi) acur[mi] = as_bf16x8(wl[mi * 64 + lane]);
 #pragma unroll
@@ -219,7 +225,7 @@ __global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in,
                 for (int mi = 0; mi < 4; ++mi) anext[mi] = as_bf16x8(wl[((t1 * 2 + kb1) * 4 + mi) * 64 + lane]);
                 if (dy == 2) {
 #pragma unroll
-                    for (int r = 0; r < 10; ++r)
+                    for (int r = 0; r < CRW + 2; ++r)
                         bnext[r] = as_bf16x8(
                             *reinterpret_cast<const uint4 *>(pw + (r * CP_COLS + dx1) * PADC + kb1 * 32));
                 }
@@ -227,41 +233,44 @@ __global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in,
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-                for (int ni = 0; ni < 8; ++ni)
+                for (int ni = 0; ni < CRW; ++ni)
                     acc[mi][ni] =
                         __builtin_amdgcn_mfma_f32_16x16x32_bf16(acur[mi], bcur[ni + dy], acc[mi][ni], 0, 0, 0);
-            // scheduling: one LDS read of the next step's fragments after each MFMA
             if (st + 1 < 18) {
-                if (dy == 2) sched_interleave<14>();
-                else sched_interleave<4>();
+                if (dy == 2) sched_interleave<4 + CRW + 2, 4 * CRW>();
+                else sched_interleave<4, 4 * CRW>();
             }
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi) acur[mi] = anext[mi];
             if (dy == 2) {
 #pragma unroll
-                for (int r = 0; r < 10; ++r) bcur[r] = bnext[r];
+                for (int r = 0; r < CRW + 2; ++r) bcur[r] = bnext[r];
             }
         }
         int b, y0, x0;
         block_origin(blk, nbx, nby, CB_ROWS, b, y0, x0);
         const size_t img = (size_t)b * H * W * CH;
-        const int4 vr = valid_rect(geo, b, H, W);
-        const bool x_in = x0 + j >= vr.z && x0 + j < vr.w;
-        const bool all_in = y0 >= vr.x && y0 + CB_ROWS <= vr.y && x0 >= vr.z && x0 + 16 <= vr.w;
+        bool all_in = true, x_in = true;
+        int4 vr = make_int4(0, H, 0, W);
+        if (MODE != 1 && geo.N != 0) {
+            vr = valid_rect(geo, b, H, W);
+            x_in = x0 + j >= vr.z && x0 + j < vr.w;
+            all_in = y0 >= vr.x && y0 + CB_ROWS <= vr.y && x0 >= vr.z && x0 + 16 <= vr.w;
+        }
         __amdgpu_buffer_rsrc_t ms;
         if (MODE == 1) ms = item_rsrc(mask_act + img, H, W);
         __syncthreads();   // every wave is done with the patch: reuse it as staging
-        uint16_t *stg = patch + wave * (8 * 16 * 64);                      // [8 rows][16 px][64 ch], swizzled
+        uint16_t *stg = patch + wave * (CRW * 16 * 64);                    // [CRW rows][16 px][64 ch], swizzled
 #pragma unroll
-        for (int ni = 0; ni < 8; ++ni) {
-            const int y = y0 + wave * 8 + ni;
-            const bool inside = x_in && y >= vr.x && y < vr.y;
+        for (int ni = 0; ni < CRW; ++ni) {
+            const int y = y0 + wave * CRW + ni;
+            const bool inside = all_in || (x_in && y >= vr.x && y < vr.y);
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi) {
                 float v[4];
                 if (MODE != 1) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] = (all_in || inside) ? fmaxf(acc[mi][ni][r], 0.f) : 0.f;
+                    for (int r = 0; r < 4; ++r) v[r] = inside ? fmaxf(acc[mi][ni][r], 0.f) : 0.f;
                 } else {
                     // the gradient flows where the post-ReLU activation is > 0
                     const unsigned off = y < H ? px_off(y * W + x0 + j, mi * 16 + 4 * g) : OOB;
@@ -285,8 +294,8 @@ __global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in,
             // (MFMA rows t < 9 of a zero-padded 16-row A), instead of storing them
             const bf16x8 ap0 = as_bf16x8(wproj[lane]), ap1 = as_bf16x8(wproj[64 + lane]);
 #pragma unroll
-            for (int ni = 0; ni < 8; ++ni) {
-                const int y = y0 + wave * 8 + ni;
+            for (int ni = 0; ni < CRW; ++ni) {
+                const int y = y0 + wave * CRW + ni;
                 const uint16_t *sp = stg + (ni * 16 + j) * 64;
                 const bf16x8 b0 = as_bf16x8(*reinterpret_cast<const uint4 *>(sp + ((g ^ (j & 7)) * 8)));
                 const bf16x8 b1 = as_bf16x8(*reinterpret_cast<const uint4 *>(sp + (((4 + g) ^ (j & 7)) * 8)));
@@ -304,10 +313,10 @@ __global__ void __launch_bounds__(256) k_conv64(const uint16_t *__restrict__ in,
         }
         const __amdgpu_buffer_rsrc_t os = item_rsrc(out + img, H, W);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int c = k * 64 + lane;                 // chunk of [8 rows][16 px][8 chunks]
+        for (int k = 0; k < CRW * 2; ++k) {
+            const int c = k * 64 + lane;                 // chunk of [CRW rows][16 px][8 chunks]
             const int ni = c >> 7, px = (c >> 3) & 15, q = c & 7;
-            const int y = y0 + wave * 8 + ni;
+            const int y = y0 + wave * CRW + ni;
             const uint4 v = *reinterpret_cast<const uint4 *>(stg + (ni * 16 + px) * 64 + ((q ^ (px & 7)) * 8));
             const unsigned off = y < H ? px_off(y * W + x0 + px, q * 8) : OOB;
             __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), os, off, 0, 0);
@@ -802,11 +811,11 @@ void forward(ri_cnn *n, const float *z, float *D, int B, int h, int w, const Cnn
     for (int l = 1; l <= L - 2; ++l) {
         const uint4 *wl = reinterpret_cast<const uint4 *>(n->wfwd + (size_t)(l - 1) * WPK * 8);
         if (n->training || l < L - 2)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<0>), dim3(persistent_grid(n, nb)), dim3(256), conv64_lds(), s,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<0>), dim3(persistent_grid(n, nb)), dim3(CNT), conv64_lds(), s,
                                A(l - 1), A(l), wl, n->params + n->off[2 * l + 1], (const uint16_t *)nullptr, geo, h,
                                w, nbx, nby, nb, (const uint4 *)nullptr, (float *)nullptr, plane);
         else
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<2>), dim3(persistent_grid(n, nb)), dim3(256), conv64_lds(), s,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<2>), dim3(persistent_grid(n, nb)), dim3(CNT), conv64_lds(), s,
                                A(l - 1), (uint16_t *)nullptr, wl, n->params + n->off[2 * l + 1],
                                (const uint16_t *)nullptr, geo, h, w, nbx, nby, nb,
                                reinterpret_cast<const uint4 *>(n->wproj), n->S, plane);
@@ -840,7 +849,7 @@ void backward(ri_cnn *n, const float *z, const float *g, int B, int h, int w, hi
                            nbx, nby, nb);
         hipLaunchKernelGGL(k_dw64_reduce, dim3((9 * 4 * 4 * 256 + CH + 255) / 256), dim3(256), 0, s, n->dwpart, nwg,
                            n->grads + n->off[2 * l], n->grads + n->off[2 * l + 1]);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<1>), dim3(persistent_grid(n, cnb)), dim3(256), conv64_lds(), s,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<1>), dim3(persistent_grid(n, cnb)), dim3(CNT), conv64_lds(), s,
                            n->dpre[cur], n->dpre[cur ^ 1],
                            reinterpret_cast<const uint4 *>(n->wbwd + (size_t)(l - 1) * WPK * 8),
                            (const float *)nullptr, n->act[l - 1], full, h, w, nbx, cby, cnb, (const uint4 *)nullptr,

@@ -234,8 +234,9 @@ def main():
                     help="image-domain noise level of the PnP comparison (1 / target dynamic range)")
     ap.add_argument("--train-batch", type=int, default=16)
     ap.add_argument("--train-patches", type=int, default=1024)
-    ap.add_argument("--facet-core", type=int, default=0, help="CNN facet core side (0: whole image in one tile)")
-    ap.add_argument("--facet-halo", type=int, default=32)
+    ap.add_argument("--facet-core", type=int, default=None,
+                    help="CNN facet core side (0: whole image in one tile; default: the workload's)")
+    ap.add_argument("--facet-halo", type=int, default=None)
     ap.add_argument("--denoiser-only", action="store_true",
                     help="only time the CNN denoiser on one whole image of the workload (for profiling) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -290,6 +291,10 @@ def main():
     import synth
 
     wl = synth.WORKLOADS[args.workload]
+    if args.facet_core is None:
+        args.facet_core = wl.extra.get("facet_core", 0)
+    if args.facet_halo is None:
+        args.facet_halo = wl.extra.get("facet_halo", 32)
     dev = torch.device("cuda:0")
     N, M = wl.N, wl.M
     log(f"workload {wl.name}: N={N} grid={wl.Np} M={M:,} W={wl.W:.1f} planes={wl.n_wplanes}")
@@ -380,11 +385,12 @@ def main():
     st_nnz, plan_s, snr = best["nnz"], best["plan_s"], best["snr"]
     L, fp64_rate = shared["L"], shared["fp64_rate"]
 
-    # Plain FB time-to-SNR on the 64-block decomposition (uneven angular sectors),
-    # hipGraph-replayed iterations, FP64 SNR trace against the true sky.
+    # Plain FB time-to-SNR on the workload's block decomposition (uneven angular
+    # sectors; C2's 64 blocks for the unblocked C1 data), hipGraph-replayed
+    # iterations, FP64 SNR trace against the true sky.
     fb_trace, pnp = None, None
     if not args.no_solve:
-        wl2 = synth.C2
+        wl2 = wl if wl.n_blocks > 1 else synth.C2
         sizes = synth.block_sizes(wl2.n_blocks, M, wl2.block_lo, wl2.block_hi)
         perm, offs = synth.blocked(uvw, sizes)
         ctxb = R.ri_create(R.plan_desc(N, M, cell_rad=wl.cell_rad, w_max=wl.W, n_wplanes=wl.n_wplanes,

@@ -53,6 +53,10 @@ class Workload:
     n_blocks: int = 1
     block_lo: int = 0
     block_hi: int = 0
+    # frequency of each channel over the reference frequency at which omega_max
+    # and W are quoted; one channel is the uv track scaled by its ratio
+    # (omega and w in wavelengths both scale with frequency)
+    channels: tuple = (1.0,)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -61,7 +65,7 @@ class Workload:
 
     @property
     def M(self) -> int:
-        return self.n_ant * (self.n_ant - 1) // 2 * self.n_times
+        return self.n_ant * (self.n_ant - 1) // 2 * self.n_times * len(self.channels)
 
     @property
     def W(self) -> float:
@@ -91,7 +95,17 @@ T_SMALL_W = Workload("T-wide-128", N=128, n_ant=16, n_times=97,
                      omega_max=2 * math.pi / 3, cell_rad=20 * ARCSEC, w_mode="uniform",
                      w_hex_max=4.0, n_wplanes=257)
 
-WORKLOADS = {w.name: w for w in (C0, C1, C2, T_SMALL_W)}
+# Full scale: 4096^2 image, 8192^2 grid, one 64-antenna track of 12,400 steps
+# as two channels at 1053 and 1399 MHz (max |omega| = pi/1.6 and W quoted at
+# 1399 MHz), M = 49,996,800, 128 uneven angular-sector blocks, 64 facets of
+# 512^2 cores (32 px CNN halo, 16 px Haar halo).
+C4 = Workload("C4-full-4096", N=4096, n_ant=64, n_times=12400,
+              omega_max=math.pi / 1.6, cell_rad=1.68 * ARCSEC, w_mode="uniform",
+              w_hex_max=4.0, n_wplanes=4097, n_blocks=128,
+              block_lo=50_000, block_hi=2_000_000, channels=(1053.0 / 1399.0, 1.0),
+              extra={"freqs_mhz": (1053.0, 1399.0), "facet_core": 512, "facet_halo": 32})
+
+WORKLOADS = {w.name: w for w in (C0, C1, C2, C4, T_SMALL_W)}
 
 
 def scaled(base: Workload, **kw) -> Workload:
@@ -215,19 +229,27 @@ def baseline_uvw(enu: np.ndarray, n_times: int, dec_deg: float, lat_deg: float,
 
 def uvw(wl: Workload) -> np.ndarray:
     """Visibility coordinates for a workload: float64 [M, 3] = (omega_u, omega_v
-    in rad/pixel, w in wavelengths)."""
+    in rad/pixel, w in wavelengths). Several channels are stacked channel by
+    channel, each the reference track scaled by its frequency ratio."""
     enu = antenna_enu(wl.n_ant)
     b = baseline_uvw(enu, wl.n_times, wl.dec_deg, wl.lat_deg, wl.hours)
     rad = np.sqrt(b[:, 0] ** 2 + b[:, 1] ** 2).max()
-    out = np.empty_like(b)
-    out[:, 0:2] = b[:, 0:2] * (wl.omega_max / rad)
+    ref = np.empty_like(b)
+    ref[:, 0:2] = b[:, 0:2] * (wl.omega_max / rad)
+    del b
     if wl.w_mode == "zero":
-        out[:, 2] = 0.0
+        ref[:, 2] = 0.0
     elif wl.w_mode == "uniform":
         rng = np.random.default_rng(SEED_W)
-        out[:, 2] = rng.uniform(-wl.W, wl.W, size=b.shape[0])
+        ref[:, 2] = rng.uniform(-wl.W, wl.W, size=ref.shape[0])
     else:
         raise ValueError(wl.w_mode)
+    if tuple(wl.channels) == (1.0,):
+        return ref
+    n = ref.shape[0]
+    out = np.empty((n * len(wl.channels), 3))
+    for k, f in enumerate(wl.channels):
+        np.multiply(ref, f, out=out[k * n:(k + 1) * n])
     return out
 
 

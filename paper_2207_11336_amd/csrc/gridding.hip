@@ -92,6 +92,20 @@ __device__ __forceinline__ T sum16(T v) {
     return v;
 }
 
+// Lane N of the caller's 16-lane DPP row, broadcast to the whole row.
+template <int N, typename T>
+__device__ __forceinline__ T row_share(T v) { return dpp_f<0x150 + N>(v); }
+template <int N, typename T>
+__device__ __forceinline__ cx<T> row_share(cx<T> v) { return mk<T>(row_share<N>(v.x), row_share<N>(v.y)); }
+
+// f(integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) { static_for_(f, std::make_integer_sequence<int, N>{}); }
+
 template <typename T>
 __device__ __forceinline__ void lds_add(T *p, T v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -145,9 +159,7 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
     double *s_red = reinterpret_cast<double *>(gs + GROUPS * SCR_G);
     int &s_item = *reinterpret_cast<int *>(s_red + 4);
     const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
-    T *kbg = kbs + grp * SCR_KB;
     cx<T> *wk = wks + grp * SCR_W;
-    cx<T> *gg = gs + grp * SCR_G;
     const int Npm = (1 << a.logNp) - 1;
     double r2 = 0.0;
 
@@ -176,23 +188,64 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
             const int pl = (int)(rec.y & 0xFFFFu), h = (int)(rec.y >> 16);
             const int S = 2 * h + 7, SS = S * S;
             const int base = (cv - item.ty0 + a.H - h - 3) * W + (cu - item.tx0 + a.H - h - 3);
-            if (OTF) axis_weights<T>(a, m, pl, h, S, lane, kbg, wk, gg);
-            const float invS = 1.0f / (float)S;
             const int NI = (SS + 15) >> 4;
             cx<T> acc = mk<T>((T)0, (T)0);
             cx<T> r;
             if (OTF) {
-                // weights from the axis weights in LDS; recomputed in the
-                // scatter below instead of being held in registers
+                // G row from its separable axis weights, all in registers:
+                // lanes 0..6 hold the u-axis KB weights kappa(f_u - (j - 3)),
+                // lanes 8..14 the v-axis ones; lane c then forms
+                //   g[c] = sum_j kappa[j] k_w[2h + j - c]    (both axes, c < S),
+                // with kappa[j] broadcast over the row by DPP. The last index
+                // of a 17-wide window (c = 16, only k_w[0] kappa[6]) is kept by
+                // lane 0. Lane c owns window column c and walks the rows; the
+                // row weight g_v[ay] is broadcast from lane ay. For S = 17,
+                // column 16 is taken row-wise (lane l: row l) and the corner
+                // (16, 16) by lane 0, which keeps the 16 lanes balanced.
+                const T fu = a.frac[2 * (size_t)m], fv = a.frac[2 * (size_t)m + 1];
+                T kbr = (T)0;
+                if (lane < 7) kbr = kb_weight<T>(fu - (T)(lane - 3), a);
+                else if (lane >= 8 && lane < 15) kbr = kb_weight<T>(fv - (T)(lane - 11), a);
+                if (lane <= 2 * h) wk[lane] = a.wtaps[(size_t)pl * (2 * a.hmax + 1) + a.hmax - h + lane];
+                wave_sync();
+                cx<T> gu = mk<T>((T)0, (T)0), gv = gu, gu16 = gu, gv16 = gu;
+                static_for<7>([&](auto J) {
+                    constexpr int j = decltype(J)::value;
+                    const T ku = row_share<j>(kbr), kv = row_share<8 + j>(kbr);
+                    const int k = 2 * h + j - lane;
+                    if (k >= 0 && k <= 2 * h) {
+                        const cx<T> w = wk[k];
+                        gu = gu + scale(w, ku);
+                        gv = gv + scale(w, kv);
+                    }
+                });
+                if (S == 17) {
+                    const cx<T> w0 = wk[0];
+                    gu16 = scale(w0, row_share<6>(kbr));
+                    gv16 = scale(w0, row_share<14>(kbr));
+                }
+                const bool col = lane < S;
                 if (OP & OP_DEGRID) {
-#pragma unroll 4
-                    for (int i = 0; i < NI; ++i) {
-                        const int t = lane + 16 * i;
-                        if (t < SS) {
-                            const int ay = (int)(((float)t + 0.5f) * invS);
-                            const int ax = t - ay * S;
-                            acc = acc + (gg[18 + ay] * gg[ax]) * Xs[base + ay * W + ax];
+                    // Lanes c >= S read a cell inside the window and add it with
+                    // weight g_u[c] = 0. Rows 0..6 exist for every S; the rest
+                    // come in pairs (S is odd), so loads issue two at a time.
+                    const cx<T> *xp = Xs + base + min(lane, S - 1);
+                    cx<T> accv = mk<T>((T)0, (T)0);
+                    cx<T> xv[7];
+                    static_for<7>([&](auto J) { xv[J] = xp[J * W]; });
+                    static_for<7>([&](auto J) { accv = accv + row_share<decltype(J)::value>(gv) * xv[J]; });
+                    static_for<5>([&](auto P) {
+                        constexpr int y0 = 7 + 2 * decltype(P)::value, y1 = y0 + 1;
+                        if (y0 < S) {
+                            const cx<T> x0 = xp[y0 * W], x1 = xp[y1 * W];
+                            accv = accv + row_share<y0>(gv) * x0;
+                            accv = accv + (y1 < 16 ? row_share<y1 & 15>(gv) : row_share<0>(gv16)) * x1;
                         }
+                    });
+                    acc = accv * gu;
+                    if (S == 17) {
+                        acc = acc + (gv * row_share<0>(gu16)) * Xs[base + lane * W + 16];
+                        if (lane == 0) acc = acc + (gv16 * gu16) * Xs[base + 16 * W + 16];
                     }
                     acc.x = sum16(acc.x);
                     acc.y = sum16(acc.y);
@@ -207,15 +260,30 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
                     r = a.yuser[a.perm[m]];
                 }
                 if (OP & OP_GRID) {
-#pragma unroll 4
-                    for (int i = 0; i < NI; ++i) {
-                        const int t = lane + 16 * i;
-                        if (t < SS) {
-                            const int ay = (int)(((float)t + 0.5f) * invS);
-                            const int ax = t - ay * S;
-                            const cx<T> c = mulc(r, gg[18 + ay] * gg[ax]);
-                            lds_add(&Yr[base + ay * W + ax], (double)c.x);
-                            lds_add(&Yi[base + ay * W + ax], (double)c.y);
+                    // Y[ay][c] += r conj(g_v[ay] g_u[c])
+                    const cx<T> rc = mulc(r, gu);
+                    double *yr = Yr + base + lane, *yi = Yi + base + lane;
+                    if (col) {   // the row weights come from lanes ay < S, all active here
+                        static_for<17>([&](auto J) {
+                            constexpr int ay = decltype(J)::value;
+                            if (ay < 7 || ay < S) {
+                                const cx<T> gy = ay < 16 ? row_share<ay & 15>(gv) : row_share<0>(gv16);
+                                const cx<T> v = mulc(rc, gy);
+                                lds_add(yr + ay * W, (double)v.x);
+                                lds_add(yi + ay * W, (double)v.y);
+                            }
+                        });
+                    }
+                    if (S == 17) {
+                        const cx<T> v = mulc(mulc(r, row_share<0>(gu16)), gv);
+                        const int o = base + lane * W + 16;
+                        lds_add(&Yr[o], (double)v.x);
+                        lds_add(&Yi[o], (double)v.y);
+                        if (lane == 0) {
+                            const cx<T> v2 = mulc(mulc(r, gu16), gv16);
+                            const int o2 = base + 16 * W + 16;
+                            lds_add(&Yr[o2], (double)v2.x);
+                            lds_add(&Yi[o2], (double)v2.y);
                         }
                     }
                 }
@@ -260,7 +328,7 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
                     }
                 }
             }
-            if (OTF) wave_sync();   // kbg/wk/gg are rewritten by the group's next visibility
+            if (OTF) wave_sync();   // wk is rewritten by the group's next visibility
         }
         __syncthreads();
         if (OP & OP_GRID) {

@@ -29,9 +29,10 @@ if ROOT not in sys.path:
 
 METRIC = "Φ†Φ visibilities/s FP32 vs FP64; PnP-FB time-to-SNR at 2048² vs plain FB"
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed FP32 instructions (the build disables them):
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
-FP32_VALU_PEAK_TFS = 78.6
+# AMD's published FP32 vector peak. The build disables packed FP32
+# instructions, yet plain v_fma_f32 alone reaches 118 TFLOP/s on the device
+# (measured with a dense FMA loop), so the published figure is the bound.
+FP32_VALU_PEAK_TFS = 157.3
 BF16_PEAK_TFS = 2500.0       # dense BF16 MFMA (no sparsity)
 
 
@@ -72,15 +73,23 @@ def measured_traffic(mode: str, tile: int):
 
 
 def otf_tile_flops(nnz: int, M: int) -> float:
-    """Algorithmic FP32 flops of one fused on-the-fly tile pass: per visibility
-    14 Kaiser-Bessel weights (24-term I0 series, 3 flops a term, plus the
-    argument, ~80 flops each) and the two axis convolutions with the w-taps
-    (at most 7 complex-by-real terms per axis weight, S weights per axis,
-    ~4 flops a term); per stored entry the separable weight (complex product,
-    6 flops), the degrid complex MAC (8) and the grid contribution (complex
-    product with conjugate, 6, plus 2 accumulating adds)."""
-    per_vis = 14 * 80 + 2 * 7 * 4 * 13
-    return float(M) * per_vis + 22.0 * nnz
+    """Algorithmic flops of one fused on-the-fly tile pass, per visibility of
+    support S (window S x S, S = 2h + 7):
+      * 14 Kaiser-Bessel weights, each a 22-term Horner series in
+        z = 1 - (2t/7)^2 (21 FMAs) plus its argument: 46 flops;
+      * the two axis weight vectors, each entry a convolution of the 7 KB
+        weights with the 2h + 1 w-taps (complex by real, 4 flops a term):
+        2 * 7 * (2h + 1) * 4 = 56 (S - 6);
+      * degrid: S^2 complex MACs of the row weight with the grid (8 flops),
+        S column scalings by g_u (6) and the 16-lane sum (30);
+      * residual and its square (6);
+      * grid: S products r conj(g_u) (6) and S^2 contributions r conj(g_u)
+        conj(g_v) (6) accumulated into the FP64 real and imaginary planes (2).
+    Total 16 S^2 + 12 S + 56 (S - 6) + 680 = 16 S^2 + 68 S + 344. The sum of S
+    over visibilities is taken as M sqrt(nnz / M) (exact when all supports are
+    equal; within 1% for the workloads' support mixes)."""
+    sum_s = M * math.sqrt(nnz / M) if M else 0.0
+    return 16.0 * nnz + 68.0 * sum_s + 344.0 * M
 
 
 def cpu_baseline(wl, uvw, n_sample: int):

@@ -259,8 +259,8 @@ __global__ void __launch_bounds__(CNT) k_conv64(const uint16_t *__restrict__ in,
         }
         __amdgpu_buffer_rsrc_t ms;
         if (MODE == 1) ms = item_rsrc(mask_act + img, H, W);
-        __syncthreads();   // every wave is done with the patch: reuse it as staging
-        uint16_t *stg = patch + wave * (CRW * 16 * 64);                    // [CRW rows][16 px][64 ch], swizzled
+        // bf16 results: pk[ni][mi] = channels 16 mi + 4 g .. +3 of pixel (row ni, column j)
+        uint2 pk[CRW][4];
 #pragma unroll
         for (int ni = 0; ni < CRW; ++ni) {
             const int y = y0 + wave * CRW + ni;
@@ -281,17 +281,25 @@ __global__ void __launch_bounds__(CNT) k_conv64(const uint16_t *__restrict__ in,
                     for (int r = 0; r < 4; ++r) v[r] = m4[r] > 0 ? acc[mi][ni][r] : 0.f;
                 }
                 const bf16x2 lo = {(__bf16)v[0], (__bf16)v[1]}, hi = {(__bf16)v[2], (__bf16)v[3]};
-                // pixel (ni, j), channels 16 mi + 4 g .. +3: 16-byte chunk 2 mi + g/2, swizzled by pixel
-                const int q = (2 * mi + (g >> 1)) ^ (j & 7);
-                *reinterpret_cast<uint2 *>(stg + (ni * 16 + j) * 64 + q * 8 + (g & 1) * 4) =
-                    make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+                pk[ni][mi] = make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
             }
         }
-        __builtin_amdgcn_wave_barrier();   // the wave reads back what its other lanes staged
         if (MODE == 2) {
             // last hidden layer: project the block's activations onto the nine
             // taps of the 64 -> 1 output layer, s_t[p] = sum_c W[c][t] act[p][c]
-            // (MFMA rows t < 9 of a zero-padded 16-row A), instead of storing them
+            // (MFMA rows t < 9 of a zero-padded 16-row A), instead of storing
+            // them. The activations go through LDS (the patch area, swizzled by
+            // pixel) to reach the MFMA operand layout.
+            __syncthreads();   // every wave is done with the patch
+            uint16_t *stg = patch + wave * (CRW * 16 * 64);                // [CRW rows][16 px][64 ch]
+#pragma unroll
+            for (int ni = 0; ni < CRW; ++ni)
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi) {
+                    const int q = (2 * mi + (g >> 1)) ^ (j & 7);
+                    *reinterpret_cast<uint2 *>(stg + (ni * 16 + j) * 64 + q * 8 + (g & 1) * 4) = pk[ni][mi];
+                }
+            __builtin_amdgcn_wave_barrier();   // the wave reads back what its other lanes staged
             const bf16x8 ap0 = as_bf16x8(wproj[lane]), ap1 = as_bf16x8(wproj[64 + lane]);
 #pragma unroll
             for (int ni = 0; ni < CRW; ++ni) {
@@ -311,15 +319,25 @@ __global__ void __launch_bounds__(CNT) k_conv64(const uint16_t *__restrict__ in,
             }
             continue;
         }
+        // Direct 16-byte stores: lane rows g and g ^ 1 (lanes l and l ^ 16)
+        // exchange halves with v_permlane16_swap so that a lane holds eight
+        // consecutive channels. For the tile pair (mi, mi + 1): even rows keep
+        // tile mi (their 4 channels + the odd row's 4), odd rows take tile
+        // mi + 1; a lane then owns 16-byte chunk 2 (mi + (g & 1)) + (g >> 1).
         const __amdgpu_buffer_rsrc_t os = item_rsrc(out + img, H, W);
 #pragma unroll
-        for (int k = 0; k < CRW * 2; ++k) {
-            const int c = k * 64 + lane;                 // chunk of [CRW rows][16 px][8 chunks]
-            const int ni = c >> 7, px = (c >> 3) & 15, q = c & 7;
+        for (int ni = 0; ni < CRW; ++ni) {
             const int y = y0 + wave * CRW + ni;
-            const uint4 v = *reinterpret_cast<const uint4 *>(stg + (ni * 16 + px) * 64 + ((q ^ (px & 7)) * 8));
-            const unsigned off = y < H ? px_off(y * W + x0 + px, q * 8) : OOB;
-            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), os, off, 0, 0);
+#pragma unroll
+            for (int mp = 0; mp < 4; mp += 2) {
+                uint2 a = pk[ni][mp], c = pk[ni][mp + 1];
+                const auto sx = __builtin_amdgcn_permlane16_swap(a.x, c.x, false, false);
+                const auto sy = __builtin_amdgcn_permlane16_swap(a.y, c.y, false, false);
+                const u32x4 v = {sx[0], sy[0], sx[1], sy[1]};
+                const int q = 2 * (mp + (g & 1)) + (g >> 1);
+                const unsigned off = y < H ? px_off(y * W + x0 + j, q * 8) : OOB;
+                __builtin_amdgcn_raw_buffer_store_b128(v, os, off, 0, 0);
+            }
         }
     }
 }

@@ -237,8 +237,8 @@ def main():
     ap.add_argument("--fb-iters", type=int, default=300)
     ap.add_argument("--no-pnp", action="store_true", help="skip the denoiser training and the PnP-FB run")
     ap.add_argument("--pnp-iters", type=int, default=500)
-    ap.add_argument("--train-steps", type=int, default=24000)
-    ap.add_argument("--train-lr", type=float, default=1e-4)
+    ap.add_argument("--train-steps", type=int, default=48000)
+    ap.add_argument("--train-lr", type=float, default=2e-4)
     ap.add_argument("--pnp-sigma", type=float, default=1e-4,
                     help="image-domain noise level of the PnP comparison (1 / target dynamic range)")
     ap.add_argument("--train-batch", type=int, default=16)

@@ -11,9 +11,12 @@
 // Work item = one uv tile (T x T cells) of one data block, or a chunk of it.
 // A workgroup stages the item's input subgrid X (T + 2H)^2 and an output
 // subgrid Y in LDS, walks the item's visibilities (one 16-lane group per
-// visibility, taps spread over the lanes), and flushes Y to the global grid
-// with float atomics. Workgroups pull items from a global counter
-// (persistent launch), largest items first.
+// visibility), and flushes Y to the global grid with float atomics.
+// Workgroups pull items from a global counter (persistent launch), largest
+// items first. With G stored (CSR) the taps are spread over the lanes in row
+// order; on the fly, lane c of the group owns window column c, holds g_u[c]
+// and g_v[c] in registers and receives each row weight by a DPP broadcast,
+// so the weights never pass through LDS.
 #include "ri_internal.h"
 
 namespace ri {

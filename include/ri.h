@@ -78,6 +78,13 @@ typedef struct {
     int32_t facet_core;    /* denoiser facet core side (multiple of 16); 0 => whole image */
     int32_t facet_halo;    /* facet halo in pixels (the CNN needs >= its receptive radius) */
     int32_t item_vis;      /* visibilities per work item of the tile launch (0 => 1024) */
+    int32_t n_wstacks;     /* w-stacking hybrid (appendix E): 0 or 1 => the w-term rides on the
+                              w-kernels alone; P in 2..64 => P stacks of equal width over [-W, W]
+                              (centres w_p = -W + (2p+1) W/P, a visibility joins the stack whose
+                              interval holds its w). Stack p's image is multiplied by the exact
+                              phase screen exp(-2 pi i w_p (sqrt(1 - l^2 - m^2) - 1)) in Z and has
+                              its own FFT pair; the w-plane table then spans the residual
+                              [-W/P, W/P]. Costs P FFT pairs and 2P grids per pass. */
 } ri_plan_desc;
 
 /* Build a context: validates the description, computes every visibility's
@@ -176,8 +183,9 @@ typedef struct {
     const void *x_true;    /* optional dev [N][N] ground truth for the SNR trace, or NULL */
     double *trace;         /* optional host [max_iter][4]: rel change, ||r||^2, SNR dB, ms */
     int32_t use_graph;     /* 1: replay a hipGraph of two captured iterations */
-    int32_t diverge_checks;/* fall back to Haar after this many consecutive checks with a
-                              growing residual, or at once on a non-finite norm (0: 3) */
+    int32_t diverge_checks;/* fall back to Haar after this many consecutive checks at which the
+                              residual ||Phi x - y||^2 grew by more than 1% since the previous
+                              check, or at once on a non-finite norm (0: 3) */
 } ri_solve_opts;
 
 typedef struct {

@@ -134,9 +134,10 @@ __device__ void fft_lds(cx<T> *s, int logL, int logCW, const cx<T> *__restrict__
 __device__ __forceinline__ bool in_band(int r, int N, int Np) { return r < N / 2 || r >= Np - N / 2; }
 
 // Z then the row DFT of image row iy (blockIdx.x), written to grid row (iy - N/2) mod N'.
+// With a w-stack's phase screen (chirp != NULL) the padded image is x c_s.
 template <typename T, bool PAD>
 __global__ void k_zpad_rowfft(const T *__restrict__ x, cx<T> *__restrict__ grid, const T *__restrict__ icorr,
-                              const cx<T> *__restrict__ tw, int N, int logNp) {
+                              const cx<T> *__restrict__ tw, int N, int logNp, const cx<T> *__restrict__ chirp) {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
     const int Np = 1 << logNp;
@@ -144,9 +145,17 @@ __global__ void k_zpad_rowfft(const T *__restrict__ x, cx<T> *__restrict__ grid,
     const T cy = icorr[iy];
     for (int gx = threadIdx.x; gx < Np; gx += blockDim.x) {
         const int ix = (gx + N / 2) & (Np - 1);
-        T v = 0;
-        if (ix < N) v = x[(size_t)iy * N + ix] * icorr[ix] * cy;
-        s[pidx<PAD>(gx)] = mk<T>(v, (T)0);
+        cx<T> v = mk<T>((T)0, (T)0);
+        if (ix < N) {
+            const T a = x[(size_t)iy * N + ix] * icorr[ix] * cy;
+            if (chirp) {
+                const cx<T> ch = chirp[(size_t)iy * N + ix];
+                v = mk<T>(a * ch.x, a * ch.y);
+            } else {
+                v = mk<T>(a, (T)0);
+            }
+        }
+        s[pidx<PAD>(gx)] = v;
     }
     __syncthreads();
     fft_lds<T, PAD>(s, logNp, 0, tw, 1, false);
@@ -156,10 +165,13 @@ __global__ void k_zpad_rowfft(const T *__restrict__ x, cx<T> *__restrict__ grid,
 }
 
 // Inverse row DFT of grid row (iy - N/2) mod N', then crop, correction, real part:
-// out[iy][ix] = Re{row[(ix - N/2) mod N']} / (kappa_hat_x kappa_hat_y).
+// out[iy][ix] = Re{row[(ix - N/2) mod N']} / (kappa_hat_x kappa_hat_y). With a
+// w-stack's phase screen the value is Re{conj(c_s) row[...]} (Z_s^dagger), added
+// to out when accumulate != 0 (the sum over stacks).
 template <typename T, bool PAD>
 __global__ void k_irowfft_crop(const cx<T> *__restrict__ grid, T *__restrict__ out, const T *__restrict__ icorr,
-                               const cx<T> *__restrict__ tw, int N, int logNp) {
+                               const cx<T> *__restrict__ tw, int N, int logNp, const cx<T> *__restrict__ chirp,
+                               int accumulate) {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
     const int Np = 1 << logNp;
@@ -172,7 +184,15 @@ __global__ void k_irowfft_crop(const cx<T> *__restrict__ grid, T *__restrict__ o
     const T cy = icorr[iy];
     for (int ix = threadIdx.x; ix < N; ix += blockDim.x) {
         const int gx = (ix - N / 2) & (Np - 1);
-        out[(size_t)iy * N + ix] = s[pidx<PAD>(gx)].x * icorr[ix] * cy;
+        const cx<T> v = s[pidx<PAD>(gx)];
+        T re = v.x;
+        if (chirp) {
+            const cx<T> ch = chirp[(size_t)iy * N + ix];
+            re = v.x * ch.x + v.y * ch.y;
+        }
+        const T val = re * icorr[ix] * cy;
+        if (accumulate) out[(size_t)iy * N + ix] += val;
+        else out[(size_t)iy * N + ix] = val;
     }
 }
 
@@ -252,7 +272,8 @@ void colfft(ri_ctx *c, cx<T> *grid_io, cx<T> *grid_out, const cx<T> *tw, bool in
 
 }  // namespace
 
-// x (N x N) -> F Z x in p.gridB (row FFT into gridA band rows, columns A in place, B into gridB)
+// x (N x N) -> F Z_s x in p.gridB[s] for every w-stack s (row FFT into gridA band rows,
+// columns A in place, B into gridB[s])
 // Row transforms pad LDS by one element per 32 (fewer bank conflicts) when it fits.
 template <typename T>
 bool row_pad(ri_ctx *c) { return sizeof(cx<T>) * (size_t)(c->Np + c->Np / 32) <= (size_t)c->dev.lds_per_block; }
@@ -266,27 +287,35 @@ void fwd_zpad_fft(ri_ctx *c, Prec<T> &p, const T *x, hipStream_t s) {
     ProfScope prof(c, PROF_FFT, s);
     if (sizeof(cx<T>) * (size_t)Np > (size_t)c->dev.lds_per_block)
         throw Error(RI_EUNSUPPORTED, "grid row does not fit the workgroup LDS");
-    if (row_pad<T>(c))
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_zpad_rowfft<T, true>), dim3(c->N), dim3(threads_for(Np, 1)), row_lds<T>(c),
-                           s, x, p.gridA, p.icorr, p.tw, c->N, c->logNp);
-    else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_zpad_rowfft<T, false>), dim3(c->N), dim3(threads_for(Np, 1)),
-                           row_lds<T>(c), s, x, p.gridA, p.icorr, p.tw, c->N, c->logNp);
-    colfft<T>(c, p.gridA, p.gridB, p.tw, false, true, false, s);
+    // one FFT per w-stack (a single one without stacking); gridA is the scratch
+    for (int st = 0; st < c->P; ++st) {
+        const cx<T> *ch = c->P > 1 ? p.chirp + (size_t)st * c->N * c->N : nullptr;
+        if (row_pad<T>(c))
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_zpad_rowfft<T, true>), dim3(c->N), dim3(threads_for(Np, 1)),
+                               row_lds<T>(c), s, x, p.gridA, p.icorr, p.tw, c->N, c->logNp, ch);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_zpad_rowfft<T, false>), dim3(c->N), dim3(threads_for(Np, 1)),
+                               row_lds<T>(c), s, x, p.gridA, p.icorr, p.tw, c->N, c->logNp, ch);
+        colfft<T>(c, p.gridA, p.gridB + (size_t)st * Np * Np, p.tw, false, true, false, s);
+    }
 }
 
-// p.gridA (Y = G^H r, full grid) -> Re Z^dagger F^dagger Y into x (N x N); gridA is clobbered
+// p.gridA (Y_s = G_s^H r, one full grid per w-stack) -> Re sum_s Z_s^dagger F^dagger Y_s
+// into x (N x N); gridA is clobbered and gridB[0] serves as the scratch.
 template <typename T>
 void adj_fft_crop(ri_ctx *c, Prec<T> &p, T *x, hipStream_t s) {
     const int Np = c->Np;
     ProfScope prof(c, PROF_FFT, s);
-    colfft<T>(c, p.gridA, p.gridB, p.tw, true, false, true, s);
-    if (row_pad<T>(c))
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_irowfft_crop<T, true>), dim3(c->N), dim3(threads_for(Np, 1)),
-                           row_lds<T>(c), s, p.gridB, x, p.icorr, p.tw, c->N, c->logNp);
-    else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_irowfft_crop<T, false>), dim3(c->N), dim3(threads_for(Np, 1)),
-                           row_lds<T>(c), s, p.gridB, x, p.icorr, p.tw, c->N, c->logNp);
+    for (int st = 0; st < c->P; ++st) {
+        const cx<T> *ch = c->P > 1 ? p.chirp + (size_t)st * c->N * c->N : nullptr;
+        colfft<T>(c, p.gridA + (size_t)st * Np * Np, p.gridB, p.tw, true, false, true, s);
+        if (row_pad<T>(c))
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_irowfft_crop<T, true>), dim3(c->N), dim3(threads_for(Np, 1)),
+                               row_lds<T>(c), s, p.gridB, x, p.icorr, p.tw, c->N, c->logNp, ch, st > 0 ? 1 : 0);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_irowfft_crop<T, false>), dim3(c->N), dim3(threads_for(Np, 1)),
+                               row_lds<T>(c), s, p.gridB, x, p.icorr, p.tw, c->N, c->logNp, ch, st > 0 ? 1 : 0);
+    }
 }
 
 template void fwd_zpad_fft<float>(ri_ctx *, Prec<float> &, const float *, hipStream_t);

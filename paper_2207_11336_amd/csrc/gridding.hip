@@ -37,7 +37,7 @@ struct TileArgs {
     int *counter;
     int tile, H, W, logNp, hmax, kb_terms;
     T kbc[KB_TERMS_MAX];           // kappa(t) = sum_k kbc[k] z^k, z = 1 - (2t/7)^2
-    const uint2 *rec;              // per visibility: (cell, plane | h << 16)
+    const uint2 *rec;              // per visibility: (cell, plane | h << 16 | w-stack << 20)
     const T *frac;
     const cx<T> *wtaps;
     const int32_t *perm;
@@ -173,10 +173,14 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
         if (it >= a.n_items) break;
         const TileItem item = a.items[it];
         const int y0 = item.ty0 - a.H, x0 = item.tx0 - a.H;
+        // all of an item's visibilities belong to one w-stack, whose grids follow
+        const size_t goff = (size_t)(a.rec[item.vb].y >> 20) << (2 * a.logNp);
+        const cx<T> *Xg = a.X + goff;
+        cx<T> *Yg = a.Y + goff;
         if (OP & OP_DEGRID) {
             for (int e = tid; e < WW; e += blockDim.x) {
                 const int r = e / W, cc = e - r * W;
-                Xs[e] = a.X[((size_t)((y0 + r) & Npm) << a.logNp) + ((x0 + cc) & Npm)];
+                Xs[e] = Xg[((size_t)((y0 + r) & Npm) << a.logNp) + ((x0 + cc) & Npm)];
             }
         }
         if (OP & OP_GRID) {
@@ -188,7 +192,7 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
             const int m = item.vb + vi;
             const uint2 rec = a.rec[m];
             const int cu = (int)(rec.x & 0xFFFFu), cv = (int)(rec.x >> 16);
-            const int pl = (int)(rec.y & 0xFFFFu), h = (int)(rec.y >> 16);
+            const int pl = (int)(rec.y & 0xFFFFu), h = (int)((rec.y >> 16) & 0xFu);
             const int S = 2 * h + 7, SS = S * S;
             const int base = (cv - item.ty0 + a.H - h - 3) * W + (cu - item.tx0 + a.H - h - 3);
             const int NI = (SS + 15) >> 4;
@@ -339,7 +343,7 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
                 const double vr = Yr[e], vi = Yi[e];
                 if (vr != 0.0 || vi != 0.0) {
                     const int r = e / W, cc = e - r * W;
-                    cx<T> *dst = a.Y + ((size_t)((y0 + r) & Npm) << a.logNp) + ((x0 + cc) & Npm);
+                    cx<T> *dst = Yg + ((size_t)((y0 + r) & Npm) << a.logNp) + ((x0 + cc) & Npm);
                     global_add(&dst->x, (T)vr);
                     global_add(&dst->y, (T)vi);
                 }
@@ -369,7 +373,7 @@ __global__ void __launch_bounds__(256) k_fill_csr(TileArgs<double> a, int64_t M,
     for (int64_t m = (int64_t)blockIdx.x * GROUPS + grp; m < M; m += (int64_t)gridDim.x * GROUPS) {
         const uint2 rec = a.rec[m];
         const int cu = (int)(rec.x & 0xFFFFu), cv = (int)(rec.x >> 16);
-        const int pl = (int)(rec.y & 0xFFFFu), h = (int)(rec.y >> 16);
+        const int pl = (int)(rec.y & 0xFFFFu), h = (int)((rec.y >> 16) & 0xFu);
         const int S = 2 * h + 7, SS = S * S;
         axis_weights<double>(a, (int)m, pl, h, S, lane, kbg, wk, gg);
         const int64_t rp = rowptr[m];

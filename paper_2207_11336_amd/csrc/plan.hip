@@ -181,10 +181,18 @@ void build_plan(ri_ctx *c, const double *uvw) {
     const ri_plan_desc &d = c->d;
     const int64_t M = c->M;
     const int P = d.n_wplanes, P_half = (P - 1) / 2;
-    const double W = d.w_max;
+    // w-stacks (appendix E hybrid): NS stacks of width 2W/NS; the plane table
+    // then covers the residual w - w_s in [-W/NS, W/NS]
+    const int NS = c->P;
+    const double Wfull = d.w_max;
+    const double W = NS > 1 ? Wfull / NS : Wfull;
     const double scale = (double)c->Np / (2.0 * M_PI);
+    c->stack_w.assign(NS, 0.0);
+    if (NS > 1)
+        for (int k = 0; k < NS; ++k) c->stack_w[k] = -Wfull + (2.0 * k + 1.0) * Wfull / NS;
 
     c->pu.resize(M); c->pv.resize(M); c->cu.resize(M); c->cv.resize(M); c->plane.resize(M);
+    c->stack.assign(M, 0);
     std::vector<int> bad(1, 0);
     parallel_for(M, [&](int64_t a, int64_t b) {
         for (int64_t m = a; m < b; ++m) {
@@ -198,6 +206,12 @@ void build_plan(ri_ctx *c, const double *uvw) {
             c->cu[m] = (int32_t)(((iu % c->Np) + c->Np) % c->Np);
             c->cv[m] = (int32_t)(((iv % c->Np) + c->Np) % c->Np);
             int j = 0;
+            if (NS > 1) {
+                double k = std::floor((w + Wfull) * NS / (2.0 * Wfull));
+                const int st = (int)std::min(std::max(k, 0.0), (double)(NS - 1));
+                c->stack[m] = st;
+                w -= c->stack_w[st];
+            }
             if (P_half > 0 && W != 0.0) {
                 double dw = W / (double)P_half;
                 double jj = std::floor(w / dw + 0.5);
@@ -262,30 +276,64 @@ void build_view(ri_ctx *c, View &v, int tile, int frac_bytes) {
     const int Np = c->Np, nta = Np / tile;
     const int64_t ntiles = (int64_t)nta * nta;
     const int nb = (int)c->block_offsets.size() - 1;
-    const int64_t nbuckets = (int64_t)nb * ntiles;
     v.tile = tile;
     v.frac_bytes = frac_bytes;
 
-    std::vector<int64_t> bucket(M);
-    std::vector<int64_t> count(nbuckets + 1, 0);
+    // Counting sort by (block, w-stack), then, inside each such segment, by uv
+    // tile (the tile counters are reset only where a segment touched them, so
+    // the work stays O(M + ntiles) however many blocks and stacks there are).
+    const int NS = c->P;
+    const int64_t nk1 = (int64_t)nb * NS;
+    std::vector<int64_t> key1(M);
+    std::vector<int64_t> c1(nk1 + 1, 0);
     for (int b = 0; b < nb; ++b)
         for (int64_t m = c->block_offsets[b]; m < c->block_offsets[b + 1]; ++m) {
-            int64_t t = (int64_t)(c->cv[m] / tile) * nta + c->cu[m] / tile;
-            bucket[m] = (int64_t)b * ntiles + t;
-            count[bucket[m] + 1]++;
+            key1[m] = (int64_t)b * NS + c->stack[m];
+            c1[key1[m] + 1]++;
         }
-    for (int64_t i = 0; i < nbuckets; ++i) count[i + 1] += count[i];
-    std::vector<int64_t> order(M);
+    for (int64_t i = 0; i < nk1; ++i) c1[i + 1] += c1[i];
+    std::vector<int64_t> ord1(M);
     {
-        std::vector<int64_t> pos(count.begin(), count.end() - 1);
-        for (int64_t m = 0; m < M; ++m) order[pos[bucket[m]]++] = m;   // stable
+        std::vector<int64_t> pos(c1.begin(), c1.end() - 1);
+        for (int64_t m = 0; m < M; ++m) ord1[pos[key1[m]]++] = m;   // stable
+    }
+    struct Bucket { int64_t k1, t, s, e; };
+    std::vector<Bucket> buckets;
+    std::vector<int64_t> order(M);
+    std::vector<int64_t> ct(ntiles + 1, 0);
+    for (int64_t k = 0; k < nk1; ++k) {
+        const int64_t s0 = c1[k], e0 = c1[k + 1];
+        if (s0 == e0) continue;
+        auto tile_of = [&](int64_t m) { return (int64_t)(c->cv[m] / tile) * nta + c->cu[m] / tile; };
+        for (int64_t i = s0; i < e0; ++i) ct[tile_of(ord1[i]) + 1]++;
+        // prefix over the touched tiles only, in tile order
+        std::vector<int64_t> touched;
+        for (int64_t i = s0; i < e0; ++i) {
+            const int64_t t = tile_of(ord1[i]);
+            if (ct[t + 1] > 0) { touched.push_back(t); ct[t + 1] = -ct[t + 1]; }   // mark seen
+        }
+        std::sort(touched.begin(), touched.end());
+        int64_t run = s0;
+        std::vector<int64_t> start(touched.size());
+        for (size_t q = 0; q < touched.size(); ++q) {
+            const int64_t n = -ct[touched[q] + 1];
+            start[q] = run;
+            buckets.push_back({k, touched[q], run, run + n});
+            ct[touched[q] + 1] = (int64_t)q;   // slot of this tile in `start`
+            run += n;
+        }
+        for (int64_t i = s0; i < e0; ++i) {
+            const int64_t m = ord1[i];
+            order[start[ct[tile_of(m) + 1]]++] = m;   // stable within the tile
+        }
+        for (int64_t t : touched) ct[t + 1] = 0;
     }
     // inside each bucket: by (support, plane, caller index)
-    parallel_for(nbuckets, [&](int64_t a, int64_t b) {
+    parallel_for((int64_t)buckets.size(), [&](int64_t a, int64_t b) {
         for (int64_t k = a; k < b; ++k) {
-            int64_t s = count[k], e = count[k + 1];
-            if (e - s < 2) continue;
-            std::sort(order.begin() + s, order.begin() + e, [&](int64_t x, int64_t y) {
+            const int64_t s0 = buckets[k].s, e0 = buckets[k].e;
+            if (e0 - s0 < 2) continue;
+            std::sort(order.begin() + s0, order.begin() + e0, [&](int64_t x, int64_t y) {
                 int hx = c->plane_h[c->plane[x]], hy = c->plane_h[c->plane[y]];
                 if (hx != hy) return hx < hy;
                 if (c->plane[x] != c->plane[y]) return c->plane[x] < c->plane[y];
@@ -294,19 +342,18 @@ void build_view(ri_ctx *c, View &v, int tile, int frac_bytes) {
         }
     });
 
-    // work items
+    // work items (one bucket = one block, one stack, one uv tile; chunks of VMAX)
     const int64_t VMAX = c->d.item_vis > 0 ? c->d.item_vis : 1024;
     std::vector<TileItem> items;
     std::vector<int64_t> work;
-    for (int64_t k = 0; k < nbuckets; ++k) {
-        int64_t s = count[k], e = count[k + 1];
-        int64_t t = k % ntiles;
-        for (int64_t a = s; a < e; a += VMAX) {
+    for (const Bucket &bk : buckets) {
+        const int64_t s0 = bk.s, e0 = bk.e, t = bk.t;
+        for (int64_t a = s0; a < e0; a += VMAX) {
             TileItem it;
             it.ty0 = (int32_t)(t / nta) * tile;
             it.tx0 = (int32_t)(t % nta) * tile;
             it.vb = (int32_t)a;
-            it.vc = (int32_t)std::min(VMAX, e - a);
+            it.vc = (int32_t)std::min(VMAX, e0 - a);
             int64_t wsum = 0;
             for (int64_t i = a; i < a + it.vc; ++i) {
                 int S = 2 * c->plane_h[c->plane[order[i]]] + c->J;
@@ -337,7 +384,7 @@ void build_view(ri_ctx *c, View &v, int tile, int frac_bytes) {
         int64_t m = order[i];
         perm[i] = (int32_t)m;
         rec[i].x = ((uint32_t)c->cv[m] << 16) | (uint32_t)c->cu[m];
-        rec[i].y = (uint32_t)c->plane[m] | ((uint32_t)c->plane_h[c->plane[m]] << 16);
+        rec[i].y = (uint32_t)c->plane[m] | ((uint32_t)c->plane_h[c->plane[m]] << 16) | ((uint32_t)c->stack[m] << 20);
         double fu = c->pu[m] - std::floor(c->pu[m] + 0.5);
         double fv = c->pv[m] - std::floor(c->pv[m] + 0.5);
         if (frac_bytes == 4) { f32[2 * i] = (float)fu; f32[2 * i + 1] = (float)fv; }
@@ -376,8 +423,26 @@ void ensure_prec(ri_ctx *c, Prec<T> &p) {
     std::vector<cx<T>> wt(nt);
     for (size_t i = 0; i < nt; ++i) wt[i] = mk<T>((T)c->wtaps64[2 * i], (T)c->wtaps64[2 * i + 1]);
     p.wtaps = upload(c, wt.data(), nt);
-    p.gridA = (cx<T> *)dev_alloc(c, sizeof(cx<T>) * (size_t)Np * Np);
-    p.gridB = (cx<T> *)dev_alloc(c, sizeof(cx<T>) * (size_t)Np * Np);
+    const size_t ng = (size_t)c->P * Np * Np;
+    p.gridA = (cx<T> *)dev_alloc(c, sizeof(cx<T>) * ng);
+    p.gridB = (cx<T> *)dev_alloc(c, sizeof(cx<T>) * ng);
+    if (c->P > 1) {
+        // phase screens c_s(n) = exp(-2 pi i w_s (sqrt(1 - l^2 - m^2) - 1)), FP64 arithmetic
+        const double dl = c->d.cell_rad;
+        std::vector<cx<T>> ch((size_t)c->P * N * N);
+        parallel_for((int64_t)c->P * N, [&](int64_t a, int64_t b) {
+            for (int64_t r = a; r < b; ++r) {
+                const int st = (int)(r / N), iy = (int)(r % N);
+                const double my = (iy - N / 2) * dl;
+                for (int ix = 0; ix < N; ++ix) {
+                    const double lx = (ix - N / 2) * dl;
+                    const double ph = -2.0 * M_PI * c->stack_w[st] * (std::sqrt(1.0 - lx * lx - my * my) - 1.0);
+                    ch[(size_t)r * N + ix] = mk<T>((T)std::cos(ph), (T)std::sin(ph));
+                }
+            }
+        });
+        p.chirp = upload(c, ch.data(), ch.size());
+    }
     p.img0 = (T *)dev_alloc(c, sizeof(T) * (size_t)N * N);
     p.img1 = (T *)dev_alloc(c, sizeof(T) * (size_t)N * N);
     p.ydata = (cx<T> *)dev_alloc(c, sizeof(cx<T>) * (size_t)std::max<int64_t>(c->M, 1));

@@ -87,7 +87,7 @@ void do_forward(ri_ctx *c, const T *x, cx<T> *y, hipStream_t s) {
 template <typename T>
 void do_adjoint(ri_ctx *c, const cx<T> *y, T *x, hipStream_t s) {
     Prec<T> &p = prec<T>(c);
-    fill_zero<T>(p.gridA, (int64_t)c->Np * c->Np, s);
+    fill_zero<T>(p.gridA, (int64_t)c->P * c->Np * c->Np, s);
     launch_tiles<T>(c, c->view, p, OP_GRID, c->d.g_mode == RI_G_OTF, nullptr, y, nullptr, nullptr, s);
     adj_fft_crop<T>(c, p, x, s);
 }
@@ -97,7 +97,7 @@ template <typename T>
 void do_gradient(ri_ctx *c, const View &v, bool otf, const T *x, const cx<T> *y_sorted, T *g, hipStream_t s) {
     Prec<T> &p = prec<T>(c);
     fwd_zpad_fft<T>(c, p, x, s);
-    fill_zero<T>(p.gridA, (int64_t)c->Np * c->Np, s);
+    fill_zero<T>(p.gridA, (int64_t)c->P * c->Np * c->Np, s);
     launch_tiles<T>(c, v, p, OP_FUSED, otf, y_sorted, nullptr, nullptr, tile_part(c), s);
     adj_fft_crop<T>(c, p, g, s);
 }
@@ -297,7 +297,6 @@ template <typename T>
 bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_report *rep) {
     hipStream_t s = nullptr;
     RI_CHECK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    Prec<T> &p = prec<T>(c);
     const int64_t n = (int64_t)c->N * c->N;
     const int K = o.max_iter;
     std::vector<void *> owned;
@@ -413,7 +412,10 @@ bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_
                 RI_CHECK_HIP(hipStreamSynchronize(s));
                 const double *q = h.data() + 4 * (k - 1);
                 const bool finite = std::isfinite(q[0]) && std::isfinite(q[1]) && std::isfinite(q[2]);
-                rising = (last_r2 >= 0.0 && q[2] > last_r2) ? rising + 1 : 0;
+                // a check counts as rising when the residual grew by more than 1%:
+                // a converging PnP iterate may drift up by less on its way to the
+                // fixed point, a diverging one grows geometrically
+                rising = (last_r2 >= 0.0 && q[2] > 1.01 * last_r2) ? rising + 1 : 0;
                 last_r2 = q[2];
                 if (!finite || (kind != RI_PROX_HAAR && rising >= div_n)) {
                     if (kind == RI_PROX_HAAR) throw Error(RI_EDEVICE, "non-finite iterate with the Haar prox");
@@ -446,7 +448,6 @@ bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_
             rr.final_residual2 = q[2];
             rr.snr_db = xt && q[3] > 0 ? 10.0 * std::log10(xt2 / q[3]) : 0.0;
             if (o.trace) {
-                int mi = 0;
                 float prev_ms = 0.f;
                 int prev_k = 0;
                 for (auto &mk_ : marks) {
@@ -462,7 +463,6 @@ bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_
                     }
                     prev_ms = ms;
                     prev_k = mk_.first;
-                    ++mi;
                 }
             }
         }
@@ -506,6 +506,8 @@ ri_status ri_create(const ri_plan_desc *desc, const double *uvw, ri_ctx **out) {
         require(d.n_blocks >= 1, "n_blocks must be >= 1");
         require(d.facet_core >= 0 && d.facet_core % 16 == 0 && d.facet_halo >= 0, "facet sizes");
         require(d.item_vis >= 0 && d.item_vis <= (1 << 20), "item_vis must be in [0, 2^20]");
+        require(d.n_wstacks >= 0 && d.n_wstacks <= 64, "n_wstacks must be in [0, 64]");
+        require(d.n_wstacks <= 1 || d.w_max > 0.0, "w-stacking needs w_max > 0");
         c = new ri_ctx();
         c->d = d;
         c->d.block_offsets = nullptr;
@@ -518,6 +520,7 @@ ri_status ri_create(const ri_plan_desc *desc, const double *uvw, ri_ctx **out) {
         c->hmax = d.hmax;
         c->H = d.hmax + 3;
         c->M = d.M;
+        c->P = d.n_wstacks > 1 ? d.n_wstacks : 1;
         {
             double a = 7.0 / 2.0 * (2.0 - 0.5);
             c->beta = M_PI * std::sqrt(a * a - 0.8);
@@ -572,6 +575,7 @@ void ri_destroy(ri_ctx *c) {
     dev_free(c, c->csr.rowptr); dev_free(c, c->csr.val); dev_free(c, c->csr.col);
     auto freep = [c](auto &p) {
         dev_free(c, p.icorr); dev_free(c, p.tw); dev_free(c, p.wtaps); dev_free(c, p.gridA); dev_free(c, p.gridB);
+        dev_free(c, p.chirp);
         dev_free(c, p.img0); dev_free(c, p.img1); dev_free(c, p.ydata);
     };
     freep(c->p32);

@@ -49,7 +49,7 @@ struct View {
     int n_items = 0;
     int64_t max_item_vis = 0;
     int32_t *perm = nullptr;      // internal -> caller index
-    uint2 *rec = nullptr;         // per visibility: ((c_v << 16) | c_u, plane | h << 16)
+    uint2 *rec = nullptr;         // per visibility: ((c_v << 16) | c_u, plane | h << 16 | stack << 20)
     void *frac = nullptr;         // float[2] or double[2] per visibility (f_u, f_v)
     int frac_bytes = 0;           // 4 or 8
     TileItem *items = nullptr;
@@ -70,7 +70,8 @@ template <typename T> struct Prec {
     T *icorr = nullptr;           // [N]  1 / kappa_hat((i - N/2) / N')
     cx<T> *tw = nullptr;          // [N'] exp(-2 pi i k / N')
     cx<T> *wtaps = nullptr;       // [n_wplanes][2*hmax+1]
-    cx<T> *gridA = nullptr, *gridB = nullptr;   // N' x N'
+    cx<T> *gridA = nullptr, *gridB = nullptr;   // [w-stacks][N'][N']
+    cx<T> *chirp = nullptr;       // [w-stacks][N][N] phase screens (stacking only)
     T *img0 = nullptr, *img1 = nullptr;         // N x N scratch images
     cx<T> *ydata = nullptr;       // stored data, internal order
 };
@@ -101,7 +102,10 @@ struct ri_ctx {
     // host-side plan copies (caller order)
     std::vector<double> pu, pv;           // FP64 grid positions
     std::vector<int32_t> cu, cv;          // window centres mod N'
-    std::vector<int32_t> plane;           // w-plane per visibility
+    std::vector<int32_t> plane;           // w-plane per visibility (of the residual w with stacking)
+    int P = 1;                            // w-stacks
+    std::vector<double> stack_w;          // [P] stack centres w_p
+    std::vector<int32_t> stack;           // stack per visibility
     std::vector<int32_t> plane_h;         // [n_wplanes]
     std::vector<double> wtaps64;          // [n_wplanes][2*hmax+1][2]
 

@@ -39,7 +39,7 @@ class ri_plan_desc(ctypes.Structure):
                 ("cell_rad", c_double), ("w_max", c_double), ("n_wplanes", c_int32), ("g_mode", c_int32),
                 ("precision", c_int32), ("tile", c_int32), ("M", c_int64), ("n_blocks", c_int32),
                 ("block_offsets", c_void_p), ("facet_core", c_int32), ("facet_halo", c_int32),
-                ("item_vis", c_int32)]
+                ("item_vis", c_int32), ("n_wstacks", c_int32)]
 
 
 class ri_solve_opts(ctypes.Structure):
@@ -197,7 +197,7 @@ def _vis(ctx, t, name):
 
 def plan_desc(N: int, M: int, *, cell_rad: float = 0.0, w_max: float = 0.0, n_wplanes: int = 1,
               hmax: int = 5, g_mode: int = RI_G_CSR, precision: int = 32, tile: int = 0, n_blocks: int = 1,
-              facet_core: int = 0, facet_halo: int = 0, item_vis: int = 0) -> ri_plan_desc:
+              facet_core: int = 0, facet_halo: int = 0, item_vis: int = 0, n_wstacks: int = 0) -> ri_plan_desc:
     d = ri_plan_desc()
     d.N, d.oversample, d.kb_support, d.hmax = N, 2, 7, hmax
     d.cell_rad, d.w_max, d.n_wplanes = cell_rad, w_max, n_wplanes
@@ -206,6 +206,7 @@ def plan_desc(N: int, M: int, *, cell_rad: float = 0.0, w_max: float = 0.0, n_wp
     d.block_offsets = None
     d.facet_core, d.facet_halo = facet_core, facet_halo
     d.item_vis = item_vis
+    d.n_wstacks = n_wstacks
     return d
 
 

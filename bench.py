@@ -230,6 +230,7 @@ def main():
     ap.add_argument("--power-its", type=int, default=20)
     ap.add_argument("--tile", type=int, default=0, help="uv tile side (0: autotuned by the library)")
     ap.add_argument("--item-vis", type=int, default=0, help="visibilities per work item (0: library default)")
+    ap.add_argument("--wstacks", type=int, default=0, help="w-stacks of the hybrid (0 or 1: w-kernels alone)")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
@@ -317,7 +318,8 @@ def main():
         g_mode = R.RI_G_CSR if mode == "csr" else R.RI_G_OTF
         t0 = time.perf_counter()
         ctx = R.ri_create(R.plan_desc(N, M, cell_rad=wl.cell_rad, w_max=wl.W, n_wplanes=wl.n_wplanes,
-                                      precision=32, g_mode=g_mode, tile=args.tile, item_vis=args.item_vis), uvw)
+                                      precision=32, g_mode=g_mode, tile=args.tile, item_vis=args.item_vis,
+                                      n_wstacks=args.wstacks), uvw)
         plan_s = time.perf_counter() - t0
         st = R.ri_get_plan_stats(ctx)
         tuned = {int(st.tuned_tile[i]): round(float(st.tuned_ms[i]), 3) for i in range(st.n_tuned)}
@@ -416,7 +418,8 @@ def main():
         ctxb = R.ri_create(R.plan_desc(N, M, cell_rad=wl.cell_rad, w_max=wl.W, n_wplanes=wl.n_wplanes,
                                        precision=32, g_mode=R.RI_G_CSR if best["mode"] == "csr" else R.RI_G_OTF,
                                        tile=best["tile"], n_blocks=wl2.n_blocks, facet_core=args.facet_core,
-                                       facet_halo=args.facet_halo), uvw[perm], block_offsets=offs)
+                                       facet_halo=args.facet_halo, n_wstacks=args.wstacks), uvw[perm],
+                           block_offsets=offs)
         yb = torch.empty(M, dtype=torch.complex64, device=dev)
         R.phi_forward(ctxb, x_true, yb)
         yb += noise[torch.as_tensor(perm, device=dev)] * (shared["tau"] / math.sqrt(2))
@@ -450,6 +453,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "N": N, "grid": wl.Np, "M": M, "g_mode": best["mode"], "nnz": st_nnz,
+                   "w_stacks": max(args.wstacks, 1),
                    "tile": best["tile"], "step": "fb_step: fused gradient + Haar-l1 prox + FP64 norms",
                    "fp64_gram_vis_per_s": fp64_rate, "plan_s": plan_s, "L": L, "snr_db": snr, **extra,
                    "fb_time_to_snr": fb_trace, "pnp": pnp},

@@ -115,6 +115,13 @@ def scaled(base: Workload, **kw) -> Workload:
     return Workload(**d)
 
 
+# C1's geometry with a four times larger w range: the per-axis chirp at the
+# image edge spans 16 grid cells at |w| = W (57,503 wavelengths), beyond any
+# 17 x 17 w-kernel; the w-stacking hybrid's workload.
+C1W = scaled(C1, name="C1W-wide-2048-w16", w_hex_max=16.0)
+WORKLOADS[C1W.name] = C1W
+
+
 # ----------------------------------------------------------------------------
 # Sky
 # ----------------------------------------------------------------------------

@@ -151,3 +151,58 @@ def denoise_facets(params, z: np.ndarray, core: int, halo: int, bf16: bool = Fal
             d, _ = forward(params, zp[sl][None], bf16=bf16, mask=inside[sl][None])
             out[y0:y0 + core, x0:x0 + core] = d[0, halo:halo + core, halo:halo + core]
     return out
+
+
+# ----------------------------------------------------------------------------
+# Jacobian of the network at z (the firm-nonexpansiveness check, appendix C:
+# the training penalty asks ||J_{2D - I}||_S <= 1; here it is measured, not
+# imposed). ReLU networks are piecewise linear: at z, layer l's Jacobian is
+# the convolution without bias followed by the mask [pre-activation > 0].
+# ----------------------------------------------------------------------------
+def jvp(params, acts, v: np.ndarray, bf16: bool = False) -> np.ndarray:
+    """J_net(z) v for v [B, H, W], with acts = forward(params, z, bf16)[1].
+    bf16: tangent activations rounded to bfloat16 where the forward pass
+    rounds its activations (weights of layers 2..L in bfloat16)."""
+    t = v[:, None].astype(np.float64)
+    L = len(params)
+    for l, (w, b) in enumerate(params):
+        wl = bf16_round(w) if (bf16 and l > 0) else w
+        pre = conv3x3(t, wl, np.zeros_like(b))
+        if l == L - 1:
+            return pre[:, 0]
+        t = pre * (acts[l + 1] > 0)
+        if bf16:
+            t = bf16_round(t)
+    return t[:, 0]
+
+
+def vjp(params, acts, u: np.ndarray, bf16: bool = False) -> np.ndarray:
+    """J_net(z)^T u for u [B, H, W] (the gradient of sum(u * net) with respect
+    to z); bf16 rounds the pre-activation gradients as backward() does."""
+    g = u[:, None].astype(np.float64)
+    L = len(params)
+    for l in range(L - 1, -1, -1):
+        w, _ = params[l]
+        wl = bf16_round(w) if (bf16 and l > 0) else w
+        dxv, _, _ = conv3x3_backward(acts[l], wl, g, need_dx=True)
+        if l == 0:
+            return dxv[:, 0]
+        g = dxv * (acts[l] > 0)
+        if bf16:
+            g = bf16_round(g)
+    return g[:, 0]
+
+
+def fne_norm(params, z: np.ndarray, iters: int = 50, seed: int = 0, bf16: bool = False) -> float:
+    """||I - 2 J_net(z)||_S = ||J_{2D - I}(z)||_S (D = I - net) by the power
+    method on J^T J from a seeded normal start."""
+    _, acts = forward(params, z, bf16)
+    v = np.random.default_rng(seed).standard_normal(z.shape)
+    v /= np.linalg.norm(v)
+    s = 0.0
+    for _ in range(iters):
+        a = v - 2.0 * jvp(params, acts, v, bf16)
+        s = float(np.linalg.norm(a))
+        b = a - 2.0 * vjp(params, acts, a, bf16)
+        v = b / np.linalg.norm(b)
+    return s

@@ -89,3 +89,60 @@ def test_facets_with_receptive_halo_are_exact(bf16):
     # a halo below the receptive radius is not exact
     short = C.denoise_facets(params, z, core=16, halo=layers - 2, bf16=bf16)
     assert np.abs(short - whole[0]).max() > 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Jacobian-vector products and the firm-nonexpansiveness norm
+# ---------------------------------------------------------------------------
+def _small_net(seed=3, layers=4, ch=8):
+    rng = np.random.default_rng(seed)
+    ps = C.init_params(layers, ch, seed=seed)
+    return [(w, rng.standard_normal(b.shape) * 0.1) for w, b in ps]
+
+
+def test_jvp_and_vjp_are_adjoint():
+    ps = _small_net()
+    rng = np.random.default_rng(1)
+    z = rng.standard_normal((2, 12, 12))
+    _, acts = C.forward(ps, z)
+    v, u = rng.standard_normal(z.shape), rng.standard_normal(z.shape)
+    lhs = float(np.sum(C.jvp(ps, acts, v) * u))
+    rhs = float(np.sum(v * C.vjp(ps, acts, u)))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_jvp_matches_central_differences():
+    ps = _small_net(seed=5)
+    rng = np.random.default_rng(2)
+    z = rng.standard_normal((1, 12, 12))
+    v = rng.standard_normal(z.shape)
+    eps = 1e-6
+
+    def net(x):
+        D, _ = C.forward(ps, x)
+        return x - D
+
+    fd = (net(z + eps * v) - net(z - eps * v)) / (2 * eps)
+    _, acts = C.forward(ps, z)
+    jv = C.jvp(ps, acts, v)
+    assert np.linalg.norm(jv - fd) <= 1e-6 * np.linalg.norm(fd)
+
+
+@pytest.mark.parametrize("a", [0.8, 0.25, 2.0])
+def test_fne_norm_closed_form(a):
+    """A two-layer, one-channel network that passes z through its centre taps
+    with an always-active ReLU is net(z) = a (z + 5): J_net = a I and
+    ||I - 2 J_net||_S = |1 - 2a|."""
+    w0 = np.zeros((1, 1, 3, 3)); w0[0, 0, 1, 1] = 1.0
+    w1 = np.zeros((1, 1, 3, 3)); w1[0, 0, 1, 1] = a
+    ps = [(w0, np.array([5.0])), (w1, np.array([0.0]))]
+    z = np.random.default_rng(4).uniform(-1, 1, (1, 8, 8))
+    assert C.fne_norm(ps, z, iters=5) == pytest.approx(abs(1 - 2 * a), rel=1e-12)
+
+
+def test_fne_norm_of_a_dead_network_is_one():
+    """All hidden pre-activations negative: J_net = 0 and ||I||_S = 1."""
+    ps = _small_net(seed=7)
+    ps = [(w, np.full(b.shape, -100.0) if l < len(ps) - 1 else b) for l, (w, b) in enumerate(ps)]
+    z = np.random.default_rng(5).standard_normal((1, 8, 8))
+    assert C.fne_norm(ps, z, iters=3) == pytest.approx(1.0, rel=1e-12)

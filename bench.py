@@ -157,6 +157,7 @@ def run_pnp(args, R, synth, ctx, noise, x_true, L):
                                check_every=50, x_true=x_true.data_ptr(), trace=trace.ctypes.data, use_graph=1)
         xs = torch.empty_like(x_true)
         rep = R.pnp_solve(ctx, y, opts, xs)
+        solve.x = xs
         return rep, trace
 
     fb_rep, fb_tr = solve(R.RI_PROX_HAAR, 0.0)
@@ -193,6 +194,23 @@ def run_pnp(args, R, synth, ctx, noise, x_true, L):
     except R.RIError as e:
         log(f"PnP solve failed: {e}")
         return {"error": str(e), "sigma": sigma, "train_s": train_s}
+    # firm nonexpansiveness of the trained network (appendix C), measured:
+    # ||J_{2D - I}||_S on noisy held-out patches and at the PnP fixed point
+    # (the final iterate in the network's scaled domain, x / alpha)
+    fnet = R.ri_cnn_create(layers=10, max_batch=4, max_h=128, max_w=128, training=True)
+    R.ri_cnn_set_params(fnet, params)
+    held = torch.tensor(synth.training_patches(4, 128, seed=97), device=x_true.device)
+    held = (held + sigma * torch.randn(held.shape, device=held.device, generator=torch.Generator(
+        device=held.device).manual_seed(11))).contiguous()
+    fne_patches = R.ri_cnn_fne_norm(fnet, held, iters=30, seed=5)
+    fnet.close()
+    fnet = R.ri_cnn_create(layers=10, max_batch=1, max_h=N, max_w=N, training=True)
+    R.ri_cnn_set_params(fnet, params)
+    fne_fixed = R.ri_cnn_fne_norm(fnet, (solve.x / rep.alpha)[None].contiguous(), iters=30, seed=5)
+    fnet.close()
+    torch.cuda.empty_cache()
+    log(f"||J_(2D-I)||_S of the trained network: {fne_patches:.3f} on noisy held-out patches, "
+        f"{fne_fixed:.3f} at the PnP fixed point (FNE needs <= 1)")
     target = fb_rep.snr_db - 0.5
     hit = np.nonzero(tr[:rep.iters, 2] >= target)[0]
     fb_hit = np.nonzero(fb_tr[:fb_rep.iters, 2] >= target)[0]
@@ -211,6 +229,7 @@ def run_pnp(args, R, synth, ctx, noise, x_true, L):
            "denoiser_roofline": {"bound": "mfma", "achieved": den_tfs, "peak": BF16_PEAK_TFS, "unit": "TFLOP/s",
                                  "frac": den_tfs / BF16_PEAK_TFS, "flops_per_application": cnn_flops(nf * side * side),
                                  "kernels": "k_conv_in, 7 x k_conv64<0>, k_conv64<2>, k_conv_sum (one application)"},
+           "fne_norm_patches": fne_patches, "fne_norm_fixed_point": fne_fixed,
            "train_steps": args.train_steps, "train_batch": args.train_batch, "train_s": train_s,
            "train_tflops": train_flops / train_s / 1e12, "train_final_loss": hist[-1][1] if hist else None}
     log(f"PnP x{rep.iters}: {rep.ms:.1f} ms ({res['pnp_ms_per_iter']:.3f} ms/it), SNR {rep.snr_db:.2f} dB vs FB "

@@ -69,6 +69,25 @@ ri_status ri_cnn_grad(ri_cnn *net, const float *z, const float *g, int32_t batch
 ri_status ri_cnn_train_step(ri_cnn *net, const float *clean, int32_t batch, int32_t h, int32_t w, float sigma,
                             uint64_t seed, float lr, double *loss, ri_stream stream);
 
+/* Jacobian of the network at z (appendix C: the firm-nonexpansiveness
+ * condition of the training loss asks ||J_{2D - I}||_S <= 1; these calls
+ * measure it). A ReLU network is piecewise linear: at z each layer acts as its
+ * convolution without bias followed by the mask [pre-activation > 0]. All
+ * three run forward(z) first and need training = 1 (stored activations);
+ * tangents and adjoints pass through bfloat16 like the activations and
+ * gradients. z, v, u, out: dev [batch][h][w] FP32. */
+/* out = J_net(z) v */
+ri_status ri_cnn_jvp(ri_cnn *net, const float *z, const float *v, float *out, int32_t batch, int32_t h, int32_t w,
+                     ri_stream stream);
+/* out = J_net(z)^T u (the gradient of sum(u * net) with respect to z) */
+ri_status ri_cnn_vjp(ri_cnn *net, const float *z, const float *u, float *out, int32_t batch, int32_t h, int32_t w,
+                     ri_stream stream);
+/* *norm_out (host) = ||I - 2 J_net(z)||_S = ||J_{2D - I}(z)||_S estimated by
+ * iters >= 1 power iterations on J^T J from a seeded normal start (FP64
+ * norms); for batch > 1 the largest over the items. Synchronous. */
+ri_status ri_cnn_fne_norm(ri_cnn *net, const float *z, int32_t batch, int32_t h, int32_t w, int32_t iters,
+                          uint64_t seed, double *norm_out, ri_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -345,10 +345,11 @@ __global__ void __launch_bounds__(CNT) k_conv64(const uint16_t *__restrict__ in,
 // First layer: FP32 input, FP32 weights W0[64][9], bias; relu, valid mask,
 // bfloat16 out. A 16 x 16 block in eight passes of 32 pixels; thread t
 // computes channels 8 (t % 8) .. +7 of one pixel, so a wave stores eight
-// whole pixels (1 KB contiguous).
+// whole pixels (1 KB contiguous). Tangent mode (mask_act != NULL, b0 NULL):
+// out = [mask_act > 0] (W0 * z), the layer's Jacobian applied to z.
 __global__ void __launch_bounds__(256) k_conv_in(const float *__restrict__ z, uint16_t *__restrict__ out,
                                                  const float *__restrict__ w0, const float *__restrict__ b0,
-                                                 CnnGeo geo, int H, int W) {
+                                                 CnnGeo geo, int H, int W, const uint16_t *__restrict__ mask_act) {
     __shared__ float zp[18][18];
     __shared__ float ws[9][CH];
     __shared__ float bs[CH];
@@ -359,7 +360,7 @@ __global__ void __launch_bounds__(256) k_conv_in(const float *__restrict__ z, ui
         zp[py][px] = (y >= 0 && y < H && x >= 0 && x < W) ? z[img + (size_t)y * W + x] : 0.f;
     }
     for (int e = tid; e < CH * 9; e += 256) ws[e % 9][e / 9] = w0[e];
-    if (tid < CH) bs[tid] = b0[tid];
+    if (tid < CH) bs[tid] = b0 ? b0[tid] : 0.f;
     __syncthreads();
     const int4 vr = valid_rect(geo, b, H, W);
     const int q = tid & 7;
@@ -384,11 +385,22 @@ __global__ void __launch_bounds__(256) k_conv_in(const float *__restrict__ z, ui
             for (int e = 0; e < 8; ++e) v[e] += wr[t][e] * zz;
         }
         uint32_t o[4];
+        if (mask_act) {
+            const uint4 mv = *reinterpret_cast<const uint4 *>(mask_act + (img + (size_t)y * W + x) * CH + 8 * q);
+            const uint32_t mu[4] = {mv.x, mv.y, mv.z, mv.w};
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const bf16x2 pr = {(__bf16)(inside ? fmaxf(v[2 * e], 0.f) : 0.f),
-                               (__bf16)(inside ? fmaxf(v[2 * e + 1], 0.f) : 0.f)};
-            o[e] = __builtin_bit_cast(uint32_t, pr);
+            for (int e = 0; e < 4; ++e) {
+                const bf16x2 pr = {(__bf16)((int16_t)(mu[e] & 0xFFFFu) > 0 ? v[2 * e] : 0.f),
+                                   (__bf16)((int16_t)(mu[e] >> 16) > 0 ? v[2 * e + 1] : 0.f)};
+                o[e] = __builtin_bit_cast(uint32_t, pr);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bf16x2 pr = {(__bf16)(inside ? fmaxf(v[2 * e], 0.f) : 0.f),
+                                   (__bf16)(inside ? fmaxf(v[2 * e + 1], 0.f) : 0.f)};
+                o[e] = __builtin_bit_cast(uint32_t, pr);
+            }
         }
         *reinterpret_cast<uint4 *>(out + (img + (size_t)y * W + x) * CH + 8 * q) = make_uint4(o[0], o[1], o[2], o[3]);
     }
@@ -406,7 +418,11 @@ __device__ __forceinline__ void load_patch_lds(uint16_t *patch, const uint16_t *
     }
 }
 
-// Last layer + residual: D = z - (b + sum_{t,c} bf16(W[0][c][t]) act[p + t - centre][c]) in FP32.
+// Last layer + residual: D = z - (b + sum_{t,c} bf16(W[0][c][t]) act[p + t - centre][c]) in FP32;
+// z == NULL and bl == NULL give the layer without bias or residual (its
+// Jacobian). FLIP: the transposed first layer, D[p] = sum_{t,c} W0[c][t]
+// act[p - (t - centre)][c] with FP32 weights (the input gradient).
+template <bool FLIP>
 __global__ void __launch_bounds__(256) k_conv_out(const uint16_t *__restrict__ act, const float *__restrict__ z,
                                                   float *__restrict__ D, const float *__restrict__ wl_,
                                                   const float *__restrict__ bl, int H, int W) {
@@ -418,13 +434,14 @@ __global__ void __launch_bounds__(256) k_conv_out(const uint16_t *__restrict__ a
     load_patch_lds(patch, act, img, y0, x0, H, W, tid);
     for (int e = tid; e < CH * 9; e += 256) {
         const int c = e / 9, t = e - c * 9;
-        ws[t * CH + c] = bfround(wl_[e]);
+        ws[t * CH + c] = FLIP ? wl_[e] : bfround(wl_[e]);
     }
     __syncthreads();
     const int ty = tid >> 4, tx = tid & 15;
-    float acc = bl[0];
+    float acc = (!FLIP && bl) ? bl[0] : 0.f;
     for (int t = 0; t < 9; ++t) {
-        const uint16_t *pp = patch + ((ty + t / 3) * 18 + tx + t % 3) * PADC;
+        const int oy = FLIP ? 2 - t / 3 : t / 3, ox = FLIP ? 2 - t % 3 : t % 3;
+        const uint16_t *pp = patch + ((ty + oy) * 18 + tx + ox) * PADC;
         const float *wt = ws + t * CH;
 #pragma unroll
         for (int c8 = 0; c8 < CH; c8 += 8) {
@@ -438,7 +455,7 @@ __global__ void __launch_bounds__(256) k_conv_out(const uint16_t *__restrict__ a
         }
     }
     const size_t o = img + (size_t)(y0 + ty) * W + x0 + tx;
-    D[o] = z[o] - acc;
+    D[o] = (!FLIP && z) ? z[o] - acc : acc;
 }
 
 // Output layer from the tap projections: D = z - (b + sum_t s_t[p + (t - centre)]).
@@ -716,6 +733,26 @@ __global__ void k_noisy(const float *__restrict__ clean, float *__restrict__ noi
         noisy[i] = clean[i] + sigma * normal_at(seed, (uint64_t)i);
 }
 
+// Seeded standard normal vector (the start of the FNE power iteration).
+__global__ void k_normal(float *__restrict__ v, int64_t n, uint64_t seed) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = normal_at(seed, (uint64_t)i);
+}
+
+// out = a - 2 t (the map I - 2 J_net applied through its Jacobian product t).
+__global__ void k_minus2(const float *__restrict__ a, const float *__restrict__ t, float *__restrict__ out,
+                         int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = a[i] - 2.f * t[i];
+}
+
+// v /= sqrt(ss[0]) (FP64 squared norm from the reduction).
+__global__ void k_scale_rsqrt(float *__restrict__ v, int64_t n, const double *__restrict__ ss) {
+    const float k = (float)(1.0 / sqrt(ss[0]));
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[i] *= k;
+}
+
 __global__ void k_init_params(float *p, const int64_t *offs, const float *stds, int nl, int64_t total, uint64_t seed) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
         int l = 0;
@@ -776,6 +813,7 @@ struct ri_cnn {
     float *dwpart = nullptr;           // training: per-workgroup weight-gradient partials
     float *blkpart = nullptr;          // training: per-block partials of the first / last layer
     double *part = nullptr;
+    double *scal = nullptr;            // FP64 scalars of the Jacobian-norm iteration
     int64_t step = 0;
     std::string err;
     std::vector<void *> allocs;
@@ -825,7 +863,7 @@ void forward(ri_cnn *n, const float *z, float *D, int B, int h, int w, const Cnn
     const int64_t plane = (int64_t)B * h * w;
     auto A = [&](int l) { return n->training ? n->act[l] : n->act[l & 1]; };
     hipLaunchKernelGGL(k_conv_in, grid, dim3(256), 0, s, z, A(0), n->params + n->off[0], n->params + n->off[1], geo,
-                       h, w);
+                       h, w, (const uint16_t *)nullptr);
     for (int l = 1; l <= L - 2; ++l) {
         const uint4 *wl = reinterpret_cast<const uint4 *>(n->wfwd + (size_t)(l - 1) * WPK * 8);
         if (n->training || l < L - 2)
@@ -839,7 +877,7 @@ void forward(ri_cnn *n, const float *z, float *D, int B, int h, int w, const Cnn
                                reinterpret_cast<const uint4 *>(n->wproj), n->S, plane);
     }
     if (n->training)
-        hipLaunchKernelGGL(k_conv_out, grid, dim3(256), convout_lds(), s, A(L - 2), z, D,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv_out<false>), grid, dim3(256), convout_lds(), s, A(L - 2), z, D,
                            n->params + n->off[2 * (L - 1)], n->params + n->off[2 * (L - 1) + 1], h, w);
     else
         hipLaunchKernelGGL(k_conv_sum, dim3(std::min<int64_t>((plane + 255) / 256, 8192)), dim3(256), 0, s, n->S, z,
@@ -877,6 +915,54 @@ void backward(ri_cnn *n, const float *z, const float *g, int B, int h, int w, hi
     hipLaunchKernelGGL(k_dw_in, grid, dim3(256), 0, s, z, n->dpre[cur], n->blkpart, h, w);
     hipLaunchKernelGGL(k_reduce_rows, dim3((CH * 9 + CH + 255) / 256), dim3(256), 0, s, n->blkpart, nblk16,
                        CH * 9 + CH, CH * 9 + CH, n->grads + n->off[0]);
+    RI_CHECK_HIP(hipGetLastError());
+}
+
+// J_net(z) v into out, with the activations of forward(z) (training mode):
+// tangents through the first layer (masked, no bias), the hidden layers
+// (MODE 1 with the forward weights: conv * [activation > 0]) and the output
+// layer without bias or residual. Tangent activations in bfloat16.
+void jvp(ri_cnn *n, const float *v, float *out, int B, int h, int w, hipStream_t s) {
+    const int L = n->L;
+    dim3 grid(w / 16, h / 16, B);
+    const int nbx = w / 16, cby = (h + CB_ROWS - 1) / CB_ROWS, cnb = nbx * cby * B;
+    const CnnGeo full;
+    hipLaunchKernelGGL(k_conv_in, grid, dim3(256), 0, s, v, n->dpre[0], n->params + n->off[0], (const float *)nullptr,
+                       full, h, w, n->act[0]);
+    int cur = 0;
+    for (int l = 1; l <= L - 2; ++l) {
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<1>), dim3(persistent_grid(n, cnb)), dim3(CNT), conv64_lds(), s,
+                           n->dpre[cur], n->dpre[cur ^ 1],
+                           reinterpret_cast<const uint4 *>(n->wfwd + (size_t)(l - 1) * WPK * 8),
+                           (const float *)nullptr, n->act[l], full, h, w, nbx, cby, cnb, (const uint4 *)nullptr,
+                           (float *)nullptr, (int64_t)0);
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv_out<false>), grid, dim3(256), convout_lds(), s, n->dpre[cur],
+                       (const float *)nullptr, out, n->params + n->off[2 * (L - 1)], (const float *)nullptr, h, w);
+    RI_CHECK_HIP(hipGetLastError());
+}
+
+// J_net(z)^T u into out: the backward data pass of backward() without the
+// weight gradients, then the transposed first layer (FP32 weights).
+void vjp(ri_cnn *n, const float *u, float *out, int B, int h, int w, hipStream_t s) {
+    const int L = n->L;
+    dim3 grid(w / 16, h / 16, B);
+    const int nbx = w / 16, cby = (h + CB_ROWS - 1) / CB_ROWS, cnb = nbx * cby * B;
+    const CnnGeo full;
+    hipLaunchKernelGGL(k_out_backward, grid, dim3(256), outbwd_lds(), s, u, n->act[L - 2],
+                       n->params + n->off[2 * (L - 1)], n->dpre[0], n->blkpart, h, w);
+    int cur = 0;
+    for (int l = L - 2; l >= 1; --l) {
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<1>), dim3(persistent_grid(n, cnb)), dim3(CNT), conv64_lds(), s,
+                           n->dpre[cur], n->dpre[cur ^ 1],
+                           reinterpret_cast<const uint4 *>(n->wbwd + (size_t)(l - 1) * WPK * 8),
+                           (const float *)nullptr, n->act[l - 1], full, h, w, nbx, cby, cnb, (const uint4 *)nullptr,
+                           (float *)nullptr, (int64_t)0);
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv_out<true>), grid, dim3(256), convout_lds(), s, n->dpre[cur],
+                       (const float *)nullptr, out, n->params + n->off[0], (const float *)nullptr, h, w);
     RI_CHECK_HIP(hipGetLastError());
 }
 
@@ -938,6 +1024,7 @@ ri_cnn *create(const ri_cnn_desc &d, uint64_t seed) {
         n->D = (float *)cnn_alloc(n, sizeof(float) * npix);
         n->zin = (float *)cnn_alloc(n, sizeof(float) * npix);
         n->part = (double *)cnn_alloc(n, sizeof(double) * 1024);
+        n->scal = (double *)cnn_alloc(n, sizeof(double) * 16);
         if (!n->training) n->S = (float *)cnn_alloc(n, sizeof(float) * 9 * npix);
         if (n->training) {
             n->grads = (float *)cnn_alloc(n, sizeof(float) * n->P);
@@ -1117,6 +1204,63 @@ ri_status ri_cnn_train_step(ri_cnn *n, const float *clean, int32_t B, int32_t h,
                            c2);
         repack(n, s);
         RI_CHECK_HIP(hipGetLastError());
+    });
+}
+
+ri_status ri_cnn_jvp(ri_cnn *n, const float *z, const float *v, float *out, int32_t B, int32_t h, int32_t w,
+                     ri_stream stream) {
+    if (!n || !z || !v || !out) return RI_EINVAL;
+    return cnn_guard(n, [&] {
+        if (!n->training) throw Error(RI_EINVAL, "network created without training buffers");
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        check_shape(n, B, h, w);
+        forward(n, z, n->D, B, h, w, CnnGeo(), s);
+        jvp(n, v, out, B, h, w, s);
+    });
+}
+
+ri_status ri_cnn_vjp(ri_cnn *n, const float *z, const float *u, float *out, int32_t B, int32_t h, int32_t w,
+                     ri_stream stream) {
+    if (!n || !z || !u || !out) return RI_EINVAL;
+    return cnn_guard(n, [&] {
+        if (!n->training) throw Error(RI_EINVAL, "network created without training buffers");
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        check_shape(n, B, h, w);
+        forward(n, z, n->D, B, h, w, CnnGeo(), s);
+        vjp(n, u, out, B, h, w, s);
+    });
+}
+
+ri_status ri_cnn_fne_norm(ri_cnn *n, const float *z, int32_t B, int32_t h, int32_t w, int32_t iters, uint64_t seed,
+                          double *norm_out, ri_stream stream) {
+    if (!n || !z || !norm_out) return RI_EINVAL;
+    return cnn_guard(n, [&] {
+        if (!n->training) throw Error(RI_EINVAL, "network created without training buffers");
+        if (iters < 1) throw Error(RI_EINVAL, "iters must be >= 1");
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        check_shape(n, B, h, w);
+        const int64_t np = (int64_t)B * h * w;
+        forward(n, z, n->D, B, h, w, CnnGeo(), s);
+        float *v = n->zin, *t = n->D, *a = n->g;
+        hipLaunchKernelGGL(k_normal, dim3(gridn(np)), dim3(256), 0, s, v, np, seed);
+        dot_partials<float>(v, v, np, n->part, s);
+        reduce_partials(n->part, 1024, 1, 1, n->scal, s);
+        hipLaunchKernelGGL(k_scale_rsqrt, dim3(gridn(np)), dim3(256), 0, s, v, np, n->scal);
+        for (int it = 0; it < iters; ++it) {
+            jvp(n, v, t, B, h, w, s);                                                   // t = J_net v
+            hipLaunchKernelGGL(k_minus2, dim3(gridn(np)), dim3(256), 0, s, v, t, a, np);   // a = (I - 2 J_net) v
+            dot_partials<float>(a, a, np, n->part, s);
+            reduce_partials(n->part, 1024, 1, 1, n->scal + 1, s);                       // ||a||^2, v unit
+            vjp(n, a, t, B, h, w, s);                                                   // t = J_net^T a
+            hipLaunchKernelGGL(k_minus2, dim3(gridn(np)), dim3(256), 0, s, a, t, v, np);   // v = (I - 2 J_net)^T a
+            dot_partials<float>(v, v, np, n->part, s);
+            reduce_partials(n->part, 1024, 1, 1, n->scal, s);
+            hipLaunchKernelGGL(k_scale_rsqrt, dim3(gridn(np)), dim3(256), 0, s, v, np, n->scal);
+        }
+        double ss = 0.0;
+        RI_CHECK_HIP(hipMemcpyAsync(&ss, n->scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        RI_CHECK_HIP(hipStreamSynchronize(s));
+        *norm_out = std::sqrt(ss);
     });
 }
 

@@ -25,7 +25,8 @@ EXPORTS = ("ri_create", "ri_destroy", "ri_last_error", "phi_forward", "phi_adjoi
            "ri_gradient", "ri_power_norm", "denoise", "fb_step", "ri_load_denoiser", "pnp_solve",
            "ri_get_plan_stats", "ri_get_plan_arrays", "ri_profile", "ri_profile_read",
            "ri_cnn_create", "ri_cnn_destroy", "ri_cnn_last_error", "ri_cnn_param_count", "ri_cnn_set_params",
-           "ri_cnn_get_params", "ri_cnn_forward", "ri_cnn_grad", "ri_cnn_train_step")
+           "ri_cnn_get_params", "ri_cnn_forward", "ri_cnn_grad", "ri_cnn_train_step", "ri_cnn_jvp", "ri_cnn_vjp",
+           "ri_cnn_fne_norm")
 
 
 class RIError(RuntimeError):
@@ -118,6 +119,12 @@ def load() -> ctypes.CDLL:
     L.ri_cnn_train_step.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, ctypes.c_float,
                                     ctypes.c_uint64, ctypes.c_float, c_void_p, c_void_p]
     L.ri_cnn_train_step.restype = st
+    for f in (L.ri_cnn_jvp, L.ri_cnn_vjp):
+        f.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p]
+        f.restype = st
+    L.ri_cnn_fne_norm.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, ctypes.c_uint64, c_void_p,
+                                  c_void_p]
+    L.ri_cnn_fne_norm.restype = st
     _lib = L
     return L
 
@@ -415,6 +422,35 @@ def ri_cnn_grad(net: Cnn, z, g, grads, stream=None):
     gp, _, _, _ = _batch(net, g, "g")
     _check_cnn(net, load().ri_cnn_grad(net.handle, zp, gp, B, h, w, _dev(grads, torch.float32, net.n_params, "grads"),
                                        _stream(stream)))
+
+
+def ri_cnn_jvp(net: Cnn, z, v, out, stream=None):
+    """out = J_net(z) v (training-mode network)."""
+    zp, B, h, w = _batch(net, z, "z")
+    if v.shape != z.shape or out.shape != z.shape:
+        raise ValueError("v and out must have the shape of z")
+    vp, _, _, _ = _batch(net, v, "v")
+    op, _, _, _ = _batch(net, out, "out")
+    _check_cnn(net, load().ri_cnn_jvp(net.handle, zp, vp, op, B, h, w, _stream(stream)))
+
+
+def ri_cnn_vjp(net: Cnn, z, u, out, stream=None):
+    """out = J_net(z)^T u (training-mode network)."""
+    zp, B, h, w = _batch(net, z, "z")
+    if u.shape != z.shape or out.shape != z.shape:
+        raise ValueError("u and out must have the shape of z")
+    up, _, _, _ = _batch(net, u, "u")
+    op, _, _, _ = _batch(net, out, "out")
+    _check_cnn(net, load().ri_cnn_vjp(net.handle, zp, up, op, B, h, w, _stream(stream)))
+
+
+def ri_cnn_fne_norm(net: Cnn, z, iters: int = 30, seed: int = 1, stream=None) -> float:
+    """||I - 2 J_net(z)||_S by the power method (the firm-nonexpansiveness check)."""
+    zp, B, h, w = _batch(net, z, "z")
+    out = ctypes.c_double(0.0)
+    _check_cnn(net, load().ri_cnn_fne_norm(net.handle, zp, B, h, w, iters, seed, ctypes.byref(out),
+                                           _stream(stream)))
+    return out.value
 
 
 def ri_cnn_train_step(net: Cnn, clean, sigma: float, seed: int, lr: float, loss=None, stream=None):

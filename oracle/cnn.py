@@ -206,3 +206,36 @@ def fne_norm(params, z: np.ndarray, iters: int = 50, seed: int = 0, bf16: bool =
         b = a - 2.0 * vjp(params, acts, a, bf16)
         v = b / np.linalg.norm(b)
     return s
+
+
+def jvp_param_grad(params, acts, v: np.ndarray, u: np.ndarray, bf16: bool = False):
+    """Gradient of u^T J_net(z) v with respect to the parameters, [(dw, db)]
+    per layer (db = 0: the Jacobian does not depend on the biases). With the
+    ReLU masks fixed (piecewise linearity), J_net(z) v is linear in each
+    layer's weights: the gradient of layer l is the correlation of the
+    pre-activation adjoint of u at layer l with the tangent of v at layer l's
+    input, i.e. backward() run with the tangents as layer inputs while the
+    masks stay those of the activations at z."""
+    L = len(params)
+    t = v[:, None].astype(np.float64)
+    tin = []
+    for l, (w, b) in enumerate(params):
+        tin.append(t)
+        wl = bf16_round(w) if (bf16 and l > 0) else w
+        if l == L - 1:
+            break
+        t = conv3x3(t, wl, np.zeros_like(b)) * (acts[l + 1] > 0)
+        if bf16:
+            t = bf16_round(t)
+    grads = [None] * L
+    g = u[:, None].astype(np.float64)
+    for l in range(L - 1, -1, -1):
+        w, b = params[l]
+        wl = bf16_round(w) if (bf16 and l > 0) else w
+        dxv, dw, _ = conv3x3_backward(tin[l], wl, g, need_dx=l > 0)
+        grads[l] = (dw, np.zeros_like(b))
+        if l > 0:
+            g = dxv * (acts[l] > 0)
+            if bf16:
+                g = bf16_round(g)
+    return grads

@@ -146,3 +146,35 @@ def test_fne_norm_of_a_dead_network_is_one():
     ps = [(w, np.full(b.shape, -100.0) if l < len(ps) - 1 else b) for l, (w, b) in enumerate(ps)]
     z = np.random.default_rng(5).standard_normal((1, 8, 8))
     assert C.fne_norm(ps, z, iters=3) == pytest.approx(1.0, rel=1e-12)
+
+
+def test_jvp_param_grad_matches_central_differences():
+    """d(u^T J_net(z) v)/dW by central differences of the weights (FP64, away
+    from ReLU kinks), and zero for the biases."""
+    ps = _small_net(seed=9, layers=3, ch=4)
+    rng = np.random.default_rng(6)
+    z = rng.standard_normal((1, 8, 8))
+    v, u = rng.standard_normal(z.shape), rng.standard_normal(z.shape)
+
+    def f(params):
+        _, acts = C.forward(params, z)
+        return float(np.sum(u * C.jvp(params, acts, v)))
+
+    _, acts = C.forward(ps, z)
+    gr = C.jvp_param_grad(ps, acts, v, u)
+    eps = 1e-6
+    for l in range(len(ps)):
+        w, b = ps[l]
+        idx = [tuple(rng.integers(0, n) for n in w.shape) for _ in range(4)]
+        for ix in idx:
+            wp, wm = w.copy(), w.copy()
+            wp[ix] += eps
+            wm[ix] -= eps
+            psp = [p if k != l else (wp, b) for k, p in enumerate(ps)]
+            psm = [p if k != l else (wm, b) for k, p in enumerate(ps)]
+            fd = (f(psp) - f(psm)) / (2 * eps)
+            assert gr[l][0][ix] == pytest.approx(fd, rel=1e-5, abs=1e-8)
+        bp = b.copy()
+        bp[0] += 1e-3
+        assert f([p if k != l else (w, bp) for k, p in enumerate(ps)]) == pytest.approx(f(ps), rel=1e-12)
+        assert np.all(gr[l][1] == 0)

@@ -88,6 +88,25 @@ ri_status ri_cnn_vjp(ri_cnn *net, const float *z, const float *u, float *out, in
 ri_status ri_cnn_fne_norm(ri_cnn *net, const float *z, int32_t batch, int32_t h, int32_t w, int32_t iters,
                           uint64_t seed, double *norm_out, ri_stream stream);
 
+/* Gradient of u^T J_net(z) v with respect to the parameters into grads (dev,
+ * param_count floats; the bias entries are 0). With the ReLU masks of z fixed,
+ * J_net(z) v is linear in each layer's weights, so this is the parameter
+ * gradient pass run with the tangents of v as layer inputs. */
+ri_status ri_cnn_jvp_grad(ri_cnn *net, const float *z, const float *v, const float *u, int32_t batch, int32_t h,
+                          int32_t w, float *grads, ri_stream stream);
+
+/* One training step with the relaxed firm-nonexpansiveness penalty (appendix
+ * C; the paper relaxes the constraint of its training loss into a soft
+ * penalty whose form it does not give): loss mean|D(u + sigma n) - u| +
+ * lambda max(||J_{2D - I}(u + sigma n)||_S^2, 1 - eps), the norm estimated by
+ * power_iters iterations on J^T J warm-started from the previous call's
+ * vector (a seeded normal at the first call), the penalty's gradient through
+ * ri_cnn_jvp_grad's pass, one Adam update. loss, fne_sq: optional dev
+ * double[1] (the l1 term, and the squared norm estimate). */
+ri_status ri_cnn_train_step_fne(ri_cnn *net, const float *clean, int32_t batch, int32_t h, int32_t w, float sigma,
+                                uint64_t seed, float lr, float lambda, float eps, int32_t power_iters, double *loss,
+                                double *fne_sq, ri_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -494,12 +494,14 @@ __global__ void k_l1(const float *__restrict__ D, const float *__restrict__ u, f
     if (threadIdx.x == 0) part[blockIdx.x] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
 }
 
-// Backward of the last layer. dpre[p][c] = [act[p][c] > 0] sum_t bf16(W[0][c][t]) g[p - (t - centre)];
+// Backward of the last layer. dpre[p][c] = [mask[p][c] > 0] sum_t bf16(W[0][c][t]) g[p - (t - centre)]
+// with mask = mask_act if given, else act;
 // this block's share of dW[c][t] = sum_p act[p + (t - centre)][c] g[p] and db = sum_p g[p] goes to
 // row `block` of part (577 floats), summed over blocks by k_reduce_rows.
 __global__ void __launch_bounds__(256) k_out_backward(const float *__restrict__ g, const uint16_t *__restrict__ act,
                                                       const float *__restrict__ wl_, uint16_t *__restrict__ dpre,
-                                                      float *__restrict__ part, int H, int W) {
+                                                      float *__restrict__ part, int H, int W,
+                                                      const uint16_t *__restrict__ mask_act) {
     extern __shared__ uint4 smem4[];
     uint16_t *patch = reinterpret_cast<uint16_t *>(smem4);          // act patch [18*18][PADC]
     float *gp = reinterpret_cast<float *>(patch + 18 * 18 * PADC);  // g patch [18][18]
@@ -519,7 +521,10 @@ __global__ void __launch_bounds__(256) k_out_backward(const float *__restrict__ 
     float gg[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) gg[t] = gp[(ty + 2 - t / 3) * 18 + tx + 2 - t % 3];
-    const uint16_t *ac = patch + ((ty + 1) * 18 + tx + 1) * PADC;
+    // the ReLU mask comes from mask_act (the activations at z) when the layer
+    // input act is a tangent, else from act itself
+    const uint16_t *ac = mask_act ? mask_act + (img + (size_t)(y0 + ty) * W + x0 + tx) * CH
+                                  : patch + ((ty + 1) * 18 + tx + 1) * PADC;
     uint16_t *dst = dpre + (img + (size_t)(y0 + ty) * W + x0 + tx) * CH;
     for (int c8 = 0; c8 < CH; c8 += 8) {
         uint32_t o[8];
@@ -746,6 +751,17 @@ __global__ void k_minus2(const float *__restrict__ a, const float *__restrict__ 
         out[i] = a[i] - 2.f * t[i];
 }
 
+// grads[i] += coef grads2[i] over [0, n) with coef = -4 lambda when the
+// squared Jacobian norm ss[0] exceeds 1 - eps, else 0 (the gradient of
+// lambda max(||J_{2D - I}||^2, 1 - eps) through u^T J_net v, u the unnormalised
+// image of the unit v).
+__global__ void k_fne_combine(float *__restrict__ grads, const float *__restrict__ grads2, int64_t n,
+                              const double *__restrict__ ss, float lambda, float eps) {
+    const float coef = ss[0] > 1.0 - (double)eps ? -4.f * lambda : 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        grads[i] += coef * grads2[i];
+}
+
 // v /= sqrt(ss[0]) (FP64 squared norm from the reduction).
 __global__ void k_scale_rsqrt(float *__restrict__ v, int64_t n, const double *__restrict__ ss) {
     const float k = (float)(1.0 / sqrt(ss[0]));
@@ -814,6 +830,10 @@ struct ri_cnn {
     float *blkpart = nullptr;          // training: per-block partials of the first / last layer
     double *part = nullptr;
     double *scal = nullptr;            // FP64 scalars of the Jacobian-norm iteration
+    std::vector<uint16_t *> tan;       // tangents of the layers (allocated on first use)
+    float *grads2 = nullptr;           // parameter gradient of u^T J_net v
+    float *fv = nullptr;               // power-iteration vector of the penalised training
+    bool fv_ready = false;
     int64_t step = 0;
     std::string err;
     std::vector<void *> allocs;
@@ -885,26 +905,31 @@ void forward(ri_cnn *n, const float *z, float *D, int B, int h, int w, const Cnn
     RI_CHECK_HIP(hipGetLastError());
 }
 
-// Gradients of sum(g * net(z)) into n->grads (zeroed here); activations from forward().
-void backward(ri_cnn *n, const float *z, const float *g, int B, int h, int w, hipStream_t s) {
+// Parameter gradients of sum(g * f) into grads (zeroed here), where f is the
+// network (ins = the activations of forward(), zin = z) or its linearisation
+// at z applied to a tangent (ins = the tangents of jvp_store(), zin = the
+// tangent v): the same passes, the layer inputs taken from ins while the ReLU
+// masks stay those of the activations at z.
+void backward_core(ri_cnn *n, const float *zin, const float *g, const std::vector<uint16_t *> &ins, float *grads,
+                   int B, int h, int w, hipStream_t s) {
     const int L = n->L;
     dim3 grid(w / 16, h / 16, B);
-    fill_real<float>(n->grads, n->P, 0.f, s);
+    fill_real<float>(grads, n->P, 0.f, s);
     const int nblk16 = (w / 16) * (h / 16) * B;
-    hipLaunchKernelGGL(k_out_backward, grid, dim3(256), outbwd_lds(), s, g, n->act[L - 2],
-                       n->params + n->off[2 * (L - 1)], n->dpre[0], n->blkpart, h, w);
+    hipLaunchKernelGGL(k_out_backward, grid, dim3(256), outbwd_lds(), s, g, ins[L - 2],
+                       n->params + n->off[2 * (L - 1)], n->dpre[0], n->blkpart, h, w, n->act[L - 2]);
     hipLaunchKernelGGL(k_reduce_rows, dim3((CH * 9 + 1 + 255) / 256), dim3(256), 0, s, n->blkpart, nblk16, CH * 9 + 1,
-                       CH * 9 + 1, n->grads + n->off[2 * (L - 1)]);
+                       CH * 9 + 1, grads + n->off[2 * (L - 1)]);
     int cur = 0;
     const int nbx = w / 16, nby = h / 16, nb = nbx * nby * B;                  // 16 x 16 blocks (weight gradients)
     const int cby = (h + CB_ROWS - 1) / CB_ROWS, cnb = nbx * cby * B;         // 32 x 16 blocks (convolutions)
     const CnnGeo full;
     for (int l = L - 2; l >= 1; --l) {
         const int nwg = persistent_grid(n, nb);
-        hipLaunchKernelGGL(k_dw64, dim3(nwg), dim3(256), dw64_lds(), s, n->dpre[cur], n->act[l - 1], n->dwpart, h, w,
+        hipLaunchKernelGGL(k_dw64, dim3(nwg), dim3(256), dw64_lds(), s, n->dpre[cur], ins[l - 1], n->dwpart, h, w,
                            nbx, nby, nb);
         hipLaunchKernelGGL(k_dw64_reduce, dim3((9 * 4 * 4 * 256 + CH + 255) / 256), dim3(256), 0, s, n->dwpart, nwg,
-                           n->grads + n->off[2 * l], n->grads + n->off[2 * l + 1]);
+                           grads + n->off[2 * l], grads + n->off[2 * l + 1]);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<1>), dim3(persistent_grid(n, cnb)), dim3(CNT), conv64_lds(), s,
                            n->dpre[cur], n->dpre[cur ^ 1],
                            reinterpret_cast<const uint4 *>(n->wbwd + (size_t)(l - 1) * WPK * 8),
@@ -912,10 +937,15 @@ void backward(ri_cnn *n, const float *z, const float *g, int B, int h, int w, hi
                            (float *)nullptr, (int64_t)0);
         cur ^= 1;
     }
-    hipLaunchKernelGGL(k_dw_in, grid, dim3(256), 0, s, z, n->dpre[cur], n->blkpart, h, w);
+    hipLaunchKernelGGL(k_dw_in, grid, dim3(256), 0, s, zin, n->dpre[cur], n->blkpart, h, w);
     hipLaunchKernelGGL(k_reduce_rows, dim3((CH * 9 + CH + 255) / 256), dim3(256), 0, s, n->blkpart, nblk16,
-                       CH * 9 + CH, CH * 9 + CH, n->grads + n->off[0]);
+                       CH * 9 + CH, CH * 9 + CH, grads + n->off[0]);
     RI_CHECK_HIP(hipGetLastError());
+}
+
+// Gradients of sum(g * net(z)) into n->grads; activations from forward().
+void backward(ri_cnn *n, const float *z, const float *g, int B, int h, int w, hipStream_t s) {
+    backward_core(n, z, g, n->act, n->grads, B, h, w, s);
 }
 
 // J_net(z) v into out, with the activations of forward(z) (training mode):
@@ -943,6 +973,45 @@ void jvp(ri_cnn *n, const float *v, float *out, int B, int h, int w, hipStream_t
     RI_CHECK_HIP(hipGetLastError());
 }
 
+void ensure_tangent(ri_cnn *n) {
+    if (!n->tan.empty()) return;
+    const size_t npix = (size_t)n->maxB * n->maxH * n->maxW;
+    for (int l = 0; l < n->L - 1; ++l) n->tan.push_back((uint16_t *)cnn_alloc(n, sizeof(uint16_t) * npix * CH));
+    n->grads2 = (float *)cnn_alloc(n, sizeof(float) * n->P);
+    n->fv = (float *)cnn_alloc(n, sizeof(float) * npix);
+}
+
+// jvp() keeping every layer's tangent in n->tan (the layer inputs of the
+// tangent backward pass).
+void jvp_store(ri_cnn *n, const float *v, float *out, int B, int h, int w, hipStream_t s) {
+    const int L = n->L;
+    dim3 grid(w / 16, h / 16, B);
+    const int nbx = w / 16, cby = (h + CB_ROWS - 1) / CB_ROWS, cnb = nbx * cby * B;
+    const CnnGeo full;
+    hipLaunchKernelGGL(k_conv_in, grid, dim3(256), 0, s, v, n->tan[0], n->params + n->off[0], (const float *)nullptr,
+                       full, h, w, n->act[0]);
+    for (int l = 1; l <= L - 2; ++l)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<1>), dim3(persistent_grid(n, cnb)), dim3(CNT), conv64_lds(), s,
+                           n->tan[l - 1], n->tan[l],
+                           reinterpret_cast<const uint4 *>(n->wfwd + (size_t)(l - 1) * WPK * 8),
+                           (const float *)nullptr, n->act[l], full, h, w, nbx, cby, cnb, (const uint4 *)nullptr,
+                           (float *)nullptr, (int64_t)0);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv_out<false>), grid, dim3(256), convout_lds(), s, n->tan[L - 2],
+                       (const float *)nullptr, out, n->params + n->off[2 * (L - 1)], (const float *)nullptr, h, w);
+    RI_CHECK_HIP(hipGetLastError());
+}
+
+// Parameter gradient of u^T J_net(z) v into n->grads2 (weights; the bias
+// entries, which the shared passes fill with sums of the adjoints, are
+// cleared: the Jacobian does not depend on the biases). Needs forward(z).
+void jvp_grad(ri_cnn *n, const float *v, const float *u, float *tscratch, int B, int h, int w, hipStream_t s) {
+    ensure_tangent(n);
+    jvp_store(n, v, tscratch, B, h, w, s);
+    backward_core(n, v, u, n->tan, n->grads2, B, h, w, s);
+    for (int l = 0; l < n->L; ++l)
+        fill_real<float>(n->grads2 + n->off[2 * l + 1], n->off[2 * l + 2] - n->off[2 * l + 1], 0.f, s);
+}
+
 // J_net(z)^T u into out: the backward data pass of backward() without the
 // weight gradients, then the transposed first layer (FP32 weights).
 void vjp(ri_cnn *n, const float *u, float *out, int B, int h, int w, hipStream_t s) {
@@ -951,7 +1020,7 @@ void vjp(ri_cnn *n, const float *u, float *out, int B, int h, int w, hipStream_t
     const int nbx = w / 16, cby = (h + CB_ROWS - 1) / CB_ROWS, cnb = nbx * cby * B;
     const CnnGeo full;
     hipLaunchKernelGGL(k_out_backward, grid, dim3(256), outbwd_lds(), s, u, n->act[L - 2],
-                       n->params + n->off[2 * (L - 1)], n->dpre[0], n->blkpart, h, w);
+                       n->params + n->off[2 * (L - 1)], n->dpre[0], n->blkpart, h, w, n->act[L - 2]);
     int cur = 0;
     for (int l = L - 2; l >= 1; --l) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_conv64<1>), dim3(persistent_grid(n, cnb)), dim3(CNT), conv64_lds(), s,
@@ -1261,6 +1330,78 @@ ri_status ri_cnn_fne_norm(ri_cnn *n, const float *z, int32_t B, int32_t h, int32
         RI_CHECK_HIP(hipMemcpyAsync(&ss, n->scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
         RI_CHECK_HIP(hipStreamSynchronize(s));
         *norm_out = std::sqrt(ss);
+    });
+}
+
+ri_status ri_cnn_jvp_grad(ri_cnn *n, const float *z, const float *v, const float *u, int32_t B, int32_t h, int32_t w,
+                          float *grads, ri_stream stream) {
+    if (!n || !z || !v || !u || !grads) return RI_EINVAL;
+    return cnn_guard(n, [&] {
+        if (!n->training) throw Error(RI_EINVAL, "network created without training buffers");
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        check_shape(n, B, h, w);
+        forward(n, z, n->D, B, h, w, CnnGeo(), s);
+        jvp_grad(n, v, u, n->D, B, h, w, s);
+        RI_CHECK_HIP(hipMemcpyAsync(grads, n->grads2, sizeof(float) * n->P, hipMemcpyDeviceToDevice, s));
+    });
+}
+
+ri_status ri_cnn_train_step_fne(ri_cnn *n, const float *clean, int32_t B, int32_t h, int32_t w, float sigma,
+                                uint64_t seed, float lr, float lambda, float eps, int32_t power_iters, double *loss,
+                                double *fne_sq, ri_stream stream) {
+    if (!n || !clean) return RI_EINVAL;
+    return cnn_guard(n, [&] {
+        if (!n->training) throw Error(RI_EINVAL, "network created without training buffers");
+        if (!(sigma >= 0.f) || !(lr > 0.f) || !(lambda >= 0.f) || !(eps >= 0.f && eps < 1.f) || power_iters < 0)
+            throw Error(RI_EINVAL, "sigma >= 0, lr > 0, lambda >= 0, 0 <= eps < 1, power_iters >= 0 required");
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        check_shape(n, B, h, w);
+        ensure_tangent(n);
+        const int64_t np = (int64_t)B * h * w;
+        // the l1 loss and its gradient, as in ri_cnn_train_step
+        hipLaunchKernelGGL(k_noisy, dim3(gridn(np)), dim3(256), 0, s, clean, n->zin, np, sigma, seed);
+        forward(n, n->zin, n->D, B, h, w, CnnGeo(), s);
+        hipLaunchKernelGGL(k_l1, dim3(1024), dim3(256), 0, s, n->D, clean, n->g, np, n->part);
+        if (loss) reduce_partials(n->part, 1024, 1, 1, loss, s);
+        backward(n, n->zin, n->g, B, h, w, s);
+        // ||J_{2D - I}(z)||_S at the training input by power iterations on
+        // J^T J, warm-started from the previous step's vector
+        float *v = n->fv, *t = n->D, *a = n->g;
+        if (!n->fv_ready) {
+            hipLaunchKernelGGL(k_normal, dim3(gridn(np)), dim3(256), 0, s, v, np, seed ^ 0x9E3779B97F4A7C15ull);
+            n->fv_ready = true;
+        }
+        auto normalise = [&](float *x) {
+            dot_partials<float>(x, x, np, n->part, s);
+            reduce_partials(n->part, 1024, 1, 1, n->scal, s);
+            hipLaunchKernelGGL(k_scale_rsqrt, dim3(gridn(np)), dim3(256), 0, s, x, np, n->scal);
+        };
+        normalise(v);
+        for (int it = 0; it < power_iters; ++it) {
+            jvp(n, v, t, B, h, w, s);
+            hipLaunchKernelGGL(k_minus2, dim3(gridn(np)), dim3(256), 0, s, v, t, a, np);
+            vjp(n, a, t, B, h, w, s);
+            hipLaunchKernelGGL(k_minus2, dim3(gridn(np)), dim3(256), 0, s, a, t, v, np);
+            normalise(v);
+        }
+        // a = (I - 2 J_net) v, ||a||^2 (v unit), and d(a^T J_net v)/dtheta
+        jvp_store(n, v, t, B, h, w, s);
+        hipLaunchKernelGGL(k_minus2, dim3(gridn(np)), dim3(256), 0, s, v, t, a, np);
+        dot_partials<float>(a, a, np, n->part, s);
+        reduce_partials(n->part, 1024, 1, 1, n->scal + 1, s);
+        backward_core(n, v, a, n->tan, n->grads2, B, h, w, s);
+        for (int l = 0; l < n->L; ++l)   // weights only: the penalty does not depend on the biases
+            hipLaunchKernelGGL(k_fne_combine, dim3(gridn(n->off[2 * l + 1] - n->off[2 * l])), dim3(256), 0, s,
+                               n->grads + n->off[2 * l], n->grads2 + n->off[2 * l], n->off[2 * l + 1] - n->off[2 * l],
+                               n->scal + 1, lambda, eps);
+        if (fne_sq) RI_CHECK_HIP(hipMemcpyAsync(fne_sq, n->scal + 1, sizeof(double), hipMemcpyDeviceToDevice, s));
+        n->step++;
+        const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, (double)n->step)));
+        const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, (double)n->step)));
+        hipLaunchKernelGGL(k_adam, dim3(gridn(n->P)), dim3(256), 0, s, n->params, n->grads, n->m, n->v, n->P, lr, c1,
+                           c2);
+        repack(n, s);
+        RI_CHECK_HIP(hipGetLastError());
     });
 }
 

@@ -26,7 +26,7 @@ EXPORTS = ("ri_create", "ri_destroy", "ri_last_error", "phi_forward", "phi_adjoi
            "ri_get_plan_stats", "ri_get_plan_arrays", "ri_profile", "ri_profile_read",
            "ri_cnn_create", "ri_cnn_destroy", "ri_cnn_last_error", "ri_cnn_param_count", "ri_cnn_set_params",
            "ri_cnn_get_params", "ri_cnn_forward", "ri_cnn_grad", "ri_cnn_train_step", "ri_cnn_jvp", "ri_cnn_vjp",
-           "ri_cnn_fne_norm")
+           "ri_cnn_fne_norm", "ri_cnn_jvp_grad", "ri_cnn_train_step_fne")
 
 
 class RIError(RuntimeError):
@@ -125,6 +125,13 @@ def load() -> ctypes.CDLL:
     L.ri_cnn_fne_norm.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, ctypes.c_uint64, c_void_p,
                                   c_void_p]
     L.ri_cnn_fne_norm.restype = st
+    L.ri_cnn_jvp_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
+                                  c_void_p]
+    L.ri_cnn_jvp_grad.restype = st
+    L.ri_cnn_train_step_fne.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, ctypes.c_float,
+                                        ctypes.c_uint64, ctypes.c_float, ctypes.c_float, ctypes.c_float, c_int32,
+                                        c_void_p, c_void_p, c_void_p]
+    L.ri_cnn_train_step_fne.restype = st
     _lib = L
     return L
 
@@ -451,6 +458,29 @@ def ri_cnn_fne_norm(net: Cnn, z, iters: int = 30, seed: int = 1, stream=None) ->
     _check_cnn(net, load().ri_cnn_fne_norm(net.handle, zp, B, h, w, iters, seed, ctypes.byref(out),
                                            _stream(stream)))
     return out.value
+
+
+def ri_cnn_jvp_grad(net: Cnn, z, v, u, grads, stream=None):
+    """grads = d(u^T J_net(z) v) / d params (bias entries 0)."""
+    import torch
+    zp, B, h, w = _batch(net, z, "z")
+    if v.shape != z.shape or u.shape != z.shape:
+        raise ValueError("v and u must have the shape of z")
+    vp, _, _, _ = _batch(net, v, "v")
+    up, _, _, _ = _batch(net, u, "u")
+    _check_cnn(net, load().ri_cnn_jvp_grad(net.handle, zp, vp, up, B, h, w,
+                                           _dev(grads, torch.float32, net.n_params, "grads"), _stream(stream)))
+
+
+def ri_cnn_train_step_fne(net: Cnn, clean, sigma: float, seed: int, lr: float, lam: float, eps: float = 0.05,
+                          power_iters: int = 2, loss=None, fne_sq=None, stream=None):
+    """Training step with the relaxed firm-nonexpansiveness penalty."""
+    import torch
+    cp, B, h, w = _batch(net, clean, "clean")
+    lp = _dev(loss, torch.float64, 1, "loss") if loss is not None else None
+    fp = _dev(fne_sq, torch.float64, 1, "fne_sq") if fne_sq is not None else None
+    _check_cnn(net, load().ri_cnn_train_step_fne(net.handle, cp, B, h, w, sigma, seed, lr, lam, eps, power_iters,
+                                                 lp, fp, _stream(stream)))
 
 
 def ri_cnn_train_step(net: Cnn, clean, sigma: float, seed: int, lr: float, loss=None, stream=None):

@@ -19,11 +19,16 @@ from . import ri as R
 
 
 def train_denoiser(patches, sigma: float, steps: int = 2000, batch: int = 16, lr: float = 1e-3,
-                   lr_min: float = 1e-5, layers: int = 10, seed: int = 5, log_every: int = 0, log=None):
+                   lr_min: float = 1e-5, layers: int = 10, seed: int = 5, log_every: int = 0, log=None,
+                   fne_lambda: float = 0.0, fne_eps: float = 0.05, fne_iters: int = 2, fne_every: int = 1):
     """Train a fresh network on ``patches`` (float32 GPU tensor [n, s, s], s a
     multiple of 16) at noise level ``sigma``. Returns (params, history) with
     params the FP32 GPU parameter vector (ri_cnn layout) and history a list of
-    (step, loss, seconds)."""
+    (step, loss, seconds, squared Jacobian-norm estimate or None).
+
+    fne_lambda > 0 adds the relaxed firm-nonexpansiveness penalty
+    fne_lambda max(||J_{2D - I}||_S^2, 1 - fne_eps) every fne_every steps
+    (fne_iters warm-started power iterations per penalised step)."""
     import torch
     n, s, s2 = patches.shape
     if s != s2 or s % 16:
@@ -32,6 +37,7 @@ def train_denoiser(patches, sigma: float, steps: int = 2000, batch: int = 16, lr
     net = R.ri_cnn_create(layers=layers, max_batch=batch, max_h=s, max_w=s, training=True, seed=seed)
     rng = np.random.default_rng(seed)
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    fsq = torch.zeros(1, dtype=torch.float64, device=dev)
     buf = torch.empty((batch, s, s), dtype=torch.float32, device=dev)
     hist = []
     t0 = time.perf_counter()
@@ -44,11 +50,18 @@ def train_denoiser(patches, sigma: float, steps: int = 2000, batch: int = 16, lr
         b = torch.rot90(b, k & 3, dims=(1, 2))
         buf.copy_(b)
         rate = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * it / max(1, steps)))
-        R.ri_cnn_train_step(net, buf, sigma, int(seed) * 1_000_003 + it, rate, loss)
+        fne_step = fne_lambda > 0 and it % fne_every == 0
+        if fne_step:
+            R.ri_cnn_train_step_fne(net, buf, sigma, int(seed) * 1_000_003 + it, rate, fne_lambda, fne_eps, fne_iters,
+                                    loss, fsq)
+        else:
+            R.ri_cnn_train_step(net, buf, sigma, int(seed) * 1_000_003 + it, rate, loss)
         if log_every and (it % log_every == 0 or it == steps - 1):
-            hist.append((it, float(loss.item()), time.perf_counter() - t0))
+            hist.append((it, float(loss.item()), time.perf_counter() - t0,
+                         float(fsq.item()) if fne_lambda > 0 else None))
             if log:
-                log(f"train step {it}: loss {hist[-1][1]:.4e} ({hist[-1][2]:.1f} s)")
+                extra = f", ||J||^2 {hist[-1][3]:.3f}" if fne_lambda > 0 else ""
+                log(f"train step {it}: loss {hist[-1][1]:.4e}{extra} ({hist[-1][2]:.1f} s)")
     params = torch.empty(net.n_params, dtype=torch.float32, device=dev)
     R.ri_cnn_get_params(net, params)
     torch.cuda.synchronize()

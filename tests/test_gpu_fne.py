@@ -96,3 +96,52 @@ def test_fne_norm_closed_form(a):
     s = R.ri_cnn_fne_norm(net, z, iters=10, seed=5)
     print(f"a = {a}: ||I - 2 J_net||_S = {s:.5f} (closed form {abs(1 - 2 * a):.5f})")
     assert s == pytest.approx(abs(1 - 2 * a), rel=1e-2)
+
+
+def test_jvp_param_grad_matches_oracle():
+    """d(u^T J_net(z) v)/d params (the penalty's gradient pass: the parameter
+    gradient pass fed with the tangents of v) against the oracle."""
+    net, ps = _net(seed=33)
+    z, _, _ = _inputs(B=2, h=32, w=32, seed=13)
+    rng = np.random.default_rng(14)
+    v = rng.uniform(0, 1, z.shape).astype(np.float32)
+    u = rng.uniform(0, 1, z.shape).astype(np.float32)
+    grads = torch.empty(net.n_params, dtype=torch.float32, device=DEV)
+    R.ri_cnn_jvp_grad(net, torch.tensor(z, device=DEV), torch.tensor(v, device=DEV), torch.tensor(u, device=DEV),
+                      grads)
+    _, acts = OC.forward(ps, z.astype(np.float64), bf16=True)
+    ref = OC.jvp_param_grad(ps, acts, v.astype(np.float64), u.astype(np.float64), bf16=True)
+    g = grads.cpu().numpy().astype(np.float64)
+    off = 0
+    errs = []
+    for l, (w, b) in enumerate(ref):
+        gw = g[off:off + w.size].reshape(w.shape)
+        off += w.size
+        gb = g[off:off + b.size]
+        off += b.size
+        assert np.all(gb == 0.0)
+        errs.append(rel(gw, w))
+    print("d(u^T J v)/dW per layer, rel:", " ".join(f"{e:.1e}" for e in errs))
+    assert max(errs) <= 3e-2
+
+
+def test_penalty_lowers_the_jacobian_norm():
+    """The relaxed firm-nonexpansiveness penalty (lambda 1e-3, every fourth
+    step, four warm-started power iterations) lowers ||J_{2D - I}||_S of the
+    trained network on held-out noisy patches."""
+    from paper_2207_11336_amd.train import train_denoiser
+    sig = 1e-2
+    patches = torch.tensor(synth.training_patches(512, 64, seed=synth.SEED_TRAIN), device=DEV)
+    test = synth.training_patches(4, 64, seed=98)
+    noisy = torch.tensor((test + sig * np.random.default_rng(6).standard_normal(test.shape)).astype(np.float32),
+                         device=DEV)
+    norms = {}
+    for lam in (0.0, 1e-3):
+        params, _ = train_denoiser(patches, sig, steps=1500, batch=16, lr=1e-3, lr_min=1e-5, fne_lambda=lam,
+                                   fne_iters=4, fne_every=4)
+        net = R.ri_cnn_create(layers=L, max_batch=4, max_h=64, max_w=64, training=True)
+        R.ri_cnn_set_params(net, params)
+        norms[lam] = R.ri_cnn_fne_norm(net, noisy, iters=30, seed=3)
+        net.close()
+    print(f"||J_(2D-I)||_S on held-out noisy patches: plain l1 {norms[0.0]:.3f}, with the penalty {norms[1e-3]:.3f}")
+    assert norms[1e-3] < 0.85 * norms[0.0]

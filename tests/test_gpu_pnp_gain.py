@@ -32,7 +32,7 @@ SIGMA = 1e-2
 def trained():
     patches = torch.tensor(synth.training_patches(1024, 64, seed=synth.SEED_TRAIN), device=DEV)
     params, hist = train_denoiser(patches, SIGMA, steps=2000, batch=16, lr=1e-3, lr_min=1e-5, log_every=500)
-    print("training loss", [(s, round(l, 6)) for s, l, _ in hist])
+    print("training loss", [(h[0], round(h[1], 6)) for h in hist])
     return params
 
 

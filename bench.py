@@ -166,7 +166,8 @@ def run_pnp(args, R, synth, ctx, noise, x_true, L):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     params, hist = train_denoiser(patches, sigma, steps=args.train_steps, batch=args.train_batch, lr=args.train_lr,
-                                  lr_min=args.train_lr / 100, log_every=max(1, args.train_steps // 4), log=log)
+                                  lr_min=args.train_lr / 100, log_every=max(1, args.train_steps // 4), log=log,
+                                  fne_lambda=args.fne_lambda, fne_iters=4, fne_every=args.fne_every)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     del patches
@@ -229,7 +230,7 @@ def run_pnp(args, R, synth, ctx, noise, x_true, L):
            "denoiser_roofline": {"bound": "mfma", "achieved": den_tfs, "peak": BF16_PEAK_TFS, "unit": "TFLOP/s",
                                  "frac": den_tfs / BF16_PEAK_TFS, "flops_per_application": cnn_flops(nf * side * side),
                                  "kernels": "k_conv_in, 7 x k_conv64<0>, k_conv64<2>, k_conv_sum (one application)"},
-           "fne_norm_patches": fne_patches, "fne_norm_fixed_point": fne_fixed,
+           "fne_norm_patches": fne_patches, "fne_norm_fixed_point": fne_fixed, "fne_lambda": args.fne_lambda,
            "train_steps": args.train_steps, "train_batch": args.train_batch, "train_s": train_s,
            "train_tflops": train_flops / train_s / 1e12, "train_final_loss": hist[-1][1] if hist else None}
     log(f"PnP x{rep.iters}: {rep.ms:.1f} ms ({res['pnp_ms_per_iter']:.3f} ms/it), SNR {rep.snr_db:.2f} dB vs FB "
@@ -263,6 +264,9 @@ def main():
                     help="image-domain noise level of the PnP comparison (1 / target dynamic range)")
     ap.add_argument("--train-batch", type=int, default=16)
     ap.add_argument("--train-patches", type=int, default=1024)
+    ap.add_argument("--fne-lambda", type=float, default=0.0,
+                    help="weight of the relaxed firm-nonexpansiveness penalty in the denoiser training (0: off)")
+    ap.add_argument("--fne-every", type=int, default=4, help="penalised training step every this many steps")
     ap.add_argument("--facet-core", type=int, default=None,
                     help="CNN facet core side (0: whole image in one tile; default: the workload's)")
     ap.add_argument("--facet-halo", type=int, default=None)

@@ -264,7 +264,7 @@ def main():
                     help="image-domain noise level of the PnP comparison (1 / target dynamic range)")
     ap.add_argument("--train-batch", type=int, default=16)
     ap.add_argument("--train-patches", type=int, default=1024)
-    ap.add_argument("--fne-lambda", type=float, default=0.0,
+    ap.add_argument("--fne-lambda", type=float, default=1e-6,
                     help="weight of the relaxed firm-nonexpansiveness penalty in the denoiser training (0: off)")
     ap.add_argument("--fne-every", type=int, default=4, help="penalised training step every this many steps")
     ap.add_argument("--facet-core", type=int, default=None,

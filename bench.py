@@ -240,6 +240,56 @@ def run_pnp(args, R, synth, ctx, noise, x_true, L):
     return res
 
 
+def run_holo(args, R, wl, uvw, x_true):
+    """Phi^dagger Phi through the stored holographic matrix (appendix E) against
+    the pass over the visibilities (the fused gradient with y = 0), FP32, on
+    the same plan: build time and storage, per-application times, the
+    banded-product kernel's HBM rate."""
+    import torch
+    ctx = R.ri_create(R.plan_desc(wl.N, wl.M, cell_rad=wl.cell_rad, w_max=wl.W, n_wplanes=wl.n_wplanes,
+                                  precision=32, g_mode=R.RI_G_OTF, tile=args.tile, item_vis=args.item_vis), uvw)
+    R.ri_holo_build(ctx)
+    s = R.ri_holo_get_stats(ctx)
+    log(f"[holo] H: {s.tiles} tiles, {s.bytes / 1e9:.2f} GB, reach {s.max_reach}, {s.pairs:.3e} pairs, "
+        f"build {s.build_ms:.0f} ms")
+    out, g = torch.empty_like(x_true), torch.empty_like(x_true)
+    for _ in range(max(1, args.warmup)):
+        R.ri_holo_normal(ctx, x_true, out)
+        R.ri_gradient(ctx, x_true, "none", g)
+    torch.cuda.synchronize()
+    K = max(1, args.steps)
+    res = {}
+    for name, fn in (("holo", lambda: R.ri_holo_normal(ctx, x_true, out)),
+                     ("visibilities", lambda: R.ri_gradient(ctx, x_true, "none", g))):
+        R.ri_profile(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            fn()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kt = R.ri_profile_read(ctx)
+        R.ri_profile(ctx, False)
+        res[name] = {"ms": 1e3 * el / K, "kernel_ms": kt.tiles_ms / max(1, kt.n_tiles),
+                     "fft_ms": kt.fft_ms / max(1, kt.n_fft)}
+    err = float(torch.linalg.vector_norm((out - g).double()) / torch.linalg.vector_norm(g.double()))
+    apply_ms = res["holo"]["kernel_ms"]
+    gbs = s.bytes / (apply_ms * 1e-3) / 1e9
+    rep = {"tiles": s.tiles, "bytes": s.bytes, "reach": s.max_reach, "build_ms": s.build_ms, "pairs": s.pairs,
+           "normal_ms": res["holo"]["ms"], "apply_kernel_ms": apply_ms, "apply_gbs": gbs,
+           "apply_frac_hbm": gbs / HBM_PEAK_GBS, "vis_pass_normal_ms": res["visibilities"]["ms"],
+           "vis_pass_kernel_ms": res["visibilities"]["kernel_ms"], "rel_diff": err,
+           "break_even_M": wl.M * apply_ms / res["visibilities"]["kernel_ms"]}
+    log(f"[holo] normal through H {rep['normal_ms']:.3f} ms (banded product {apply_ms:.3f} ms, {gbs:.0f} GB/s = "
+        f"{100 * rep['apply_frac_hbm']:.1f}% of HBM peak) vs pass over the visibilities {rep['vis_pass_normal_ms']:.3f}"
+        f" ms (tile kernel {rep['vis_pass_kernel_ms']:.3f} ms); rel diff {err:.2e}; break-even M "
+        f"{rep['break_even_M']:.3e}")
+    R.ri_holo_release(ctx)
+    ctx.close()
+    torch.cuda.empty_cache()
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +301,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="uv tile side (0: autotuned by the library)")
     ap.add_argument("--item-vis", type=int, default=0, help="visibilities per work item (0: library default)")
     ap.add_argument("--wstacks", type=int, default=0, help="w-stacks of the hybrid (0 or 1: w-kernels alone)")
+    ap.add_argument("--no-holo", action="store_true",
+                    help="skip building the holographic matrix H = G^H G and timing Phi^dagger Phi through it")
+    ap.add_argument("--holo-only", action="store_true", help="only the holographic measurement")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
@@ -336,6 +389,9 @@ def main():
     noise = torch.tensor(synth.noise_normals(M), dtype=torch.complex64, device=dev)
     modes = ["otf", "csr"] if args.mode == "auto" else [args.mode]
     shared = {}
+    if args.holo_only:
+        print(json.dumps({"workload": wl.name, "holographic": run_holo(args, R, wl, uvw, x_true)}), flush=True)
+        return
 
     def run_mode(mode):
         g_mode = R.RI_G_CSR if mode == "csr" else R.RI_G_OTF
@@ -465,6 +521,8 @@ def main():
         del yb
         torch.cuda.empty_cache()
 
+    holo = None if args.no_holo else run_holo(args, R, wl, uvw, x_true)
+
     cpu = None
     if not args.no_cpu:
         log(f"CPU oracle baseline on {args.cpu_sample:,} visibilities ...")
@@ -479,7 +537,7 @@ def main():
                    "w_stacks": max(args.wstacks, 1),
                    "tile": best["tile"], "step": "fb_step: fused gradient + Haar-l1 prox + FP64 norms",
                    "fp64_gram_vis_per_s": fp64_rate, "plan_s": plan_s, "L": L, "snr_db": snr, **extra,
-                   "fb_time_to_snr": fb_trace, "pnp": pnp},
+                   "fb_time_to_snr": fb_trace, "pnp": pnp, "holographic": holo},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

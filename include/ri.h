@@ -202,6 +202,43 @@ typedef struct {
 ri_status pnp_solve(ri_ctx *ctx, const void *y, const ri_solve_opts *opts, void *x_out,
                     ri_solve_report *report);
 
+/* Holographic form of the normal operator (appendix E): with the data in
+ * blocks p, Phi^dagger Phi = Z^dagger F^dagger H F Z with H = sum_p G_p^H G_p
+ * (eq. E2), an N'^2 x N'^2 grid operator whose size follows the uv coverage
+ * and the window sides, not the number of visibilities. H is banded: entry
+ * H[k][k'] vanishes unless one window holds both cells (per axis
+ * |k - k'| <= largest window side - 1).
+ *
+ * ri_holo_build accumulates H on the device from the context's plan (FP64
+ * window weights, stored in the context precision) and keeps it in the
+ * context: the upper half of the band of every 32 x 32 grid tile that some
+ * window touches, the lower half being its conjugate transpose. Replaces a
+ * previous H. Synchronous. RI_EUNSUPPORTED with w-stacking (n_wstacks > 1) or
+ * when a tile's band does not fit the workgroup LDS; RI_ENOMEM when H does
+ * not fit the device. ri_holo_release frees it (also done by ri_destroy). */
+ri_status ri_holo_build(ri_ctx *ctx, ri_stream stream);
+ri_status ri_holo_release(ri_ctx *ctx);
+
+/* Y = H X on the fine grid. X, Y: dev [N'][N'] complex (context precision),
+ * row-major [ky][kx] with the image centre at cell 0 (frequency index k at
+ * k mod N'); Y is overwritten; X and Y may not alias. RI_EINVAL before
+ * ri_holo_build. */
+ri_status ri_holo_apply(ri_ctx *ctx, const void *X, void *Y, ri_stream stream);
+
+/* out = Re{Phi^dagger Phi} x = Re{Z^dagger F^dagger H F Z} x through H (no pass
+ * over the visibilities). x, out: dev [N][N] real (context precision). */
+ri_status ri_holo_normal(ri_ctx *ctx, const void *x, void *out, ri_stream stream);
+
+typedef struct {
+    int64_t tiles;         /* stored 32 x 32 grid tiles */
+    int64_t entries;       /* stored complex entries (upper half of each tile's band) */
+    int64_t bytes;         /* device bytes of those entries */
+    int64_t pairs;         /* window-cell pairs accumulated by the build */
+    int32_t max_reach;     /* largest band half-width R over the tiles */
+    double build_ms;       /* wall time of the last ri_holo_build */
+} ri_holo_stats;
+ri_status ri_holo_get_stats(const ri_ctx *ctx, ri_holo_stats *out);
+
 /* Plan statistics for tests and the benchmark. */
 typedef struct {
     int64_t M, nnz;        /* visibilities, stored/implied G entries */

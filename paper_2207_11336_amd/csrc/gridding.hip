@@ -17,6 +17,12 @@
 // order; on the fly, lane c of the group owns window column c, holds g_u[c]
 // and g_v[c] in registers and receives each row weight by a DPP broadcast,
 // so the weights never pass through LDS.
+//
+// The same row weights fill the stored G (k_fill_csr) and the holographic
+// matrix H = G^H G of appendix E (k_fill_holo; its storage and banded product
+// are in holo.hip).
+#include <numeric>
+
 #include "ri_internal.h"
 
 namespace ri {
@@ -388,6 +394,59 @@ __global__ void __launch_bounds__(256) k_fill_csr(TileArgs<double> a, int64_t M,
     }
 }
 
+// H = G^H G (appendix E), row by row of G: every pair of cells k, k + d of
+// the window with d in the stored upper half (dy > 0, or dy = 0 and dx >= 0)
+// adds conj(G[m, k]) G[m, k + d] = conj(g_v[ay] g_u[ax]) g_v[by] g_u[bx] to
+// H[k][k + d] (FP64 products, added in T by device-scope atomics). The 16
+// lanes of a group take consecutive window columns ax of one offset, so each
+// atomic instruction lands on one or two cache lines of an offset plane.
+// Visibility i of the launch is m = i * stride mod M (stride coprime to M):
+// groups in flight work on windows far apart in the tile-sorted order and
+// rarely add to the same entries at once.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill_holo(TileArgs<double> a, int64_t M, int64_t stride,
+                                                   const int32_t *tmap, const int4 *tinfo, const int64_t *off,
+                                                   cx<T> *H) {
+    __shared__ double kbs[GROUPS * SCR_KB];
+    __shared__ cx<double> wks[GROUPS * SCR_W];
+    __shared__ cx<double> gs[GROUPS * SCR_G];
+    const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
+    double *kbg = kbs + grp * SCR_KB;
+    cx<double> *wk = wks + grp * SCR_W;
+    cx<double> *gg = gs + grp * SCR_G;
+    const int Npm = (1 << a.logNp) - 1, ntx = 1 << (a.logNp - 5);
+    for (int64_t i = (int64_t)blockIdx.x * GROUPS + grp; i < M; i += (int64_t)gridDim.x * GROUPS) {
+        const int64_t m = (int64_t)((uint64_t)i * (uint64_t)stride % (uint64_t)M);   // M < 2^31
+        const uint2 rec = a.rec[m];
+        const int cu = (int)(rec.x & 0xFFFFu), cv = (int)(rec.x >> 16);
+        const int pl = (int)(rec.y & 0xFFFFu), h = (int)((rec.y >> 16) & 0xFu);
+        const int S = 2 * h + 7;
+        axis_weights<double>(a, (int)m, pl, h, S, lane, kbg, wk, gg);
+        for (int ay = 0; ay < S; ++ay) {
+            const int ky = (cv + ay - h - 3) & Npm;
+            const int trow = (ky >> 5) * ntx, cyl = (ky & 31) * 32;
+            const cx<double> gva = conjg(gg[18 + ay]);
+            for (int by = ay; by < S; ++by) {
+                const cx<double> pv = gva * gg[18 + by];
+                const int dy = by - ay;
+                for (int dx = dy == 0 ? 0 : 1 - S; dx < S; ++dx) {
+                    const int axlo = max(0, -dx), axhi = min(S, S - dx);
+                    for (int ax = axlo + lane; ax < axhi; ax += 16) {
+                        const int kx = (cu + ax - h - 3) & Npm;
+                        const int slot = tmap[trow + (kx >> 5)];
+                        const int R = tinfo[slot].z;
+                        const cx<double> v = pv * mulc(gg[ax + dx], gg[ax]);
+                        cx<T> *dst = H + off[slot] + ((int64_t)(dy * (2 * R + 1) + dx + R) << 10) + cyl + (kx & 31);
+                        global_add(&dst->x, (T)v.x);
+                        global_add(&dst->y, (T)v.y);
+                    }
+                }
+            }
+        }
+        wave_sync();
+    }
+}
+
 template <typename T>
 TileArgs<T> make_args(ri_ctx *c, const View &v, Prec<T> &p) {
     TileArgs<T> a{};
@@ -494,11 +553,28 @@ void fill_csr(ri_ctx *c, hipStream_t s) {
     }
 }
 
+template <typename T>
+void fill_holo(ri_ctx *c, const View &v, hipStream_t s) {
+    if (v.frac_bytes != 8) throw Error(RI_EINVAL, "holographic build needs FP64 fractions");
+    ensure_prec<double>(c, c->p64);
+    TileArgs<double> a = make_args<double>(c, v, c->p64);
+    if (c->M > 0) {
+        int nwg = (int)std::min<int64_t>((c->M + GROUPS - 1) / GROUPS, (int64_t)c->dev.cu_count * 16);
+        int64_t stride = std::max<int64_t>(1, (int64_t)(0.6180339887498949 * (double)c->M));
+        while (std::gcd(stride, c->M) != 1) ++stride;
+        hipLaunchKernelGGL(k_fill_holo<T>, dim3(nwg), dim3(256), 0, s, a, c->M, stride, c->holo.tmap,
+                           c->holo.tinfo, c->holo.off, (cx<T> *)c->holo.val);
+        RI_CHECK_HIP(hipGetLastError());
+    }
+}
+
 template void launch_tiles<float>(ri_ctx *, const View &, Prec<float> &, int, bool, const cx<float> *,
                                   const cx<float> *, cx<float> *, double *, hipStream_t);
 template void launch_tiles<double>(ri_ctx *, const View &, Prec<double> &, int, bool, const cx<double> *,
                                    const cx<double> *, cx<double> *, double *, hipStream_t);
 template void fill_csr<float>(ri_ctx *, hipStream_t);
 template void fill_csr<double>(ri_ctx *, hipStream_t);
+template void fill_holo<float>(ri_ctx *, const View &, hipStream_t);
+template void fill_holo<double>(ri_ctx *, const View &, hipStream_t);
 
 }  // namespace ri

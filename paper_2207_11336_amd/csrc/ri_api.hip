@@ -166,6 +166,7 @@ void build_main_view(ri_ctx *c, int tile) {
     free_view(c, c->view);
     if (c->csr.val) {
         dev_free(c, c->csr.rowptr); dev_free(c, c->csr.val); dev_free(c, c->csr.col);
+    holo_free(c);
         c->csr = CSR();
     }
     build_view(c, c->view, tile, f64frac ? 8 : 4);
@@ -573,6 +574,7 @@ void ri_destroy(ri_ctx *c) {
     free_view(c, c->view);
     free_view(c, c->view64);
     dev_free(c, c->csr.rowptr); dev_free(c, c->csr.val); dev_free(c, c->csr.col);
+    holo_free(c);
     auto freep = [c](auto &p) {
         dev_free(c, p.icorr); dev_free(c, p.tw); dev_free(c, p.wtaps); dev_free(c, p.gridA); dev_free(c, p.gridB);
         dev_free(c, p.chirp);
@@ -790,6 +792,64 @@ ri_status ri_get_plan_stats(const ri_ctx *c, ri_plan_stats *o) {
         o->tuned_ms[o->n_tuned] = t.second;
         o->n_tuned++;
     }
+    return RI_OK;
+}
+
+ri_status ri_holo_build(ri_ctx *c, ri_stream s) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        if (c->P > 1) throw Error(RI_EUNSUPPORTED, "holographic matrices with w-stacking are not implemented");
+        holo_build(c, view_fp64(c), st(s));
+    });
+}
+
+ri_status ri_holo_release(ri_ctx *c) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        RI_CHECK_HIP(hipDeviceSynchronize());
+        holo_free(c);
+    });
+}
+
+ri_status ri_holo_apply(ri_ctx *c, const void *X, void *Y, ri_stream s) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        require(X && Y, "X or Y is NULL");
+        require(X != Y, "X and Y may not alias");
+        require(c->holo.ready, "no holographic matrix: call ri_holo_build first");
+        if (c->d.precision == 32) holo_apply<float>(c, (const cx<float> *)X, (cx<float> *)Y, st(s));
+        else holo_apply<double>(c, (const cx<double> *)X, (cx<double> *)Y, st(s));
+    });
+}
+
+ri_status ri_holo_normal(ri_ctx *c, const void *x, void *out, ri_stream s) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        require(x && out, "x or out is NULL");
+        require(c->holo.ready, "no holographic matrix: call ri_holo_build first");
+        if (c->d.precision == 32) {
+            Prec<float> &p = c->p32;
+            fwd_zpad_fft<float>(c, p, (const float *)x, st(s));
+            holo_apply<float>(c, p.gridB, p.gridA, st(s));
+            adj_fft_crop<float>(c, p, (float *)out, st(s));
+        } else {
+            Prec<double> &p = c->p64;
+            fwd_zpad_fft<double>(c, p, (const double *)x, st(s));
+            holo_apply<double>(c, p.gridB, p.gridA, st(s));
+            adj_fft_crop<double>(c, p, (double *)out, st(s));
+        }
+    });
+}
+
+ri_status ri_holo_get_stats(const ri_ctx *c, ri_holo_stats *o) {
+    if (!c || !o) return RI_EINVAL;
+    const Holo &h = c->holo;
+    o->tiles = h.n_slots;
+    o->entries = h.entries;
+    o->bytes = h.entries * (c->d.precision == 64 ? 16 : 8);
+    o->pairs = h.pairs;
+    o->max_reach = h.max_R;
+    o->build_ms = h.build_ms;
     return RI_OK;
 }
 

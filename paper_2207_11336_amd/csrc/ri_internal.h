@@ -76,6 +76,27 @@ template <typename T> struct Prec {
     cx<T> *ydata = nullptr;       // stored data, internal order
 };
 
+// Holographic matrix H = G^H G on the fine grid (appendix E), kept for the
+// 32 x 32-cell tiles of the grid that some window touches. Slot s (tile
+// origin ty0, tx0) stores the upper half of H's band, offsets d = (dy, dx)
+// with dy in [0, R_s], dx in [-R_s, R_s] (R_s + 1 = the largest window side
+// over the visibilities touching the tile; dy = 0, dx < 0 stays zero since
+// H[k + d][k] = conj H[k][k + d]), one 1024-cell plane per offset:
+//   H[k][k + d] at off[s] + ((dy (2 R_s + 1) + dx + R_s) << 10) + (ky & 31) * 32 + (kx & 31).
+constexpr int HOLO_T = 32;
+struct Holo {
+    bool ready = false;
+    int n_slots = 0;
+    int64_t entries = 0;          // stored complex entries
+    int64_t pairs = 0;            // window-cell pairs accumulated by the build
+    int32_t *tmap = nullptr;      // [(N'/32)^2] slot of each tile, -1 when untouched
+    int4 *tinfo = nullptr;        // [slot] (ty0, tx0, R, 0)
+    int64_t *off = nullptr;       // [slot] first entry
+    void *val = nullptr;          // cx<T>[entries], T the context precision
+    int max_R = 0;
+    double build_ms = 0.0;
+};
+
 enum { PROF_TILES = 0, PROF_FFT = 1, PROF_PROX = 2, PROF_OTHER = 3, PROF_N = 4 };
 struct ProfEvent {
     int cat;
@@ -115,6 +136,7 @@ struct ri_ctx {
     ri::View view64;                      // FP64 OTF view for the power iteration (if needed)
     bool view64_is_main = false;
     ri::CSR csr;
+    ri::Holo holo;
 
     ri::Prec<float> p32;
     ri::Prec<double> p64;
@@ -184,6 +206,14 @@ template <typename T> void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, in
                                         const cx<T> *y_sorted, const cx<T> *y_user,
                                         cx<T> *y_out_user, double *r2_partials, hipStream_t s);
 template <typename T> void fill_csr(ri_ctx *c, hipStream_t s);
+// Accumulate G^H G of the visibilities of v (FP64 fractions) into c->holo.val (zeroed).
+template <typename T> void fill_holo(ri_ctx *c, const View &v, hipStream_t s);
+
+// holo.hip
+void holo_build(ri_ctx *c, const View &v64, hipStream_t s);
+void holo_free(ri_ctx *c);
+// Y = H X on the N' x N' grid (Y is overwritten).
+template <typename T> void holo_apply(ri_ctx *c, const cx<T> *X, cx<T> *Y, hipStream_t s);
 int tiles_partials(ri_ctx *c);
 
 // image.hip

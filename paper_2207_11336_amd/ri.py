@@ -26,7 +26,8 @@ EXPORTS = ("ri_create", "ri_destroy", "ri_last_error", "phi_forward", "phi_adjoi
            "ri_get_plan_stats", "ri_get_plan_arrays", "ri_profile", "ri_profile_read",
            "ri_cnn_create", "ri_cnn_destroy", "ri_cnn_last_error", "ri_cnn_param_count", "ri_cnn_set_params",
            "ri_cnn_get_params", "ri_cnn_forward", "ri_cnn_grad", "ri_cnn_train_step", "ri_cnn_jvp", "ri_cnn_vjp",
-           "ri_cnn_fne_norm", "ri_cnn_jvp_grad", "ri_cnn_train_step_fne")
+           "ri_cnn_fne_norm", "ri_cnn_jvp_grad", "ri_cnn_train_step_fne", "ri_holo_build", "ri_holo_release",
+           "ri_holo_apply", "ri_holo_normal", "ri_holo_get_stats")
 
 
 class RIError(RuntimeError):
@@ -67,6 +68,11 @@ class ri_plan_stats(ctypes.Structure):
                 ("tuned_tile", c_int32 * 4), ("tuned_ms", c_double * 4)]
 
 
+class ri_holo_stats(ctypes.Structure):
+    _fields_ = [("tiles", c_int64), ("entries", c_int64), ("bytes", c_int64), ("pairs", c_int64),
+                ("max_reach", c_int32), ("build_ms", c_double)]
+
+
 class ri_kernel_times(ctypes.Structure):
     _fields_ = [("n_tiles", c_int32), ("n_fft", c_int32), ("n_prox", c_int32), ("n_other", c_int32),
                 ("tiles_ms", c_double), ("fft_ms", c_double), ("prox_ms", c_double), ("other_ms", c_double)]
@@ -104,6 +110,11 @@ def load() -> ctypes.CDLL:
     L.ri_get_plan_arrays.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.ri_get_plan_arrays.restype = st
     L.ri_profile.argtypes = [c_void_p, c_int32]; L.ri_profile.restype = st
+    L.ri_holo_build.argtypes = [c_void_p, c_void_p]; L.ri_holo_build.restype = st
+    L.ri_holo_release.argtypes = [c_void_p]; L.ri_holo_release.restype = st
+    L.ri_holo_apply.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]; L.ri_holo_apply.restype = st
+    L.ri_holo_normal.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]; L.ri_holo_normal.restype = st
+    L.ri_holo_get_stats.argtypes = [c_void_p, POINTER(ri_holo_stats)]; L.ri_holo_get_stats.restype = st
     L.ri_profile_read.argtypes = [c_void_p, POINTER(ri_kernel_times)]; L.ri_profile_read.restype = st
     L.ri_cnn_create.argtypes = [POINTER(ri_cnn_desc), ctypes.c_uint64, POINTER(c_void_p)]
     L.ri_cnn_create.restype = st
@@ -339,6 +350,34 @@ def ri_profile_read(ctx: Context) -> ri_kernel_times:
     t = ri_kernel_times()
     _check(ctx, load().ri_profile_read(ctx.handle, ctypes.byref(t)))
     return t
+
+
+def _grid(ctx, t, name):
+    import torch
+    cd = torch.complex64 if ctx.precision == 32 else torch.complex128
+    return _dev(t, cd, 4 * ctx.N * ctx.N, name)
+
+
+def ri_holo_build(ctx: Context, stream=None):
+    _check(ctx, load().ri_holo_build(ctx.handle, _stream(stream)))
+
+
+def ri_holo_release(ctx: Context):
+    _check(ctx, load().ri_holo_release(ctx.handle))
+
+
+def ri_holo_apply(ctx: Context, X, Y, stream=None):
+    _check(ctx, load().ri_holo_apply(ctx.handle, _grid(ctx, X, "X"), _grid(ctx, Y, "Y"), _stream(stream)))
+
+
+def ri_holo_normal(ctx: Context, x, out, stream=None):
+    _check(ctx, load().ri_holo_normal(ctx.handle, _image(ctx, x, "x"), _image(ctx, out, "out"), _stream(stream)))
+
+
+def ri_holo_get_stats(ctx: Context) -> ri_holo_stats:
+    s = ri_holo_stats()
+    _check(ctx, load().ri_holo_get_stats(ctx.handle, ctypes.byref(s)))
+    return s
 
 
 # ----------------------------------------------------------------------------

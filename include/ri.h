@@ -55,7 +55,7 @@ typedef enum {
 } ri_status;
 
 enum { RI_G_CSR = 0, RI_G_OTF = 1 };
-enum { RI_PROX_HAAR = 0, RI_PROX_CNN = 1 };
+enum { RI_PROX_HAAR = 0, RI_PROX_CNN = 1, RI_PROX_SARA = 2 };
 
 /* Plan description. All sizes explicit; nothing is read through globals. */
 typedef struct {
@@ -136,6 +136,15 @@ ri_status ri_power_norm(ri_ctx *ctx, int32_t max_it, double rtol, const double *
  *   RI_PROX_HAAR: D(z) = max(0, Psi soft_t(Psi^dagger z)), Psi the orthonormal
  *                 2D Haar basis with four levels, every coefficient
  *                 thresholded at t = param (eq. B2: t = tau / sqrt(2L));
+ *   RI_PROX_SARA: uSARA's denoiser (section "uSARA's handcrafted denoiser"):
+ *                 D(z) = argmin_x ||x - z||^2 / 2 + t ||w . Psi^dagger x||_1 + iota_+(x),
+ *                 t = param, Psi = [Dirac, db1, ..., db8] / 3 (orthonormal 2D
+ *                 periodic Daubechies wavelets with 1..8 vanishing moments, 4
+ *                 levels, minimum-phase filters), w the context's weights (1
+ *                 until ri_sara_reweight). Computed by the context's number of
+ *                 dual forward-backward sub-iterations (ri_sara_setup; 10 by
+ *                 default), warm-started from the dual variable the previous
+ *                 call left; z and out may not alias; needs N divisible by 16;
  *   RI_PROX_CNN:  D(z) = z - net(z), the residual CNN loaded by
  *                 ri_load_denoiser (appendix C), applied facet by facet
  *                 (appendix D): each facet's tile carries a halo, pixels
@@ -166,8 +175,10 @@ ri_status ri_load_denoiser(ri_ctx *ctx, const float *params, int64_t n_params, i
                            ri_stream stream);
 
 /* Whole solve: parameters from the paper's rules (appendices B, C, F), FB or
- * PnP-FB iterations from x = 0, divergence watch with Haar fallback.
- * Haar: t = tau / sqrt(2L) (eq. B2). CNN: the problem is rescaled by
+ * PnP-FB iterations from x = 0, divergence watch with Haar fallback (CNN).
+ * Haar and SARA: t = tau / sqrt(2L) (eq. B2, eq. lambda); SARA starts from
+ * w = 1 and a zero dual variable and reweights every reweight_every
+ * iterations (uSARA). CNN: the problem is rescaled by
  * alpha = max(dirty peak / beta, tau / (sigma_train sqrt(2L))) with beta the
  * dirty-beam peak (appendix F), so that the rescaled noise level
  * tau / (alpha sqrt(2L)) does not exceed the training level (eqs. C2-C3); the
@@ -183,9 +194,12 @@ typedef struct {
     const void *x_true;    /* optional dev [N][N] ground truth for the SNR trace, or NULL */
     double *trace;         /* optional host [max_iter][4]: rel change, ||r||^2, SNR dB, ms */
     int32_t use_graph;     /* 1: replay a hipGraph of two captured iterations */
-    int32_t diverge_checks;/* fall back to Haar after this many consecutive checks at which the
-                              residual ||Phi x - y||^2 grew by more than 1% since the previous
-                              check, or at once on a non-finite norm (0: 3) */
+    int32_t diverge_checks;/* CNN only: fall back to Haar after this many consecutive checks at
+                              which the residual ||Phi x - y||^2 grew by more than 1% since the
+                              previous check, or at once on a non-finite norm (0: 3) */
+    int32_t reweight_every;/* SARA only: after every this many iterations the log-sum weights
+                              are renewed, w = rho / (rho + |Psi^dagger x|) with rho = t
+                              (0: plain weighted l1 with w = 1, no reweighting) */
 } ri_solve_opts;
 
 typedef struct {
@@ -201,6 +215,27 @@ typedef struct {
  * Synchronous. */
 ri_status pnp_solve(ri_ctx *ctx, const void *y, const ri_solve_opts *opts, void *x_out,
                     ri_solve_report *report);
+
+/* uSARA's denoiser state (RI_PROX_SARA). ri_sara_setup allocates it on first
+ * use (dual variable and weights, [9][N][N] each, plus two [8][N][N] work
+ * arrays, in the context precision), sets the number of dual forward-backward
+ * sub-iterations per prox (>= 1), and resets the dual variable to 0 and the
+ * weights to 1. Needs N divisible by 16. */
+ri_status ri_sara_setup(ri_ctx *ctx, int32_t sub_iters, ri_stream stream);
+
+/* Log-sum reweighting: w = rho / (rho + |Psi^dagger x|) (the weights of the
+ * penalty's linear majorant at x), rho > 0. x: dev [N][N]. */
+ri_status ri_sara_reweight(ri_ctx *ctx, const void *x, double rho, ri_stream stream);
+
+/* The dictionary itself: coef = Psi^dagger x and x = Psi coef, coef dev
+ * [9][N][N] (slot 0 the Dirac basis, slot p the Daubechies wavelet with p
+ * vanishing moments in the usual pyramid layout: each level's low-low block in
+ * the top-left corner, then its three detail blocks), both scaled by 1/3. */
+ri_status ri_sara_analysis(ri_ctx *ctx, const void *x, void *coef, ri_stream stream);
+ri_status ri_sara_synthesis(ri_ctx *ctx, const void *coef, void *x, ri_stream stream);
+
+/* Copy the dual variable and/or the weights (dev [9][N][N] each, NULL to skip). */
+ri_status ri_sara_get_state(ri_ctx *ctx, void *v, void *w, ri_stream stream);
 
 /* Holographic form of the normal operator (appendix E): with the data in
  * blocks p, Phi^dagger Phi = Z^dagger F^dagger H F Z with H = sum_p G_p^H G_p

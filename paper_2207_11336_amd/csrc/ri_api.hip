@@ -130,11 +130,15 @@ void fb_step_sorted(ri_ctx *c, const T *x_in, const cx<T> *ys, double gamma, int
             reduce_partials(tile_part(c), tiles_partials(c), 1, 1, norms + 2, s);
         }
     } else {
-        // PnP step: z = x - gamma g, x_out = D(z) facet by facet
-        require(c->cnn != nullptr, "no CNN denoiser loaded (ri_load_denoiser)");
+        // z = x - gamma g, x_out = D(z): the CNN facet by facet (PnP step) or
+        // uSARA's sub-iterative prox
         const int64_t n = (int64_t)c->N * c->N;
         axpby<T>(p.img1, x_in, (T)1, p.img0, (T)(-gamma), n, s);
-        {
+        if (kind == RI_PROX_SARA) {
+            if (!c->sara.ready) sara_setup(c, 0, s);
+            sara_prox<T>(c, p.img1, (T)param, x_out, s);
+        } else {
+            require(c->cnn != nullptr, "no CNN denoiser loaded (ri_load_denoiser)");
             ProfScope ps(c, PROF_PROX, s);
             cnn_denoise<T>(c->cnn, p.img1, x_out, c->N, c->d.facet_core, c->d.facet_halo, s);
         }
@@ -167,6 +171,7 @@ void build_main_view(ri_ctx *c, int tile) {
     if (c->csr.val) {
         dev_free(c, c->csr.rowptr); dev_free(c, c->csr.val); dev_free(c, c->csr.col);
     holo_free(c);
+    sara_free(c);
         c->csr = CSR();
     }
     build_view(c, c->view, tile, f64frac ? 8 : 4);
@@ -347,6 +352,7 @@ bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_
             param = o.tau / (rr.alpha * std::sqrt(2.0 * L));
         }
         rr.t_or_sigma = param;
+        if (kind == RI_PROX_SARA) sara_setup(c, 0, s);   // v = 0, w = 1 (plain weighted l1 first)
         T *xa = (T *)dev_alloc(c, sizeof(T) * n); owned.push_back(xa);
         T *xb = (T *)dev_alloc(c, sizeof(T) * n); owned.push_back(xb);
         T *xsave = (T *)dev_alloc(c, sizeof(T) * n); owned.push_back(xsave);
@@ -389,7 +395,7 @@ bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_
         std::vector<std::pair<int, hipEvent_t>> marks;   // (iterations done, event)
         RI_CHECK_HIP(hipEventRecord(e0, s));
         const int div_n = o.diverge_checks > 0 ? o.diverge_checks : 3;
-        int rising = 0, k = 0, next_check = o.check_every;
+        int rising = 0, k = 0, next_check = o.check_every, reweights = 0;
         double last_r2 = -1.0;
         std::vector<double> h(4 * std::max(1, K));
         while (k < K) {
@@ -401,6 +407,11 @@ bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_
                 fb_step_sorted<T>(c, xa, ys, rr.gamma, kind, param, xb, nrm + 4 * k, xt, rr.alpha, s);
                 RI_CHECK_HIP(hipMemcpyAsync(xa, xb, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
                 k += 1;
+            }
+            if (kind == RI_PROX_SARA && o.reweight_every > 0 && k / o.reweight_every > reweights && k < K) {
+                // log-sum reweighting (rho = gamma lambda): w = rho / (rho + |Psi^dagger x|)
+                reweights = k / o.reweight_every;
+                sara_reweight<T>(c, xa, (T)param, s);
             }
             hipEvent_t ev;
             RI_CHECK_HIP(hipEventCreate(&ev)); evs.push_back(ev);
@@ -418,8 +429,8 @@ bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_
                 // fixed point, a diverging one grows geometrically
                 rising = (last_r2 >= 0.0 && q[2] > 1.01 * last_r2) ? rising + 1 : 0;
                 last_r2 = q[2];
-                if (!finite || (kind != RI_PROX_HAAR && rising >= div_n)) {
-                    if (kind == RI_PROX_HAAR) throw Error(RI_EDEVICE, "non-finite iterate with the Haar prox");
+                if (!finite || (kind == RI_PROX_CNN && rising >= div_n)) {
+                    if (kind != RI_PROX_CNN) throw Error(RI_EDEVICE, "non-finite iterate with a convex prox");
                     // restore the last healthy iterate and continue with the Haar prox
                     RI_CHECK_HIP(hipMemcpyAsync(xa, xsave, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
                     kind = RI_PROX_HAAR;
@@ -666,8 +677,15 @@ ri_status denoise(ri_ctx *c, const void *z, void *out, int32_t kind, double para
     if (!c) return RI_EINVAL;
     return guard(c, [&] {
         require(z && out, "z or out is NULL");
-        require(kind == RI_PROX_HAAR || kind == RI_PROX_CNN, "unknown denoiser kind");
-        if (kind == RI_PROX_HAAR) {
+        require(kind == RI_PROX_HAAR || kind == RI_PROX_CNN || kind == RI_PROX_SARA, "unknown denoiser kind");
+        if (kind == RI_PROX_SARA) {
+            require(c->N % 16 == 0, "the SARA dictionary needs N divisible by 16");
+            require(std::isfinite(param) && param >= 0.0, "threshold must be finite and >= 0");
+            require(z != out, "z and out may not alias for the SARA prox");
+            if (!c->sara.ready) sara_setup(c, 0, st(s));
+            if (c->d.precision == 32) sara_prox<float>(c, (const float *)z, (float)param, (float *)out, st(s));
+            else sara_prox<double>(c, (const double *)z, param, (double *)out, st(s));
+        } else if (kind == RI_PROX_HAAR) {
             require(c->N % 16 == 0, "the Haar prox needs N divisible by 16");
             require(std::isfinite(param) && param >= 0.0, "threshold must be finite and >= 0");
             if (c->d.precision == 32)
@@ -693,7 +711,7 @@ ri_status fb_step(ri_ctx *c, const void *x_in, const void *y, double gamma, int3
     return guard(c, [&] {
         require(x_in && x_out && x_in != x_out, "x_in, x_out must be distinct non-NULL buffers");
         require(std::isfinite(gamma) && gamma > 0.0, "gamma must be finite and > 0");
-        require(kind == RI_PROX_HAAR || kind == RI_PROX_CNN, "unknown denoiser kind");
+        require(kind == RI_PROX_HAAR || kind == RI_PROX_CNN || kind == RI_PROX_SARA, "unknown denoiser kind");
         require(c->N % 16 == 0, "the denoisers need N divisible by 16");
         if (c->d.precision == 32)
             do_fb_step<float>(c, (const float *)x_in, y, gamma, kind, param, (float *)x_out, norms, st(s));
@@ -729,7 +747,9 @@ ri_status pnp_solve(ri_ctx *c, const void *y, const ri_solve_opts *o, void *x_ou
     ri_status r = guard(c, [&] {
         require(o && x_out, "opts or x_out is NULL");
         require(o->max_iter >= 0 && o->check_every >= 1 && o->tau >= 0.0, "bad solve options");
-        require(o->prox_kind == RI_PROX_HAAR || o->prox_kind == RI_PROX_CNN, "unknown denoiser kind");
+        require(o->prox_kind == RI_PROX_HAAR || o->prox_kind == RI_PROX_CNN || o->prox_kind == RI_PROX_SARA,
+                "unknown denoiser kind");
+        require(o->reweight_every >= 0, "reweight_every must be >= 0");
         require(c->N % 16 == 0, "the Haar prox needs N divisible by 16");
         if (c->d.precision == 32) fell = solve<float>(c, y, *o, (float *)x_out, rep);
         else fell = solve<double>(c, y, *o, (double *)x_out, rep);
@@ -793,6 +813,59 @@ ri_status ri_get_plan_stats(const ri_ctx *c, ri_plan_stats *o) {
         o->n_tuned++;
     }
     return RI_OK;
+}
+
+ri_status ri_sara_setup(ri_ctx *c, int32_t sub_iters, ri_stream s) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        require(sub_iters >= 1 && sub_iters <= 100000, "sub_iters must be in 1..100000");
+        sara_setup(c, sub_iters, st(s));
+        RI_CHECK_HIP(hipGetLastError());
+    });
+}
+
+ri_status ri_sara_reweight(ri_ctx *c, const void *x, double rho, ri_stream s) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        require(x != nullptr, "x is NULL");
+        require(std::isfinite(rho) && rho > 0.0, "rho must be finite and > 0");
+        if (!c->sara.ready) sara_setup(c, 0, st(s));
+        if (c->d.precision == 32) sara_reweight<float>(c, (const float *)x, (float)rho, st(s));
+        else sara_reweight<double>(c, (const double *)x, rho, st(s));
+        RI_CHECK_HIP(hipGetLastError());
+    });
+}
+
+ri_status ri_sara_analysis(ri_ctx *c, const void *x, void *coef, ri_stream s) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        require(x && coef, "x or coef is NULL");
+        if (!c->sara.ready) sara_setup(c, 0, st(s));
+        if (c->d.precision == 32) sara_analysis<float>(c, (const float *)x, (float *)coef, st(s));
+        else sara_analysis<double>(c, (const double *)x, (double *)coef, st(s));
+        RI_CHECK_HIP(hipGetLastError());
+    });
+}
+
+ri_status ri_sara_synthesis(ri_ctx *c, const void *coef, void *x, ri_stream s) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        require(x && coef, "x or coef is NULL");
+        if (!c->sara.ready) sara_setup(c, 0, st(s));
+        if (c->d.precision == 32) sara_synthesis<float>(c, (const float *)coef, (float *)x, st(s));
+        else sara_synthesis<double>(c, (const double *)coef, (double *)x, st(s));
+        RI_CHECK_HIP(hipGetLastError());
+    });
+}
+
+ri_status ri_sara_get_state(ri_ctx *c, void *v, void *w, ri_stream s) {
+    if (!c) return RI_EINVAL;
+    return guard(c, [&] {
+        require(c->sara.ready, "no SARA state: call ri_sara_setup or use the SARA prox first");
+        const size_t bytes = (c->d.precision == 64 ? 8 : 4) * 9 * (size_t)c->N * c->N;
+        if (v) RI_CHECK_HIP(hipMemcpyAsync(v, c->sara.v, bytes, hipMemcpyDeviceToDevice, st(s)));
+        if (w) RI_CHECK_HIP(hipMemcpyAsync(w, c->sara.w, bytes, hipMemcpyDeviceToDevice, st(s)));
+    });
 }
 
 ri_status ri_holo_build(ri_ctx *c, ri_stream s) {

@@ -97,6 +97,15 @@ struct Holo {
     double build_ms = 0.0;
 };
 
+// uSARA's denoiser state (sara.hip): dual variable and weights over the nine
+// bases of the dictionary, [9][N][N] each (slot 0 the Dirac basis), and two
+// [8][N][N] transform work arrays.
+struct SaraState {
+    bool ready = false;
+    int sub_iters = 10;           // dual forward-backward sub-iterations per prox
+    void *v = nullptr, *w = nullptr, *work = nullptr, *tmp = nullptr;
+};
+
 enum { PROF_TILES = 0, PROF_FFT = 1, PROF_PROX = 2, PROF_OTHER = 3, PROF_N = 4 };
 struct ProfEvent {
     int cat;
@@ -137,6 +146,7 @@ struct ri_ctx {
     bool view64_is_main = false;
     ri::CSR csr;
     ri::Holo holo;
+    ri::SaraState sara;
 
     ri::Prec<float> p32;
     ri::Prec<double> p64;
@@ -208,6 +218,15 @@ template <typename T> void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, in
 template <typename T> void fill_csr(ri_ctx *c, hipStream_t s);
 // Accumulate G^H G of the visibilities of v (FP64 fractions) into c->holo.val (zeroed).
 template <typename T> void fill_holo(ri_ctx *c, const View &v, hipStream_t s);
+
+// sara.hip: uSARA's prox, reweighting and dictionary transforms (context precision T)
+void sara_setup(ri_ctx *c, int sub_iters, hipStream_t s);   // allocate on first use; v = 0, w = 1
+void sara_reset(ri_ctx *c, hipStream_t s);
+void sara_free(ri_ctx *c);
+template <typename T> void sara_prox(ri_ctx *c, const T *z, T thr, T *x_out, hipStream_t s);
+template <typename T> void sara_reweight(ri_ctx *c, const T *x, T rho, hipStream_t s);
+template <typename T> void sara_analysis(ri_ctx *c, const T *x, T *coef9, hipStream_t s);
+template <typename T> void sara_synthesis(ri_ctx *c, const T *coef9, T *x, hipStream_t s);
 
 // holo.hip
 void holo_build(ri_ctx *c, const View &v64, hipStream_t s);

@@ -1,0 +1,407 @@
+// uSARA's denoiser (section "uSARA's handcrafted denoiser"): the prox of
+// t ||w . Psi^dagger x||_1 + iota_+(x) for the SARA dictionary
+// Psi = [Dirac, db1, ..., db8] / 3 (each basis an orthonormal 2D periodic
+// wavelet transform with 4 levels), by sub-iterations of dual forward-backward
+// with unit step (||Psi^dagger|| = 1):
+//   x_k = max(0, z - Psi v_k),   v_{k+1} = clip(v_k + Psi^dagger x_k, -t w, t w),
+// warm-started from the previous call's dual variable, and the reweighting of
+// the log-sum penalty, w = rho / (rho + |Psi^dagger x|).
+//
+// Filters: the minimum-phase Daubechies low-pass filter with p vanishing
+// moments (2p taps) is the spectral factor h(z) = sqrt(2) ((1+z)/2)^p Q(z)/Q(1)
+// with Q's roots the roots outside the unit circle of z^{p-1} P_p((2-z-1/z)/4),
+// P_p(y) = sum_{k<p} C(p-1+k, k) y^k; computed on the host (roots of P_p in y
+// by Durand-Kerner in long double, then mapped to z) and checked for
+// orthonormality before use. High-pass g[t] = (-1)^t h[L-1-t].
+//
+// Transform (per basis b = blockIdx.z, all 8 wavelet bases in one launch):
+// one level on an n x n block (row stride N): rows then columns, each
+// a[k] = sum_t h[t] x[(2k+t) mod n], d[k] = sum_t g[t] x[(2k+t) mod n],
+// low half first; the top-left block goes on to the next level. The column
+// pass writes only the low-low block for the next level and finalises every
+// other coefficient in place: the dual update (clip), the new weight, or the
+// plain coefficient. Synthesis runs the adjoint from the coarsest level, reading
+// the coarse block from the previous level's result and the details from the
+// coefficients; its last row pass sums the 8 bases and the Dirac part and
+// applies max(0, z - .) with the Dirac dual update fused.
+#include <cmath>
+#include <complex>
+
+#include "ri_internal.h"
+
+namespace ri {
+
+namespace {
+
+constexpr int NW = 8;          // wavelet bases (db1 .. db8)
+constexpr int LEVELS = 4;
+constexpr int LMAX = 16;
+
+__constant__ double c_h64[NW][LMAX];
+__constant__ double c_g64[NW][LMAX];
+__constant__ float c_h32[NW][LMAX];
+__constant__ float c_g32[NW][LMAX];
+
+template <typename T> __device__ __forceinline__ T fh(int b, int t);
+template <typename T> __device__ __forceinline__ T fg(int b, int t);
+template <> __device__ __forceinline__ double fh<double>(int b, int t) { return c_h64[b][t]; }
+template <> __device__ __forceinline__ double fg<double>(int b, int t) { return c_g64[b][t]; }
+template <> __device__ __forceinline__ float fh<float>(int b, int t) { return c_h32[b][t]; }
+template <> __device__ __forceinline__ float fg<float>(int b, int t) { return c_g32[b][t]; }
+
+enum { FIN_DUAL = 0, FIN_WEIGHT = 1, FIN_COEF = 2 };
+enum { SYN_PROX = 0, SYN_PLAIN = 1 };
+
+// Finalised coefficient val (unscaled) of basis slot j (1..8, 0 = Dirac) at flat index e.
+template <typename T, int FIN>
+__device__ __forceinline__ void finalise(T *dst9, const T *w9, size_t i9, T val, T scale, T par) {
+    const T cval = val * scale;
+    if (FIN == FIN_DUAL) {
+        const T lim = par * w9[i9];
+        dst9[i9] = fmin(fmax(dst9[i9] + cval, -lim), lim);
+    } else if (FIN == FIN_WEIGHT) {
+        dst9[i9] = par / (par + fabs(cval));
+    } else {
+        dst9[i9] = cval;
+    }
+}
+
+// Row analysis of the n x n block of every basis: in (basis stride in_bs) -> tmp.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ana_rows(const T *__restrict__ in, int64_t in_bs, T *__restrict__ tmp,
+                                                  int N, int n) {
+    const int b = blockIdx.z, row = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x, half = n >> 1;
+    if (k >= half) return;
+    const T *src = in + b * in_bs + (size_t)row * N;
+    const int L = 2 * (b + 1), m = n - 1;
+    T a = 0, d = 0;
+    for (int t = 0; t < L; ++t) {
+        const T v = src[(2 * k + t) & m];
+        a += fh<T>(b, t) * v;
+        d += fg<T>(b, t) * v;
+    }
+    T *dst = tmp + (size_t)b * N * N + (size_t)row * N;
+    dst[k] = a;
+    dst[half + k] = d;
+}
+
+// Column analysis: tmp -> low-low block into work (unless last) and every
+// other coefficient finalised into dst9 (slot b + 1).
+template <typename T, int FIN>
+__global__ void __launch_bounds__(256) k_ana_cols(const T *__restrict__ tmp, T *__restrict__ work, T *dst9,
+                                                  const T *__restrict__ w9, int N, int n, int last, T scale, T par) {
+    const int b = blockIdx.z;
+    const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int k = blockIdx.y * 4 + (threadIdx.x >> 6), half = n >> 1;
+    if (col >= n || k >= half) return;
+    const size_t NN = (size_t)N * N;
+    const T *src = tmp + b * NN + col;
+    const int L = 2 * (b + 1), m = n - 1;
+    T a = 0, d = 0;
+    for (int t = 0; t < L; ++t) {
+        const T v = src[(size_t)((2 * k + t) & m) * N];
+        a += fh<T>(b, t) * v;
+        d += fg<T>(b, t) * v;
+    }
+    const size_t base9 = (size_t)(b + 1) * NN;
+    if (!last && col < half) work[b * NN + (size_t)k * N + col] = a;
+    else finalise<T, FIN>(dst9, w9, base9 + (size_t)k * N + col, a, scale, par);
+    finalise<T, FIN>(dst9, w9, base9 + (size_t)(half + k) * N + col, d, scale, par);
+}
+
+// Dirac slot of the analysis (weights or plain coefficients).
+template <typename T, int FIN>
+__global__ void k_ana_dirac(const T *__restrict__ x, T *dst9, int64_t n, T scale, T par) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        finalise<T, FIN>(dst9, nullptr, (size_t)i, x[i], scale, par);
+}
+
+// Column synthesis of level block n: the coarse block (rows and columns < n/2)
+// from work (or from the coefficients at the coarsest level), the rest from
+// the coefficients v9 (slot b + 1) -> tmp.
+template <typename T>
+__global__ void __launch_bounds__(256) k_syn_cols(const T *__restrict__ v9, const T *__restrict__ work,
+                                                  T *__restrict__ tmp, int N, int n, int coarsest) {
+    const int b = blockIdx.z;
+    const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int i = blockIdx.y * 4 + (threadIdx.x >> 6), half = n >> 1;
+    if (col >= n || i >= n) return;
+    const size_t NN = (size_t)N * N;
+    const T *cf = v9 + (size_t)(b + 1) * NN + col;
+    const T *lo = (!coarsest && col < half) ? work + b * NN + col : cf;
+    const int L = 2 * (b + 1), m = n - 1;
+    T x = 0;
+    for (int t = i & 1; t < L; t += 2) {
+        const int k = ((i - t) & m) >> 1;
+        x += fh<T>(b, t) * lo[(size_t)k * N] + fg<T>(b, t) * cf[(size_t)(half + k) * N];
+    }
+    tmp[b * NN + (size_t)i * N + col] = x;
+}
+
+// Row synthesis of level block n (not the last): tmp -> work.
+template <typename T>
+__global__ void __launch_bounds__(256) k_syn_rows(const T *__restrict__ tmp, T *__restrict__ work, int N, int n) {
+    const int b = blockIdx.z, row = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, half = n >> 1;
+    if (j >= n) return;
+    const size_t NN = (size_t)N * N;
+    const T *src = tmp + b * NN + (size_t)row * N;
+    const int L = 2 * (b + 1), m = n - 1;
+    T x = 0;
+    for (int t = j & 1; t < L; t += 2) {
+        const int k = ((j - t) & m) >> 1;
+        x += fh<T>(b, t) * src[k] + fg<T>(b, t) * src[half + k];
+    }
+    work[b * NN + (size_t)row * N + j] = x;
+}
+
+// Last row synthesis (n = N), summed over the 8 bases plus the Dirac slot:
+// SYN_PLAIN: x = scale * s; SYN_PROX: x = max(0, z - scale * s) and the
+// Dirac dual update v0 = clip(v0 + scale * x, -t w0, t w0).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_syn_final(const T *__restrict__ tmp, T *v9, const T *__restrict__ w9,
+                                                   const T *__restrict__ z, T *__restrict__ x, int N, T scale,
+                                                   T thr) {
+    const int row = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, half = N >> 1;
+    if (j >= N) return;
+    const size_t NN = (size_t)N * N;
+    const size_t p = (size_t)row * N + j;
+    const int m = N - 1;
+    T s = v9[p];
+    for (int b = 0; b < NW; ++b) {
+        const T *src = tmp + b * NN + (size_t)row * N;
+        const int L = 2 * (b + 1);
+        for (int t = j & 1; t < L; t += 2) {
+            const int k = ((j - t) & m) >> 1;
+            s += fh<T>(b, t) * src[k] + fg<T>(b, t) * src[half + k];
+        }
+    }
+    if (MODE == SYN_PLAIN) {
+        x[p] = scale * s;
+    } else {
+        const T xo = fmax((T)0, z[p] - scale * s);
+        x[p] = xo;
+        const T lim = thr * w9[p];
+        v9[p] = fmin(fmax(v9[p] + scale * xo, -lim), lim);
+    }
+}
+
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// Filters on the host
+// ---------------------------------------------------------------------------
+using cld = std::complex<long double>;
+
+// Roots of sum_k a[k] y^k (degree d = a.size() - 1 >= 1) by Durand-Kerner.
+std::vector<cld> poly_roots(const std::vector<long double> &a) {
+    const int d = (int)a.size() - 1;
+    std::vector<cld> r(d);
+    const cld seed(0.4L, 0.9L);
+    cld pw(1.0L, 0.0L);
+    for (int i = 0; i < d; ++i) { r[i] = pw; pw *= seed; }
+    auto eval = [&](cld y) {
+        cld v = 0;
+        for (int k = d; k >= 0; --k) v = v * y + a[k];
+        return v / a[d];
+    };
+    for (int it = 0; it < 2000; ++it) {
+        long double moved = 0;
+        for (int i = 0; i < d; ++i) {
+            cld den = 1;
+            for (int j = 0; j < d; ++j)
+                if (j != i) den *= (r[i] - r[j]);
+            const cld step = eval(r[i]) / den;
+            r[i] -= step;
+            moved = std::max(moved, std::abs(step));
+        }
+        if (moved < 1e-24L) break;
+    }
+    return r;
+}
+
+std::vector<double> daubechies(int p) {
+    std::vector<cld> q(1, cld(1.0L, 0.0L));   // Q(z), increasing powers
+    if (p > 1) {
+        std::vector<long double> a(p);
+        long double binom = 1;                 // C(p-1+k, k)
+        for (int k = 0; k < p; ++k) {
+            a[k] = binom;
+            binom = binom * (long double)(p + k) / (long double)(k + 1);
+        }
+        for (const cld &y : poly_roots(a)) {
+            const cld bq = 1.0L - 2.0L * y;
+            const cld disc = std::sqrt(bq * bq - 1.0L);
+            const cld z = std::abs(bq + disc) > 1.0L ? bq + disc : bq - disc;
+            std::vector<cld> nq(q.size() + 1, cld(0));
+            for (size_t i = 0; i < q.size(); ++i) {
+                nq[i + 1] += q[i];
+                nq[i] -= z * q[i];
+            }
+            q.swap(nq);
+        }
+    }
+    std::vector<long double> h(q.size());
+    for (size_t i = 0; i < q.size(); ++i) h[i] = q[i].real();
+    for (int k = 0; k < p; ++k) {              // times (1 + z) / 2, p times
+        std::vector<long double> nh(h.size() + 1, 0.0L);
+        for (size_t i = 0; i < h.size(); ++i) {
+            nh[i] += 0.5L * h[i];
+            nh[i + 1] += 0.5L * h[i];
+        }
+        h.swap(nh);
+    }
+    long double sum = 0;
+    for (long double v : h) sum += v;
+    std::vector<double> out(h.size());
+    for (size_t i = 0; i < h.size(); ++i) out[i] = (double)(h[i] * std::sqrt(2.0L) / sum);
+    // orthonormality check: sum_k h[k] h[k + 2m] = delta_m
+    for (int m = 0; m < p; ++m) {
+        long double dot = 0;
+        for (size_t k = 0; k + 2 * m < out.size(); ++k) dot += (long double)out[k] * out[k + 2 * m];
+        if (std::fabs((double)dot - (m == 0 ? 1.0 : 0.0)) > 1e-13)
+            throw Error(RI_EDEVICE, "Daubechies filter " + std::to_string(p) + " failed its orthonormality check");
+    }
+    return out;
+}
+
+void upload_filters(ri_ctx *c) {
+    double h64[NW][LMAX] = {}, g64[NW][LMAX] = {};
+    float h32[NW][LMAX] = {}, g32[NW][LMAX] = {};
+    for (int b = 0; b < NW; ++b) {
+        const std::vector<double> h = daubechies(b + 1);
+        const int L = (int)h.size();
+        for (int t = 0; t < L; ++t) {
+            h64[b][t] = h[t];
+            g64[b][t] = (t & 1 ? -1.0 : 1.0) * h[L - 1 - t];
+            h32[b][t] = (float)h64[b][t];
+            g32[b][t] = (float)g64[b][t];
+        }
+    }
+    RI_CHECK_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_h64), h64, sizeof(h64)));
+    RI_CHECK_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_g64), g64, sizeof(g64)));
+    RI_CHECK_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_h32), h32, sizeof(h32)));
+    RI_CHECK_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_g32), g32, sizeof(g32)));
+    (void)c;
+}
+
+// Psi^dagger x into dst9 (FIN selects the dual update, the weights or the plain coefficients).
+template <typename T, int FIN>
+void analysis(ri_ctx *c, const T *x, T *dst9, T par, bool dirac, hipStream_t s) {
+    SaraState &st = c->sara;
+    const int N = c->N;
+    const T scale = (T)(1.0 / 3.0);
+    T *work = (T *)st.work, *tmp = (T *)st.tmp;
+    const T *w9 = (const T *)st.w;
+    if (dirac)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ana_dirac<T, FIN>), dim3(1024), dim3(256), 0, s, x, dst9,
+                           (int64_t)N * N, scale, par);
+    for (int l = 0; l < LEVELS; ++l) {
+        const int n = N >> l;
+        const T *in = l == 0 ? x : work;
+        const int64_t in_bs = l == 0 ? 0 : (int64_t)N * N;
+        hipLaunchKernelGGL(k_ana_rows<T>, dim3(cdiv(n / 2, 256), n, NW), dim3(256), 0, s, in, in_bs, tmp, N, n);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ana_cols<T, FIN>), dim3(cdiv(n, 64), cdiv(n / 2, 4), NW), dim3(256), 0,
+                           s, tmp, work, dst9, w9, N, n, l == LEVELS - 1 ? 1 : 0, scale, par);
+    }
+}
+
+// Psi v9 (MODE SYN_PLAIN) or x = max(0, z - Psi v9) with the Dirac dual update (SYN_PROX).
+template <typename T, int MODE>
+void synthesis(ri_ctx *c, T *v9, const T *z, T *x, T thr, hipStream_t s) {
+    SaraState &st = c->sara;
+    const int N = c->N;
+    const T scale = (T)(1.0 / 3.0);
+    T *work = (T *)st.work, *tmp = (T *)st.tmp;
+    for (int l = LEVELS - 1; l >= 0; --l) {
+        const int n = N >> l;
+        hipLaunchKernelGGL(k_syn_cols<T>, dim3(cdiv(n, 64), cdiv(n, 4), NW), dim3(256), 0, s, v9, work, tmp, N, n,
+                           l == LEVELS - 1 ? 1 : 0);
+        if (l > 0)
+            hipLaunchKernelGGL(k_syn_rows<T>, dim3(cdiv(n, 256), n, NW), dim3(256), 0, s, tmp, work, N, n);
+    }
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_syn_final<T, MODE>), dim3(cdiv(N, 256), N), dim3(256), 0, s, tmp, v9,
+                       (const T *)st.w, z, x, N, scale, thr);
+}
+
+}  // namespace
+
+void sara_free(ri_ctx *c) {
+    SaraState &st = c->sara;
+    dev_free(c, st.v);
+    dev_free(c, st.w);
+    dev_free(c, st.work);
+    dev_free(c, st.tmp);
+    const int sub = st.sub_iters;
+    st = SaraState{};
+    st.sub_iters = sub;
+}
+
+void sara_setup(ri_ctx *c, int sub_iters, hipStream_t s) {
+    if (c->N % 16 != 0) throw Error(RI_EUNSUPPORTED, "the SARA dictionary needs N divisible by 16");
+    SaraState &st = c->sara;
+    if (sub_iters > 0) st.sub_iters = sub_iters;
+    const size_t eb = c->d.precision == 64 ? sizeof(double) : sizeof(float);
+    const size_t NN = (size_t)c->N * c->N;
+    if (!st.ready) {
+        upload_filters(c);
+        st.v = dev_alloc(c, eb * 9 * NN);
+        st.w = dev_alloc(c, eb * 9 * NN);
+        st.work = dev_alloc(c, eb * NW * NN);
+        st.tmp = dev_alloc(c, eb * NW * NN);
+        st.ready = true;
+    }
+    sara_reset(c, s);
+}
+
+void sara_reset(ri_ctx *c, hipStream_t s) {
+    SaraState &st = c->sara;
+    const int64_t n9 = 9 * (int64_t)c->N * c->N;
+    if (c->d.precision == 64) {
+        fill_real<double>((double *)st.v, n9, 0.0, s);
+        fill_real<double>((double *)st.w, n9, 1.0, s);
+    } else {
+        fill_real<float>((float *)st.v, n9, 0.0f, s);
+        fill_real<float>((float *)st.w, n9, 1.0f, s);
+    }
+}
+
+template <typename T>
+void sara_prox(ri_ctx *c, const T *z, T thr, T *x_out, hipStream_t s) {
+    SaraState &st = c->sara;
+    ProfScope ps(c, PROF_PROX, s);
+    T *v9 = (T *)st.v;
+    for (int k = 0; k < st.sub_iters; ++k) {
+        synthesis<T, SYN_PROX>(c, v9, z, x_out, thr, s);
+        analysis<T, FIN_DUAL>(c, x_out, v9, thr, false, s);
+    }
+}
+
+template <typename T>
+void sara_reweight(ri_ctx *c, const T *x, T rho, hipStream_t s) {
+    ProfScope ps(c, PROF_OTHER, s);
+    analysis<T, FIN_WEIGHT>(c, x, (T *)c->sara.w, rho, true, s);
+}
+
+template <typename T>
+void sara_analysis(ri_ctx *c, const T *x, T *coef9, hipStream_t s) {
+    analysis<T, FIN_COEF>(c, x, coef9, (T)0, true, s);
+}
+
+template <typename T>
+void sara_synthesis(ri_ctx *c, const T *coef9, T *x, hipStream_t s) {
+    synthesis<T, SYN_PLAIN>(c, const_cast<T *>(coef9), nullptr, x, (T)0, s);
+}
+
+template void sara_prox<float>(ri_ctx *, const float *, float, float *, hipStream_t);
+template void sara_prox<double>(ri_ctx *, const double *, double, double *, hipStream_t);
+template void sara_reweight<float>(ri_ctx *, const float *, float, hipStream_t);
+template void sara_reweight<double>(ri_ctx *, const double *, double, hipStream_t);
+template void sara_analysis<float>(ri_ctx *, const float *, float *, hipStream_t);
+template void sara_analysis<double>(ri_ctx *, const double *, double *, hipStream_t);
+template void sara_synthesis<float>(ri_ctx *, const float *, float *, hipStream_t);
+template void sara_synthesis<double>(ri_ctx *, const double *, double *, hipStream_t);
+
+}  // namespace ri

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libri.so")
 
 RI_OK, RI_EINVAL, RI_ENOMEM, RI_EDEVICE, RI_EUNSUPPORTED, RI_ENOTCONV, RI_FELLBACK = 0, -1, -2, -3, -4, -5, 1
 RI_G_CSR, RI_G_OTF = 0, 1
-RI_PROX_HAAR, RI_PROX_CNN = 0, 1
+RI_PROX_HAAR, RI_PROX_CNN, RI_PROX_SARA = 0, 1, 2
 RI_NO_DATA = c_void_p(-1 & 0xFFFFFFFFFFFFFFFF)
 
 EXPORTS = ("ri_create", "ri_destroy", "ri_last_error", "phi_forward", "phi_adjoint", "ri_set_data",
@@ -27,7 +27,8 @@ EXPORTS = ("ri_create", "ri_destroy", "ri_last_error", "phi_forward", "phi_adjoi
            "ri_cnn_create", "ri_cnn_destroy", "ri_cnn_last_error", "ri_cnn_param_count", "ri_cnn_set_params",
            "ri_cnn_get_params", "ri_cnn_forward", "ri_cnn_grad", "ri_cnn_train_step", "ri_cnn_jvp", "ri_cnn_vjp",
            "ri_cnn_fne_norm", "ri_cnn_jvp_grad", "ri_cnn_train_step_fne", "ri_holo_build", "ri_holo_release",
-           "ri_holo_apply", "ri_holo_normal", "ri_holo_get_stats")
+           "ri_holo_apply", "ri_holo_normal", "ri_holo_get_stats", "ri_sara_setup", "ri_sara_reweight",
+           "ri_sara_analysis", "ri_sara_synthesis", "ri_sara_get_state")
 
 
 class RIError(RuntimeError):
@@ -47,7 +48,8 @@ class ri_plan_desc(ctypes.Structure):
 class ri_solve_opts(ctypes.Structure):
     _fields_ = [("max_iter", c_int32), ("rel_tol", c_double), ("prox_kind", c_int32), ("tau", c_double),
                 ("sigma_train", c_double), ("L", c_double), ("check_every", c_int32), ("x_true", c_void_p),
-                ("trace", c_void_p), ("use_graph", c_int32), ("diverge_checks", c_int32)]
+                ("trace", c_void_p), ("use_graph", c_int32), ("diverge_checks", c_int32),
+                ("reweight_every", c_int32)]
 
 
 class ri_solve_report(ctypes.Structure):
@@ -110,6 +112,11 @@ def load() -> ctypes.CDLL:
     L.ri_get_plan_arrays.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.ri_get_plan_arrays.restype = st
     L.ri_profile.argtypes = [c_void_p, c_int32]; L.ri_profile.restype = st
+    L.ri_sara_setup.argtypes = [c_void_p, c_int32, c_void_p]; L.ri_sara_setup.restype = st
+    L.ri_sara_reweight.argtypes = [c_void_p, c_void_p, c_double, c_void_p]; L.ri_sara_reweight.restype = st
+    L.ri_sara_analysis.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]; L.ri_sara_analysis.restype = st
+    L.ri_sara_synthesis.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]; L.ri_sara_synthesis.restype = st
+    L.ri_sara_get_state.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]; L.ri_sara_get_state.restype = st
     L.ri_holo_build.argtypes = [c_void_p, c_void_p]; L.ri_holo_build.restype = st
     L.ri_holo_release.argtypes = [c_void_p]; L.ri_holo_release.restype = st
     L.ri_holo_apply.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]; L.ri_holo_apply.restype = st
@@ -356,6 +363,32 @@ def _grid(ctx, t, name):
     import torch
     cd = torch.complex64 if ctx.precision == 32 else torch.complex128
     return _dev(t, cd, 4 * ctx.N * ctx.N, name)
+
+
+def _coef9(ctx, t, name):
+    return _dev(t, ctx.real_dtype, 9 * ctx.N * ctx.N, name)
+
+
+def ri_sara_setup(ctx: Context, sub_iters: int = 10, stream=None):
+    _check(ctx, load().ri_sara_setup(ctx.handle, int(sub_iters), _stream(stream)))
+
+
+def ri_sara_reweight(ctx: Context, x, rho: float, stream=None):
+    _check(ctx, load().ri_sara_reweight(ctx.handle, _image(ctx, x, "x"), float(rho), _stream(stream)))
+
+
+def ri_sara_analysis(ctx: Context, x, coef, stream=None):
+    _check(ctx, load().ri_sara_analysis(ctx.handle, _image(ctx, x, "x"), _coef9(ctx, coef, "coef"), _stream(stream)))
+
+
+def ri_sara_synthesis(ctx: Context, coef, x, stream=None):
+    _check(ctx, load().ri_sara_synthesis(ctx.handle, _coef9(ctx, coef, "coef"), _image(ctx, x, "x"),
+                                         _stream(stream)))
+
+
+def ri_sara_get_state(ctx: Context, v=None, w=None, stream=None):
+    _check(ctx, load().ri_sara_get_state(ctx.handle, _coef9(ctx, v, "v") if v is not None else None,
+                                         _coef9(ctx, w, "w") if w is not None else None, _stream(stream)))
 
 
 def ri_holo_build(ctx: Context, stream=None):

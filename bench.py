@@ -118,6 +118,53 @@ def cnn_flops(n_pixels: int, layers: int = 10, ch: int = 64) -> float:
     return float(n_pixels) * 2 * 9 * (ch + (layers - 2) * ch * ch + ch)
 
 
+def sara_prox_bytes(N: int, elem: int = 4) -> float:
+    """Algorithmic HBM bytes of one dual forward-backward sub-iteration of the
+    SARA prox: the dual variable read and written and the weights read (nine
+    N x N coefficient planes each), z read, x written and read back once."""
+    return elem * N * N * (9 * 3 + 3)
+
+
+def run_usara(args, R, ctx, x_true, target, solve):
+    """uSARA (reweighted FB with the SARA prox, t = tau / sqrt(2L), rho = t)
+    on the same blocked problem and data as FB and PnP-FB: prox time per call
+    and its HBM rate, then the hipGraph-replayed solve with its SNR trace."""
+    import numpy as np
+    import torch
+    N = x_true.shape[0]
+    R.ri_sara_setup(ctx, args.sara_sub)
+    z = x_true.clone()
+    out = torch.empty_like(z)
+    R.denoise(ctx, z, out, R.RI_PROX_SARA, 1e-3)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        R.denoise(ctx, z, out, R.RI_PROX_SARA, 1e-3)
+    e1.record()
+    torch.cuda.synchronize()
+    prox_ms = e0.elapsed_time(e1) / 5
+    sub_bytes = sara_prox_bytes(N)
+    gbs = sub_bytes * args.sara_sub / (prox_ms * 1e-3) / 1e9
+    log(f"SARA prox: {prox_ms:.3f} ms per call ({args.sara_sub} sub-iterations, {prox_ms / args.sara_sub:.3f} ms "
+        f"each, {gbs:.0f} GB/s algorithmic)")
+    rep, tr = solve(R.RI_PROX_SARA, 0.0, args.sara_reweight)
+    hit = np.nonzero(tr[:rep.iters, 2] >= target)[0]
+    marks = (10, 50, 100, 200, 300, 500, 1000)
+    res = {"sub_iters": args.sara_sub, "reweight_every": args.sara_reweight, "prox_ms": prox_ms,
+           "prox_sub_iter_ms": prox_ms / args.sara_sub, "prox_bytes_per_sub_iter": sub_bytes,
+           "prox_gbs": gbs, "prox_frac_hbm": gbs / HBM_PEAK_GBS, "iters": rep.iters, "ms": rep.ms,
+           "ms_per_iter": rep.ms / max(1, rep.iters), "final_snr_db": rep.snr_db, "t": rep.t_or_sigma,
+           "residual2": rep.final_residual2, "target_snr_db": target,
+           "ms_to_target": float(tr[hit[0], 3]) if hit.size else None,
+           "its_to_target": int(hit[0]) + 1 if hit.size else None,
+           "snr_at": {str(k): round(float(tr[k - 1, 2]), 3) for k in marks if k <= rep.iters}}
+    log(f"uSARA x{rep.iters} ({args.sara_sub} sub-its, reweight every {args.sara_reweight}): {rep.ms:.1f} ms "
+        f"({res['ms_per_iter']:.3f} ms/it), SNR {rep.snr_db:.2f} dB; to {target:.2f} dB: {res['ms_to_target']} ms; "
+        f"trace {res['snr_at']}")
+    return res
+
+
 def run_pnp(args, R, synth, ctx, noise, x_true, L):
     """PnP-FB against plain FB on the blocked problem at the denoiser's dynamic
     range. The visibility noise is set so that the rescaled image-domain noise
@@ -151,10 +198,11 @@ def run_pnp(args, R, synth, ctx, noise, x_true, L):
     log(f"PnP data: alpha0 {alpha0:.4e}, sigma {sigma:.1e} -> tau {tau:.4e} (input SNR {isnr:.1f} dB)")
     K = args.pnp_iters
 
-    def solve(kind, sig_train):
+    def solve(kind, sig_train, reweight_every=0):
         trace = np.zeros((K, 4))
         opts = R.ri_solve_opts(max_iter=K, rel_tol=0.0, prox_kind=kind, tau=tau, sigma_train=sig_train, L=L,
-                               check_every=50, x_true=x_true.data_ptr(), trace=trace.ctypes.data, use_graph=1)
+                               check_every=50, x_true=x_true.data_ptr(), trace=trace.ctypes.data, use_graph=1,
+                               reweight_every=reweight_every)
         xs = torch.empty_like(x_true)
         rep = R.pnp_solve(ctx, y, opts, xs)
         solve.x = xs
@@ -162,6 +210,7 @@ def run_pnp(args, R, synth, ctx, noise, x_true, L):
 
     fb_rep, fb_tr = solve(R.RI_PROX_HAAR, 0.0)
     log(f"FB x{fb_rep.iters} at sigma {sigma:.0e}: {fb_rep.ms:.1f} ms, SNR {fb_rep.snr_db:.2f} dB")
+    usara = None if args.no_usara else run_usara(args, R, ctx, x_true, fb_rep.snr_db - 0.5, solve)
     patches = torch.tensor(synth.training_patches(args.train_patches, 128), device=x_true.device)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -232,7 +281,8 @@ def run_pnp(args, R, synth, ctx, noise, x_true, L):
                                  "kernels": "k_conv_in, 7 x k_conv64<0>, k_conv64<2>, k_conv_sum (one application)"},
            "fne_norm_patches": fne_patches, "fne_norm_fixed_point": fne_fixed, "fne_lambda": args.fne_lambda,
            "train_steps": args.train_steps, "train_batch": args.train_batch, "train_s": train_s,
-           "train_tflops": train_flops / train_s / 1e12, "train_final_loss": hist[-1][1] if hist else None}
+           "train_tflops": train_flops / train_s / 1e12, "train_final_loss": hist[-1][1] if hist else None,
+           "usara": usara}
     log(f"PnP x{rep.iters}: {rep.ms:.1f} ms ({res['pnp_ms_per_iter']:.3f} ms/it), SNR {rep.snr_db:.2f} dB vs FB "
         f"{fb_rep.snr_db:.2f} dB; to {target:.2f} dB: PnP {res['pnp_ms_to_target']} ms vs FB "
         f"{res['fb_ms_to_target']} ms; fell back {rep.fell_back}")
@@ -301,6 +351,11 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="uv tile side (0: autotuned by the library)")
     ap.add_argument("--item-vis", type=int, default=0, help="visibilities per work item (0: library default)")
     ap.add_argument("--wstacks", type=int, default=0, help="w-stacks of the hybrid (0 or 1: w-kernels alone)")
+    ap.add_argument("--no-usara", action="store_true", help="skip the uSARA solve in the PnP comparison")
+    ap.add_argument("--sara-sub", type=int, default=5, help="dual forward-backward sub-iterations per SARA prox")
+    ap.add_argument("--sara-reweight", type=int, default=50, help="uSARA reweighting period (iterations)")
+    ap.add_argument("--sara-only", action="store_true",
+                    help="only time the SARA prox on the workload's image size (profiling)")
     ap.add_argument("--no-holo", action="store_true",
                     help="skip building the holographic matrix H = G^H G and timing Phi^dagger Phi through it")
     ap.add_argument("--holo-only", action="store_true", help="only the holographic measurement")
@@ -338,6 +393,32 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        return
+
+    if args.sara_only:
+        import torch
+
+        import paper_2207_11336_amd.ri as R
+        import synth
+        wl = synth.WORKLOADS[args.workload]
+        uvw = synth.random_uvw(64, 1.0, 0.0, seed=1)
+        ctx = R.ri_create(R.plan_desc(wl.N, 64, precision=32, g_mode=R.RI_G_OTF), uvw)
+        R.ri_sara_setup(ctx, args.sara_sub)
+        z = torch.tensor(synth.sky(wl.N), dtype=torch.float32, device="cuda:0")
+        out = torch.empty_like(z)
+        for _ in range(max(1, args.warmup)):
+            R.denoise(ctx, z, out, R.RI_PROX_SARA, 1e-3)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            R.denoise(ctx, z, out, R.RI_PROX_SARA, 1e-3)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        b = sara_prox_bytes(wl.N) * args.sara_sub
+        print(json.dumps({"sara_prox_ms": ms, "sub_iters": args.sara_sub, "sub_iter_ms": ms / args.sara_sub,
+                          "algorithmic_bytes": b, "gbs": b / (ms * 1e-3) / 1e9}))
         return
 
     if args.denoiser_only:

@@ -26,6 +26,7 @@
 // applies max(0, z - .) with the Dirac dual update fused.
 #include <cmath>
 #include <complex>
+#include <utility>
 
 #include "ri_internal.h"
 
@@ -49,6 +50,14 @@ template <> __device__ __forceinline__ double fg<double>(int b, int t) { return 
 template <> __device__ __forceinline__ float fh<float>(int b, int t) { return c_h32[b][t]; }
 template <> __device__ __forceinline__ float fg<float>(int b, int t) { return c_g32[b][t]; }
 
+// f(integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) { static_for_(f, std::make_integer_sequence<int, N>{}); }
+
 enum { FIN_DUAL = 0, FIN_WEIGHT = 1, FIN_COEF = 2 };
 enum { SYN_PROX = 0, SYN_PLAIN = 1 };
 
@@ -66,48 +75,91 @@ __device__ __forceinline__ void finalise(T *dst9, const T *w9, size_t i9, T val,
     }
 }
 
+// Column passes are register-blocked: a thread computes KB consecutive outputs
+// of one column from one window of inputs held in registers (2 KB + L - 2
+// inputs for analysis, KB + L/2 - 1 of each half for synthesis). Row passes
+// stage the row in LDS by coalesced loads, one output per lane per step. The
+// filter length L is a template parameter (one instantiation per basis, chosen
+// from blockIdx.z).
+constexpr int KB = 8;
+
+// f(std::integral_constant<int, L>) for the filter length L = 2 (b + 1) of basis b.
+template <typename F>
+__device__ __forceinline__ void with_length(int b, F &&f) {
+    switch (b) {
+        case 0: f(std::integral_constant<int, 2>{}); break;
+        case 1: f(std::integral_constant<int, 4>{}); break;
+        case 2: f(std::integral_constant<int, 6>{}); break;
+        case 3: f(std::integral_constant<int, 8>{}); break;
+        case 4: f(std::integral_constant<int, 10>{}); break;
+        case 5: f(std::integral_constant<int, 12>{}); break;
+        case 6: f(std::integral_constant<int, 14>{}); break;
+        default: f(std::integral_constant<int, 16>{}); break;
+    }
+}
+
 // Row analysis of the n x n block of every basis: in (basis stride in_bs) -> tmp.
+// Workgroup: one row of one basis, staged in LDS by coalesced loads; lane
+// outputs k = tid, tid + 256, ... of both halves.
 template <typename T>
 __global__ void __launch_bounds__(256) k_ana_rows(const T *__restrict__ in, int64_t in_bs, T *__restrict__ tmp,
                                                   int N, int n) {
-    const int b = blockIdx.z, row = blockIdx.y;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x, half = n >> 1;
-    if (k >= half) return;
+    extern __shared__ unsigned char smem_raw[];
+    T *row_s = reinterpret_cast<T *>(smem_raw);
+    const int b = blockIdx.z, row = blockIdx.y, half = n >> 1, m = n - 1;
     const T *src = in + b * in_bs + (size_t)row * N;
-    const int L = 2 * (b + 1), m = n - 1;
-    T a = 0, d = 0;
-    for (int t = 0; t < L; ++t) {
-        const T v = src[(2 * k + t) & m];
-        a += fh<T>(b, t) * v;
-        d += fg<T>(b, t) * v;
-    }
+    for (int e = threadIdx.x; e < n; e += blockDim.x) row_s[e] = src[e];
+    __syncthreads();
     T *dst = tmp + (size_t)b * N * N + (size_t)row * N;
-    dst[k] = a;
-    dst[half + k] = d;
+    with_length(b, [&](auto Lc) {
+        constexpr int L = decltype(Lc)::value;
+        for (int k = threadIdx.x; k < half; k += blockDim.x) {
+            T a = 0, d = 0;
+#pragma unroll
+            for (int t = 0; t < L; ++t) {
+                const T v = row_s[(2 * k + t) & m];
+                a += fh<T>(b, t) * v;
+                d += fg<T>(b, t) * v;
+            }
+            dst[k] = a;
+            dst[half + k] = d;
+        }
+    });
 }
 
 // Column analysis: tmp -> low-low block into work (unless last) and every
-// other coefficient finalised into dst9 (slot b + 1).
+// other coefficient finalised into dst9 (slot b + 1). Thread: column col,
+// outputs k0 .. k0 + KB - 1 of both halves.
 template <typename T, int FIN>
 __global__ void __launch_bounds__(256) k_ana_cols(const T *__restrict__ tmp, T *__restrict__ work, T *dst9,
                                                   const T *__restrict__ w9, int N, int n, int last, T scale, T par) {
     const int b = blockIdx.z;
     const int col = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int k = blockIdx.y * 4 + (threadIdx.x >> 6), half = n >> 1;
-    if (col >= n || k >= half) return;
+    const int k0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * KB, half = n >> 1, m = n - 1;
+    if (col >= n || k0 >= half) return;
     const size_t NN = (size_t)N * N;
     const T *src = tmp + b * NN + col;
-    const int L = 2 * (b + 1), m = n - 1;
-    T a = 0, d = 0;
-    for (int t = 0; t < L; ++t) {
-        const T v = src[(size_t)((2 * k + t) & m) * N];
-        a += fh<T>(b, t) * v;
-        d += fg<T>(b, t) * v;
-    }
     const size_t base9 = (size_t)(b + 1) * NN;
-    if (!last && col < half) work[b * NN + (size_t)k * N + col] = a;
-    else finalise<T, FIN>(dst9, w9, base9 + (size_t)k * N + col, a, scale, par);
-    finalise<T, FIN>(dst9, w9, base9 + (size_t)(half + k) * N + col, d, scale, par);
+    with_length(b, [&](auto Lc) {
+        constexpr int L = decltype(Lc)::value, NR = 2 * KB + L - 2;
+        T r[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) r[j] = src[(size_t)((2 * k0 + j) & m) * N];
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+            const int k = k0 + kk;
+            if (k >= half) break;
+            T a = 0, d = 0;
+#pragma unroll
+            for (int t = 0; t < L; ++t) {
+                a += fh<T>(b, t) * r[2 * kk + t];
+                d += fg<T>(b, t) * r[2 * kk + t];
+            }
+            if (!last && col < half) work[b * NN + (size_t)k * N + col] = a;
+            else finalise<T, FIN>(dst9, w9, base9 + (size_t)k * N + col, a, scale, par);
+            finalise<T, FIN>(dst9, w9, base9 + (size_t)(half + k) * N + col, d, scale, par);
+        }
+    });
 }
 
 // Dirac slot of the analysis (weights or plain coefficients).
@@ -117,74 +169,140 @@ __global__ void k_ana_dirac(const T *__restrict__ x, T *dst9, int64_t n, T scale
         finalise<T, FIN>(dst9, nullptr, (size_t)i, x[i], scale, par);
 }
 
+// Synthesis of 2 KB consecutive outputs i0 .. i0 + 2 KB - 1 (i0 even) along one
+// axis from the low half A and the high half D (element k at A[k * stride]):
+// x[i] = sum_{t = i mod 2} h[t] A[k] + g[t] D[k], k = (i - t)/2 mod half.
+template <typename T, int L>
+__device__ __forceinline__ void syn_block(int b, const T *A, const T *D, size_t stride, int i0, int half, T *x) {
+    constexpr int S2 = L / 2, NA = KB + S2 - 1;
+    const int kb0 = (i0 >> 1) - S2 + 1, hm = half - 1;
+    T ar[NA], dr[NA];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+        const size_t k = (size_t)((kb0 + j) & hm);
+        ar[j] = A[k * stride];
+        dr[j] = D[k * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            T v = 0;
+#pragma unroll
+            for (int s2 = 0; s2 < S2; ++s2) {
+                const int t = par + 2 * s2;
+                v += fh<T>(b, t) * ar[u - s2 + S2 - 1] + fg<T>(b, t) * dr[u - s2 + S2 - 1];
+            }
+            x[2 * u + par] = v;
+        }
+    }
+}
+
 // Column synthesis of level block n: the coarse block (rows and columns < n/2)
 // from work (or from the coefficients at the coarsest level), the rest from
-// the coefficients v9 (slot b + 1) -> tmp.
+// the coefficients v9 (slot b + 1) -> tmp. Thread: column col, rows i0 .. i0 + 2 KB - 1.
 template <typename T>
 __global__ void __launch_bounds__(256) k_syn_cols(const T *__restrict__ v9, const T *__restrict__ work,
                                                   T *__restrict__ tmp, int N, int n, int coarsest) {
     const int b = blockIdx.z;
     const int col = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int i = blockIdx.y * 4 + (threadIdx.x >> 6), half = n >> 1;
-    if (col >= n || i >= n) return;
+    const int i0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * 2 * KB, half = n >> 1;
+    if (col >= n || i0 >= n) return;
     const size_t NN = (size_t)N * N;
     const T *cf = v9 + (size_t)(b + 1) * NN + col;
     const T *lo = (!coarsest && col < half) ? work + b * NN + col : cf;
-    const int L = 2 * (b + 1), m = n - 1;
-    T x = 0;
-    for (int t = i & 1; t < L; t += 2) {
-        const int k = ((i - t) & m) >> 1;
-        x += fh<T>(b, t) * lo[(size_t)k * N] + fg<T>(b, t) * cf[(size_t)(half + k) * N];
-    }
-    tmp[b * NN + (size_t)i * N + col] = x;
+    T x[2 * KB];
+    with_length(b, [&](auto Lc) { syn_block<T, decltype(Lc)::value>(b, lo, cf + (size_t)half * N, N, i0, half, x); });
+    T *dst = tmp + b * NN + col;
+#pragma unroll
+    for (int u = 0; u < 2 * KB; ++u)
+        if (i0 + u < n) dst[(size_t)(i0 + u) * N] = x[u];
 }
 
-// Row synthesis of level block n (not the last): tmp -> work.
+// Row synthesis of one staged row (low half A = s[0, half), high half D =
+// s[half, n)) at output j: sum_{t = j mod 2} h[t] A[k] + g[t] D[k], k = (j - t)/2 mod half.
+template <typename T, int L>
+__device__ __forceinline__ T syn_row_at(int b, const T *row_s, int j, int half) {
+    const int hm = half - 1, j2 = j >> 1, par = j & 1;
+    T x = 0;
+#pragma unroll
+    for (int s2 = 0; s2 < L / 2; ++s2) {
+        const int k = (j2 - s2) & hm;
+        x += fh<T>(b, par + 2 * s2) * row_s[k] + fg<T>(b, par + 2 * s2) * row_s[half + k];
+    }
+    return x;
+}
+
+// Row synthesis of level block n (not the last): tmp -> work. Workgroup: one
+// row of one basis staged in LDS.
 template <typename T>
 __global__ void __launch_bounds__(256) k_syn_rows(const T *__restrict__ tmp, T *__restrict__ work, int N, int n) {
-    const int b = blockIdx.z, row = blockIdx.y;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x, half = n >> 1;
-    if (j >= n) return;
+    extern __shared__ unsigned char smem_raw[];
+    T *row_s = reinterpret_cast<T *>(smem_raw);
+    const int b = blockIdx.z, row = blockIdx.y, half = n >> 1;
     const size_t NN = (size_t)N * N;
     const T *src = tmp + b * NN + (size_t)row * N;
-    const int L = 2 * (b + 1), m = n - 1;
-    T x = 0;
-    for (int t = j & 1; t < L; t += 2) {
-        const int k = ((j - t) & m) >> 1;
-        x += fh<T>(b, t) * src[k] + fg<T>(b, t) * src[half + k];
-    }
-    work[b * NN + (size_t)row * N + j] = x;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) row_s[e] = src[e];
+    __syncthreads();
+    T *dst = work + b * NN + (size_t)row * N;
+    with_length(b, [&](auto Lc) {
+        for (int j = threadIdx.x; j < n; j += blockDim.x) dst[j] = syn_row_at<T, decltype(Lc)::value>(b, row_s, j, half);
+    });
 }
 
 // Last row synthesis (n = N), summed over the 8 bases plus the Dirac slot:
 // SYN_PLAIN: x = scale * s; SYN_PROX: x = max(0, z - scale * s) and the
-// Dirac dual update v0 = clip(v0 + scale * x, -t w0, t w0).
+// Dirac dual update v0 = clip(v0 + scale * x, -t w0, t w0). Workgroup: one
+// row; the 8 bases' rows pass through LDS one after another, each lane
+// accumulating its pixels j = tid + 256 q in registers.
+constexpr int FINAL_MAXQ = 16;   // N <= 4096 with 256 lanes
 template <typename T, int MODE>
 __global__ void __launch_bounds__(256) k_syn_final(const T *__restrict__ tmp, T *v9, const T *__restrict__ w9,
                                                    const T *__restrict__ z, T *__restrict__ x, int N, T scale,
                                                    T thr) {
-    const int row = blockIdx.y;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x, half = N >> 1;
-    if (j >= N) return;
+    extern __shared__ unsigned char smem_raw[];
+    T *row_s = reinterpret_cast<T *>(smem_raw);
+    const int row = blockIdx.y, half = N >> 1, tid = threadIdx.x;
+    const int nq = (N + 255) >> 8;
     const size_t NN = (size_t)N * N;
-    const size_t p = (size_t)row * N + j;
-    const int m = N - 1;
-    T s = v9[p];
-    for (int b = 0; b < NW; ++b) {
-        const T *src = tmp + b * NN + (size_t)row * N;
-        const int L = 2 * (b + 1);
-        for (int t = j & 1; t < L; t += 2) {
-            const int k = ((j - t) & m) >> 1;
-            s += fh<T>(b, t) * src[k] + fg<T>(b, t) * src[half + k];
-        }
+    T acc[FINAL_MAXQ], pre[FINAL_MAXQ];
+#pragma unroll
+    for (int q = 0; q < FINAL_MAXQ; ++q) {
+        acc[q] = 0;
+        pre[q] = (q < nq && tid + 256 * q < N) ? tmp[(size_t)row * N + tid + 256 * q] : (T)0;
     }
-    if (MODE == SYN_PLAIN) {
-        x[p] = scale * s;
-    } else {
-        const T xo = fmax((T)0, z[p] - scale * s);
-        x[p] = xo;
-        const T lim = thr * w9[p];
-        v9[p] = fmin(fmax(v9[p] + scale * xo, -lim), lim);
+    // the next basis's row is loaded into registers while the current one is used
+    static_for<NW>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < FINAL_MAXQ; ++q)
+            if (q < nq && tid + 256 * q < N) row_s[tid + 256 * q] = pre[q];
+        __syncthreads();
+        if (b + 1 < NW) {
+            const T *nxt = tmp + (b + 1) * NN + (size_t)row * N;
+#pragma unroll
+            for (int q = 0; q < FINAL_MAXQ; ++q)
+                if (q < nq && tid + 256 * q < N) pre[q] = nxt[tid + 256 * q];
+        }
+#pragma unroll
+        for (int q = 0; q < FINAL_MAXQ; ++q)
+            if (q < nq && tid + 256 * q < N) acc[q] += syn_row_at<T, 2 * (b + 1)>(b, row_s, tid + 256 * q, half);
+    });
+#pragma unroll
+    for (int q = 0; q < FINAL_MAXQ; ++q) {
+        const int j = tid + 256 * q;
+        if (q >= nq || j >= N) break;
+        const size_t p = (size_t)row * N + j;
+        const T tot = v9[p] + acc[q];
+        if (MODE == SYN_PLAIN) {
+            x[p] = scale * tot;
+        } else {
+            const T xo = fmax((T)0, z[p] - scale * tot);
+            x[p] = xo;
+            const T lim = thr * w9[p];
+            v9[p] = fmin(fmax(v9[p] + scale * xo, -lim), lim);
+        }
     }
 }
 
@@ -302,9 +420,9 @@ void analysis(ri_ctx *c, const T *x, T *dst9, T par, bool dirac, hipStream_t s) 
         const int n = N >> l;
         const T *in = l == 0 ? x : work;
         const int64_t in_bs = l == 0 ? 0 : (int64_t)N * N;
-        hipLaunchKernelGGL(k_ana_rows<T>, dim3(cdiv(n / 2, 256), n, NW), dim3(256), 0, s, in, in_bs, tmp, N, n);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ana_cols<T, FIN>), dim3(cdiv(n, 64), cdiv(n / 2, 4), NW), dim3(256), 0,
-                           s, tmp, work, dst9, w9, N, n, l == LEVELS - 1 ? 1 : 0, scale, par);
+        hipLaunchKernelGGL(k_ana_rows<T>, dim3(1, n, NW), dim3(256), sizeof(T) * n, s, in, in_bs, tmp, N, n);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ana_cols<T, FIN>), dim3(cdiv(n, 64), cdiv(n / 2, 4 * KB), NW),
+                           dim3(256), 0, s, tmp, work, dst9, w9, N, n, l == LEVELS - 1 ? 1 : 0, scale, par);
     }
 }
 
@@ -317,12 +435,12 @@ void synthesis(ri_ctx *c, T *v9, const T *z, T *x, T thr, hipStream_t s) {
     T *work = (T *)st.work, *tmp = (T *)st.tmp;
     for (int l = LEVELS - 1; l >= 0; --l) {
         const int n = N >> l;
-        hipLaunchKernelGGL(k_syn_cols<T>, dim3(cdiv(n, 64), cdiv(n, 4), NW), dim3(256), 0, s, v9, work, tmp, N, n,
-                           l == LEVELS - 1 ? 1 : 0);
+        hipLaunchKernelGGL(k_syn_cols<T>, dim3(cdiv(n, 64), cdiv(n, 4 * 2 * KB), NW), dim3(256), 0, s, v9, work, tmp,
+                           N, n, l == LEVELS - 1 ? 1 : 0);
         if (l > 0)
-            hipLaunchKernelGGL(k_syn_rows<T>, dim3(cdiv(n, 256), n, NW), dim3(256), 0, s, tmp, work, N, n);
+            hipLaunchKernelGGL(k_syn_rows<T>, dim3(1, n, NW), dim3(256), sizeof(T) * n, s, tmp, work, N, n);
     }
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_syn_final<T, MODE>), dim3(cdiv(N, 256), N), dim3(256), 0, s, tmp, v9,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_syn_final<T, MODE>), dim3(1, N), dim3(256), sizeof(T) * N, s, tmp, v9,
                        (const T *)st.w, z, x, N, scale, thr);
 }
 

@@ -2,8 +2,8 @@
 nothing in the product imports it).
 
 Paper passages followed (section "uSARA's handcrafted denoiser"): the prior
-is non-negativity plus sparsity in an overcomplete dictionary Psi, a
-normalised concatenation of orthogonal wavelet bases, under the log-sum
+is non-negativity plus sparsity in an overcomplete dictionary Psi that stacks
+several orthogonal wavelet bases under one normalisation, with the log-sum
 penalty lambda sum_n rho log(1 + |(Psi^dagger x)_n| / rho); the non-convex
 problem is solved by reweighting: a series of weighted-l1 + non-negativity
 problems, each by FB, whose prox has no closed form and is computed by

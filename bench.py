@@ -290,7 +290,7 @@ def run_pnp(args, R, synth, ctx, noise, x_true, L):
     return res
 
 
-def run_holo(args, R, wl, uvw, x_true):
+def run_holo(args, R, wl, uvw, x_true, L=None, tau=None):
     """Phi^dagger Phi through the stored holographic matrix (appendix E) against
     the pass over the visibilities (the fused gradient with y = 0), FP32, on
     the same plan: build time and storage, per-application times, the
@@ -323,17 +323,36 @@ def run_holo(args, R, wl, uvw, x_true):
         res[name] = {"ms": 1e3 * el / K, "kernel_ms": kt.tiles_ms / max(1, kt.n_tiles),
                      "fft_ms": kt.fft_ms / max(1, kt.n_fft)}
     err = float(torch.linalg.vector_norm((out - g).double()) / torch.linalg.vector_norm(g.double()))
+    # FB solves (Haar prox, hipGraph replay) with gradients through H and over the visibilities
+    import numpy as np
+    L = L or R.ri_power_norm(ctx, max_it=30, rtol=0.0)[0]
+    y = torch.empty(wl.M, dtype=torch.complex64, device=x_true.device)
+    R.phi_forward(ctx, x_true, y)
+    tau = tau or float(torch.linalg.vector_norm(y.to(torch.complex128))) * 10 ** (-40 / 20) / math.sqrt(wl.M)
+    solves = {}
+    for use_holo in (0, 1):
+        K = 100
+        trace = np.zeros((K, 4))
+        opts = R.ri_solve_opts(max_iter=K, rel_tol=0.0, prox_kind=R.RI_PROX_HAAR, tau=tau, L=L, check_every=50,
+                               x_true=x_true.data_ptr(), trace=trace.ctypes.data, use_graph=1, use_holo=use_holo)
+        xs = torch.empty_like(x_true)
+        rep = R.pnp_solve(ctx, y, opts, xs)
+        solves[use_holo] = (rep.ms / rep.iters, rep.snr_db)
     apply_ms = res["holo"]["kernel_ms"]
     gbs = s.bytes / (apply_ms * 1e-3) / 1e9
     rep = {"tiles": s.tiles, "bytes": s.bytes, "reach": s.max_reach, "build_ms": s.build_ms, "pairs": s.pairs,
            "normal_ms": res["holo"]["ms"], "apply_kernel_ms": apply_ms, "apply_gbs": gbs,
            "apply_frac_hbm": gbs / HBM_PEAK_GBS, "vis_pass_normal_ms": res["visibilities"]["ms"],
            "vis_pass_kernel_ms": res["visibilities"]["kernel_ms"], "rel_diff": err,
-           "break_even_M": wl.M * apply_ms / res["visibilities"]["kernel_ms"]}
+           "break_even_M": wl.M * apply_ms / res["visibilities"]["kernel_ms"],
+           "fb_ms_per_iter_holo": solves[1][0], "fb_ms_per_iter_vis": solves[0][0],
+           "fb_snr_100_holo": solves[1][1], "fb_snr_100_vis": solves[0][1]}
     log(f"[holo] normal through H {rep['normal_ms']:.3f} ms (banded product {apply_ms:.3f} ms, {gbs:.0f} GB/s = "
         f"{100 * rep['apply_frac_hbm']:.1f}% of HBM peak) vs pass over the visibilities {rep['vis_pass_normal_ms']:.3f}"
         f" ms (tile kernel {rep['vis_pass_kernel_ms']:.3f} ms); rel diff {err:.2e}; break-even M "
         f"{rep['break_even_M']:.3e}")
+    log(f"[holo] FB x100 through H {solves[1][0]:.3f} ms/it (SNR {solves[1][1]:.3f} dB) vs over the visibilities "
+        f"{solves[0][0]:.3f} ms/it (SNR {solves[0][1]:.3f} dB)")
     R.ri_holo_release(ctx)
     ctx.close()
     torch.cuda.empty_cache()
@@ -602,7 +621,7 @@ def main():
         del yb
         torch.cuda.empty_cache()
 
-    holo = None if args.no_holo else run_holo(args, R, wl, uvw, x_true)
+    holo = None if args.no_holo else run_holo(args, R, wl, uvw, x_true, shared["L"], shared["tau"])
 
     cpu = None
     if not args.no_cpu:

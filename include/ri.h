@@ -200,6 +200,13 @@ typedef struct {
     int32_t reweight_every;/* SARA only: after every this many iterations the log-sum weights
                               are renewed, w = rho / (rho + |Psi^dagger x|) with rho = t
                               (0: plain weighted l1 with w = 1, no reweighting) */
+    int32_t use_holo;      /* 1: every gradient through the holographic matrix built by
+                              ri_holo_build, Re{Z^dagger F^dagger H F Z} x - Re{Phi^dagger y}, with
+                              Re{Phi^dagger y} and ||y||^2 from one pass over the visibilities at the
+                              start; the reported ||Phi x - y||^2 is then
+                              <x, Re Phi^dagger Phi x> - 2 <x, Re Phi^dagger y> + ||y||^2 (FP64 sums of
+                              context-precision terms, so it loses relative accuracy as the residual
+                              approaches the noise level). 0: the pass over the visibilities. */
 } ri_solve_opts;
 
 typedef struct {

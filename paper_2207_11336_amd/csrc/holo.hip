@@ -92,6 +92,11 @@ __global__ void __launch_bounds__(1024) k_holo_apply(const cx<T> *__restrict__ H
     }
 }
 
+// ||Phi x - y||^2 = <x, Re Phi^dagger Phi x> - 2 <x, Re Phi^dagger y> + ||y||^2 from device scalars.
+__global__ void k_holo_r2(double *out, const double *dots, const double *yy) {
+    out[0] = dots[0] - 2.0 * dots[1] + yy[0];
+}
+
 template <typename T>
 size_t apply_lds(int R) {
     const size_t RN = (size_t)(HOLO_T + 2 * R) * (HOLO_T + R);
@@ -185,6 +190,19 @@ void holo_apply(ri_ctx *c, const cx<T> *X, cx<T> *Y, hipStream_t s) {
     RI_CHECK_HIP(hipGetLastError());
 }
 
+template <typename T>
+void holo_normal(ri_ctx *c, Prec<T> &p, const T *x, T *out, hipStream_t s) {
+    fwd_zpad_fft<T>(c, p, x, s);
+    holo_apply<T>(c, p.gridB, p.gridA, s);
+    adj_fft_crop<T>(c, p, out, s);
+}
+
+void holo_residual(double *out, const double *dots, const double *yy, hipStream_t s) {
+    hipLaunchKernelGGL(k_holo_r2, dim3(1), dim3(1), 0, s, out, dots, yy);
+}
+
+template void holo_normal<float>(ri_ctx *, Prec<float> &, const float *, float *, hipStream_t);
+template void holo_normal<double>(ri_ctx *, Prec<double> &, const double *, double *, hipStream_t);
 template void holo_apply<float>(ri_ctx *, const cx<float> *, cx<float> *, hipStream_t);
 template void holo_apply<double>(ri_ctx *, const cx<double> *, cx<double> *, hipStream_t);
 

@@ -117,17 +117,36 @@ const cx<T> *resolve_data(ri_ctx *c, const void *y, hipStream_t s) {
 // One iteration of eq. (A2) with the data in internal order (or none). norms
 // (dev double[3], or [4] with x_true): ||x_out - x_in||^2, ||x_out||^2,
 // ||Phi x_in - y||^2 and ||alpha x_out - x_true||^2.
+// With holo_dirty (and holo_yy), the gradient comes from the stored holographic
+// matrix: g = Re{Z^dagger F^dagger H F Z} x - Re{Phi^dagger y}, and
+// ||Phi x - y||^2 = <x, Re Phi^dagger Phi x> - 2 <x, Re Phi^dagger y> + ||y||^2.
 template <typename T>
 void fb_step_sorted(ri_ctx *c, const T *x_in, const cx<T> *ys, double gamma, int kind, double param, T *x_out,
-                    double *norms, const T *x_true, double alpha, hipStream_t s) {
+                    double *norms, const T *x_true, double alpha, hipStream_t s, const T *holo_dirty = nullptr,
+                    const double *holo_yy = nullptr) {
     Prec<T> &p = prec<T>(c);
-    do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, x_in, ys, p.img0, s);
+    const bool holo = holo_dirty != nullptr;
+    if (holo) {
+        const int64_t nn = (int64_t)c->N * c->N;
+        holo_normal<T>(c, p, x_in, p.img0, s);
+        if (norms) {
+            double *dots = c->d_scalars + 40;
+            dot_partials<T>(x_in, p.img0, nn, img_part(c), s);
+            reduce_partials(img_part(c), 1024, 1, 1, dots, s);
+            dot_partials<T>(x_in, holo_dirty, nn, img_part(c), s);
+            reduce_partials(img_part(c), 1024, 1, 1, dots + 1, s);
+            holo_residual(norms + 2, dots, holo_yy, s);
+        }
+        axpby<T>(p.img0, p.img0, (T)1, holo_dirty, (T)(-1), nn, s);
+    } else {
+        do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, x_in, ys, p.img0, s);
+    }
     if (kind == RI_PROX_HAAR) {
         const int nwg = ((c->N / 16) * (c->N / 16) + 3) / 4;
         haar_prox<T>(c, x_in, p.img0, (T)gamma, nullptr, (T)param, x_out, img_part(c), s);
         if (norms) {
             reduce_partials(img_part(c), nwg, 2, 2, norms, s);
-            reduce_partials(tile_part(c), tiles_partials(c), 1, 1, norms + 2, s);
+            if (!holo) reduce_partials(tile_part(c), tiles_partials(c), 1, 1, norms + 2, s);
         }
     } else {
         // z = x - gamma g, x_out = D(z): the CNN facet by facet (PnP step) or
@@ -147,7 +166,7 @@ void fb_step_sorted(ri_ctx *c, const T *x_in, const cx<T> *ys, double gamma, int
             reduce_partials(img_part(c), 1024, 1, 1, norms, s);
             dot_partials<T>(x_out, x_out, n, img_part(c), s);
             reduce_partials(img_part(c), 1024, 1, 1, norms + 1, s);
-            reduce_partials(tile_part(c), tiles_partials(c), 1, 1, norms + 2, s);
+            if (!holo) reduce_partials(tile_part(c), tiles_partials(c), 1, 1, norms + 2, s);
         }
     }
     if (norms && x_true) {
@@ -354,6 +373,18 @@ bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_
         rr.t_or_sigma = param;
         if (kind == RI_PROX_SARA) sara_setup(c, 0, s);   // v = 0, w = 1 (plain weighted l1 first)
         T *xa = (T *)dev_alloc(c, sizeof(T) * n); owned.push_back(xa);
+        T *hdirty = nullptr;
+        double *hyy = nullptr;
+        if (o.use_holo) {
+            // Re{Phi^dagger y} and ||y||^2 from one pass over the visibilities at x = 0
+            require(c->holo.ready, "use_holo needs the holographic matrix (ri_holo_build)");
+            hdirty = (T *)dev_alloc(c, sizeof(T) * n); owned.push_back(hdirty);
+            hyy = (double *)dev_alloc(c, sizeof(double)); owned.push_back(hyy);
+            fill_real<T>(xa, n, (T)0, s);
+            do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, xa, ys, hdirty, s);
+            reduce_partials(tile_part(c), tiles_partials(c), 1, 1, hyy, s);
+            axpby<T>(hdirty, hdirty, (T)(-1), nullptr, (T)0, n, s);
+        }
         T *xb = (T *)dev_alloc(c, sizeof(T) * n); owned.push_back(xb);
         T *xsave = (T *)dev_alloc(c, sizeof(T) * n); owned.push_back(xsave);
         double *slots = (double *)dev_alloc(c, sizeof(double) * 8); owned.push_back(slots);
@@ -378,8 +409,8 @@ bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_
             if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
             RI_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             try {
-                fb_step_sorted<T>(c, xa, ys, rr.gamma, kd, prm, xb, slots, xt, rr.alpha, s);
-                fb_step_sorted<T>(c, xb, ys, rr.gamma, kd, prm, xa, slots + 4, xt, rr.alpha, s);
+                fb_step_sorted<T>(c, xa, ys, rr.gamma, kd, prm, xb, slots, xt, rr.alpha, s, hdirty, hyy);
+                fb_step_sorted<T>(c, xb, ys, rr.gamma, kd, prm, xa, slots + 4, xt, rr.alpha, s, hdirty, hyy);
             } catch (...) {
                 hipGraph_t g2 = nullptr;
                 (void)hipStreamEndCapture(s, &g2);
@@ -404,7 +435,7 @@ bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_
                 RI_CHECK_HIP(hipMemcpyAsync(nrm + 4 * k, slots, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
                 k += 2;
             } else {
-                fb_step_sorted<T>(c, xa, ys, rr.gamma, kind, param, xb, nrm + 4 * k, xt, rr.alpha, s);
+                fb_step_sorted<T>(c, xa, ys, rr.gamma, kind, param, xb, nrm + 4 * k, xt, rr.alpha, s, hdirty, hyy);
                 RI_CHECK_HIP(hipMemcpyAsync(xa, xb, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
                 k += 1;
             }
@@ -900,17 +931,8 @@ ri_status ri_holo_normal(ri_ctx *c, const void *x, void *out, ri_stream s) {
     return guard(c, [&] {
         require(x && out, "x or out is NULL");
         require(c->holo.ready, "no holographic matrix: call ri_holo_build first");
-        if (c->d.precision == 32) {
-            Prec<float> &p = c->p32;
-            fwd_zpad_fft<float>(c, p, (const float *)x, st(s));
-            holo_apply<float>(c, p.gridB, p.gridA, st(s));
-            adj_fft_crop<float>(c, p, (float *)out, st(s));
-        } else {
-            Prec<double> &p = c->p64;
-            fwd_zpad_fft<double>(c, p, (const double *)x, st(s));
-            holo_apply<double>(c, p.gridB, p.gridA, st(s));
-            adj_fft_crop<double>(c, p, (double *)out, st(s));
-        }
+        if (c->d.precision == 32) holo_normal<float>(c, c->p32, (const float *)x, (float *)out, st(s));
+        else holo_normal<double>(c, c->p64, (const double *)x, (double *)out, st(s));
     });
 }
 

@@ -233,6 +233,10 @@ void holo_build(ri_ctx *c, const View &v64, hipStream_t s);
 void holo_free(ri_ctx *c);
 // Y = H X on the N' x N' grid (Y is overwritten).
 template <typename T> void holo_apply(ri_ctx *c, const cx<T> *X, cx<T> *Y, hipStream_t s);
+// out = Re{Z^dagger F^dagger H F Z} x (uses p.gridA and p.gridB).
+template <typename T> void holo_normal(ri_ctx *c, Prec<T> &p, const T *x, T *out, hipStream_t s);
+// out[0] = dots[0] - 2 dots[1] + yy[0] (the residual norm from the normal operator).
+void holo_residual(double *out, const double *dots, const double *yy, hipStream_t s);
 int tiles_partials(ri_ctx *c);
 
 // image.hip

@@ -49,7 +49,7 @@ class ri_solve_opts(ctypes.Structure):
     _fields_ = [("max_iter", c_int32), ("rel_tol", c_double), ("prox_kind", c_int32), ("tau", c_double),
                 ("sigma_train", c_double), ("L", c_double), ("check_every", c_int32), ("x_true", c_void_p),
                 ("trace", c_void_p), ("use_graph", c_int32), ("diverge_checks", c_int32),
-                ("reweight_every", c_int32)]
+                ("reweight_every", c_int32), ("use_holo", c_int32)]
 
 
 class ri_solve_report(ctypes.Structure):

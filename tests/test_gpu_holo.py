@@ -199,3 +199,47 @@ def test_full_size_normal_through_h():
     print(f"C1: normal through H against the visibility pass {e:.2e}")
     assert e <= 1e-5
     R.ri_holo_release(ctx)
+
+
+@pytest.mark.parametrize("prec,graph", [(64, 1), (64, 0), (32, 1)])
+def test_solve_through_h_matches_the_visibility_solve(case, prec, graph):
+    """pnp_solve with use_holo: FB (Haar) iterations whose gradients come from the
+    stored H reach the same iterates, residuals and SNR trace as the solve over the
+    visibilities."""
+    from oracle import fb as OF
+    W, uvw, op, _ = case
+    x_true = synth.sky(N, seed=7, n_compact=8, n_ext=1)
+    y0 = op.phi(x_true)
+    tau = OF.tau_from_isnr(y0, 30.0)
+    y = y0 + OF.complex_noise(tau, synth.noise_normals(uvw.shape[0], synth.SEED_NOISE))
+    ft, ct = _types(prec)
+    ctx = _ctx(uvw, W, prec)
+    R.ri_holo_build(ctx)
+    yt = torch.tensor(y, dtype=ct, device=DEV)
+    xt = torch.tensor(x_true, dtype=ft, device=DEV)
+    L, _ = R.ri_power_norm(ctx, max_it=300, rtol=1e-10)
+    out, tr = {}, {}
+    for use_holo in (0, 1):
+        trace = np.zeros((40, 4))
+        opts = R.ri_solve_opts(max_iter=40, rel_tol=0.0, prox_kind=R.RI_PROX_HAAR, tau=tau, L=L, check_every=10,
+                               x_true=xt.data_ptr(), trace=trace.ctypes.data, use_graph=graph, use_holo=use_holo)
+        xs = torch.empty(N, N, dtype=ft, device=DEV)
+        rep = R.pnp_solve(ctx, yt, opts, xs)
+        assert rep.iters == 40
+        out[use_holo], tr[use_holo] = xs.cpu().numpy(), trace
+    e_x = rel(out[1], out[0])
+    e_r = np.abs(tr[1][:, 1] - tr[0][:, 1]).max() / tr[0][:, 1].max()
+    e_snr = np.abs(tr[1][:, 2] - tr[0][:, 2]).max()
+    print(f"FP{prec} graph {graph}: x through H vs over the visibilities {e_x:.2e}; residual trace {e_r:.2e}; "
+          f"SNR trace {e_snr:.2e} dB (final {tr[1][-1, 2]:.3f} dB)")
+    tol_x, tol_r = (1e-11, 1e-9) if prec == 64 else (1e-4, 1e-3)
+    assert e_x <= tol_x and e_r <= tol_r and e_snr <= (1e-9 if prec == 64 else 1e-3)
+
+
+def test_solve_through_h_needs_h(case):
+    W, uvw, _, _ = case
+    ctx = _ctx(uvw, W, 32)
+    opts = R.ri_solve_opts(max_iter=2, prox_kind=R.RI_PROX_HAAR, tau=1.0, L=1.0, check_every=1, use_holo=1)
+    with pytest.raises(R.RIError):
+        R.pnp_solve(ctx, torch.zeros(uvw.shape[0], dtype=torch.complex64, device=DEV), opts,
+                    torch.empty(N, N, device=DEV))

@@ -62,11 +62,17 @@ double *tile_part(ri_ctx *c) { return c->d_partials; }
 double *img_part(ri_ctx *c) { return c->d_partials + tiles_partials(c); }
 
 // FP64 view for the power iteration: the main view when it already carries
-// FP64 fractions at a tile that fits FP64 subgrids, else a dedicated one.
+// FP64 fractions at a tile that fits FP64 subgrids, else a dedicated one at
+// the main view's (autotuned) tile, halved until its FP64 subgrids fit (at C1
+// tile 8 runs the FP64 pass 8% faster than tile 16).
 const View &view_fp64(ri_ctx *c) {
     if (c->view.frac_bytes == 8 && lds_for_tile(c->view.tile, c->H, 16) <= (size_t)c->dev.lds_per_block)
         return c->view;
-    if (!c->view64.items) build_view(c, c->view64, pick_tile(c, 0, 16), 8);
+    if (!c->view64.items) {
+        int t = c->view.tile > 0 ? c->view.tile : 16;
+        while (t > 8 && lds_for_tile(t, c->H, 16) > (size_t)c->dev.lds_per_block) t /= 2;
+        build_view(c, c->view64, pick_tile(c, t, 16), 8);
+    }
     return c->view64;
 }
 

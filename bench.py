@@ -41,11 +41,12 @@ def log(msg: str):
 
 
 def csr_tile_bytes(nnz: int, M: int, Np: int) -> float:
-    """Algorithmic HBM bytes of one fused CSR tile pass (FP32): each stored G
-    entry once (8 B value + 4 B column), per visibility its row pointer (8 B),
-    data (8 B), cell (4 B) and plane (2 B), the input grid read once and the
-    output grid written once (8 B per cell each)."""
-    return 12.0 * nnz + 22.0 * M + 16.0 * Np * Np
+    """Algorithmic HBM bytes of one fused tile pass with G stored (FP32): each
+    stored G value once (8 B; the columns follow from the row's window), per
+    visibility its row pointer (8 B), data (8 B), cell (4 B) and plane (2 B),
+    the input grid read once and the output grid written once (8 B per cell
+    each)."""
+    return 8.0 * nnz + 22.0 * M + 16.0 * Np * Np
 
 
 def measured_traffic(mode: str, tile: int):

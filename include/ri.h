@@ -66,7 +66,9 @@ typedef struct {
     double cell_rad;       /* pixel size delta [rad], enters the w-term */
     double w_max;          /* W [wavelengths]: the w-plane table spans [-W, W]; 0 => no w-term */
     int32_t n_wplanes;     /* odd number of w-planes (w = 0 is the centre plane) */
-    int32_t g_mode;        /* RI_G_CSR: G stored as CSR (complex values + int32 columns);
+    int32_t g_mode;        /* RI_G_CSR: G stored row by row: the complex values of each row's
+                              window in window order, int64 row pointers; the columns follow
+                              from the window and are not stored;
                               RI_G_OTF: G rows computed on the fly from the KB and w-tables */
     int32_t precision;     /* 32 or 64: element type of Phi, Phi^dagger and the FFT */
     int32_t tile;          /* uv tile side in grid cells (8..128, divides N'); 0 => autotuned at

@@ -49,7 +49,6 @@ struct TileArgs {
     const int32_t *perm;
     const int64_t *rowptr;
     const cx<T> *gval;
-    const int32_t *gcol;
     const cx<T> *X;
     cx<T> *Y;
     const cx<T> *ysorted;
@@ -310,10 +309,11 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
                     li[i] = base;
                     const int t = lane + 16 * i;
                     if (i < NI && t < SS) {
+                        // entry t of the row is window cell (t / S, t % S): its
+                        // column is implied by the row's window, only the value is stored
                         wv[i] = a.gval[rp + t];
-                        const int col = a.gcol[rp + t];
-                        const int gy = col >> a.logNp, gx = col & Npm;
-                        li[i] = ((gy - y0) & Npm) * W + ((gx - x0) & Npm);
+                        const int ay = t / S;
+                        li[i] = base + ay * W + (t - ay * S);
                         if (OP & OP_DEGRID) acc = acc + wv[i] * Xs[li[i]];
                     }
                 }
@@ -364,10 +364,11 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
     }
 }
 
-// CSR G fill: values (FP64 arithmetic, rounded to T) and flat columns.
+// Stored G fill: per row the values of its S x S window in row-major window
+// order (FP64 arithmetic, rounded to T); the columns follow from the window.
 template <typename T>
 __global__ void __launch_bounds__(256) k_fill_csr(TileArgs<double> a, int64_t M, const int64_t *rowptr,
-                                                  cx<T> *val, int32_t *col) {
+                                                  cx<T> *val) {
     __shared__ double kbs[GROUPS * SCR_KB];
     __shared__ cx<double> wks[GROUPS * SCR_W];
     __shared__ cx<double> gs[GROUPS * SCR_G];
@@ -375,10 +376,8 @@ __global__ void __launch_bounds__(256) k_fill_csr(TileArgs<double> a, int64_t M,
     double *kbg = kbs + grp * SCR_KB;
     cx<double> *wk = wks + grp * SCR_W;
     cx<double> *gg = gs + grp * SCR_G;
-    const int Np = 1 << a.logNp, Npm = Np - 1;
     for (int64_t m = (int64_t)blockIdx.x * GROUPS + grp; m < M; m += (int64_t)gridDim.x * GROUPS) {
         const uint2 rec = a.rec[m];
-        const int cu = (int)(rec.x & 0xFFFFu), cv = (int)(rec.x >> 16);
         const int pl = (int)(rec.y & 0xFFFFu), h = (int)((rec.y >> 16) & 0xFu);
         const int S = 2 * h + 7, SS = S * S;
         axis_weights<double>(a, (int)m, pl, h, S, lane, kbg, wk, gg);
@@ -387,8 +386,6 @@ __global__ void __launch_bounds__(256) k_fill_csr(TileArgs<double> a, int64_t M,
             const int ay = t / S, ax = t - ay * S;
             const cx<double> w = gg[18 + ay] * gg[ax];
             val[rp + t] = mk<T>((T)w.x, (T)w.y);
-            const int gy = (cv + ay - h - 3) & Npm, gx = (cu + ax - h - 3) & Npm;
-            col[rp + t] = gy * Np + gx;
         }
         wave_sync();
     }
@@ -511,7 +508,6 @@ void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, int op, bool otf, const 
     if (!otf) {
         a.rowptr = c->csr.rowptr;
         a.gval = (const cx<T> *)c->csr.val;
-        a.gcol = c->csr.col;
     }
     fill_zero_i32(c->d_counter, 1, s);
     ProfScope prof(c, PROF_TILES, s);
@@ -542,13 +538,12 @@ void fill_csr(ri_ctx *c, hipStream_t s) {
     c->csr.rowptr = (int64_t *)dev_alloc(c, sizeof(int64_t) * (c->M + 1));
     RI_CHECK_HIP(hipMemcpy(c->csr.rowptr, rp.data(), sizeof(int64_t) * (c->M + 1), hipMemcpyHostToDevice));
     c->csr.val = dev_alloc(c, sizeof(cx<T>) * (size_t)c->csr.nnz);
-    c->csr.col = (int32_t *)dev_alloc(c, sizeof(int32_t) * (size_t)c->csr.nnz);
     ensure_prec<double>(c, c->p64);
     TileArgs<double> a = make_args<double>(c, v, c->p64);
     if (c->M > 0) {
         int nwg = (int)std::min<int64_t>((c->M + GROUPS - 1) / GROUPS, (int64_t)c->dev.cu_count * 16);
-        hipLaunchKernelGGL(k_fill_csr<T>, dim3(nwg), dim3(256), 0, s, a, c->M, c->csr.rowptr, (cx<T> *)c->csr.val,
-                           c->csr.col);
+        hipLaunchKernelGGL(k_fill_csr<T>, dim3(nwg), dim3(256), 0, s, a, c->M, c->csr.rowptr,
+                           (cx<T> *)c->csr.val);
         RI_CHECK_HIP(hipGetLastError());
     }
 }

@@ -194,7 +194,7 @@ void build_main_view(ri_ctx *c, int tile) {
     const bool f64frac = c->d.g_mode == RI_G_CSR || c->d.precision == 64;
     free_view(c, c->view);
     if (c->csr.val) {
-        dev_free(c, c->csr.rowptr); dev_free(c, c->csr.val); dev_free(c, c->csr.col);
+        dev_free(c, c->csr.rowptr); dev_free(c, c->csr.val);
     holo_free(c);
     sara_free(c);
         c->csr = CSR();
@@ -621,7 +621,7 @@ void ri_destroy(ri_ctx *c) {
     (void)hipDeviceSynchronize();
     free_view(c, c->view);
     free_view(c, c->view64);
-    dev_free(c, c->csr.rowptr); dev_free(c, c->csr.val); dev_free(c, c->csr.col);
+    dev_free(c, c->csr.rowptr); dev_free(c, c->csr.val);
     holo_free(c);
     auto freep = [c](auto &p) {
         dev_free(c, p.icorr); dev_free(c, p.tw); dev_free(c, p.wtaps); dev_free(c, p.gridA); dev_free(c, p.gridB);

@@ -56,11 +56,13 @@ struct View {
     std::vector<int64_t> perm_host;  // kept for tests (caller index of each internal slot)
 };
 
+// Stored G: row m (internal order) holds the S x S values of its window in
+// row-major window order; the columns follow from the row's window (centre
+// cell and support in the view's record), so none are stored.
 struct CSR {
     int64_t nnz = 0;
     int64_t *rowptr = nullptr;    // [M+1], internal order
     void *val = nullptr;          // cx<T>[nnz]
-    int32_t *col = nullptr;       // [nnz] flat grid index gy*N'+gx
     int val_bytes = 0;
 };
 

@@ -11,6 +11,8 @@
 // columns, so every global access is a contiguous CW-element row segment:
 //   pass A: N1-point transforms along rows n2 + N2*n1, times W_{N'}^{n2 k1};
 //   pass B: N2-point transforms along rows N2*k1 + n2, written to row k1 + N1*k2.
+#include <utility>
+
 #include "ri_internal.h"
 
 namespace ri {
@@ -244,6 +246,80 @@ __global__ void k_colpass_b(const cx<T> *__restrict__ in, cx<T> *__restrict__ ou
     }
 }
 
+// ---------------------------------------------------------------------------
+// Column passes of the 4096-point FP32 transform (N1 = N2 = 64) in registers:
+// lane c of a one-wave workgroup holds the 64 points of column c, so every
+// load and store of the wave is one contiguous 512-byte row segment and no
+// LDS or barrier is involved. 64-point radix-2 decimation in frequency
+// (natural order in, bit-reversed out), twiddles from the FP64-computed table.
+// ---------------------------------------------------------------------------
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) { static_for_(f, std::make_integer_sequence<int, N>{}); }
+
+__device__ __forceinline__ void fft64_reg(cx<float> *v, const cx<float> *__restrict__ tw, int tw_mul, bool inv) {
+    static_for<6>([&](auto St) {
+        constexpr int span = 32 >> decltype(St)::value;
+        static_for<64>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            if constexpr ((j & span) == 0) {
+                const cx<float> a = v[j], b = v[j + span];
+                v[j] = a + b;
+                cx<float> d = a - b;
+                constexpr int e = (j & (span - 1)) * (32 / span);
+                if constexpr (e != 0) {
+                    cx<float> w = tw[e * tw_mul];
+                    if (inv) w.y = -w.y;
+                    d = d * w;
+                }
+                v[j + span] = d;
+            }
+        });
+    });
+}
+
+// Pass A in place: rows n2 + 64 n1 -> 64-point transforms over n1, times W_{N'}^{n2 k1}, rows n2 + 64 k1.
+__global__ void __launch_bounds__(64) k_colpass_a_reg(cx<float> *__restrict__ grid, const cx<float> *__restrict__ tw,
+                                                      int N, int logNp, int band_in, int inv) {
+    const int Np = 1 << logNp;
+    const int c = blockIdx.x * 64 + threadIdx.x, n2 = blockIdx.y;
+    cx<float> v[64];
+    static_for<64>([&](auto I) {
+        constexpr int n1 = decltype(I)::value;
+        const int r = n2 + 64 * n1;
+        v[n1] = (!band_in || in_band(r, N, Np)) ? grid[(size_t)r * Np + c] : mk<float>(0.f, 0.f);
+    });
+    fft64_reg(v, tw, Np >> 6, inv != 0);
+    static_for<64>([&](auto K) {
+        constexpr int k1 = decltype(K)::value;
+        cx<float> w = tw[n2 * k1];
+        if (inv) w.y = -w.y;
+        grid[(size_t)(n2 + 64 * k1) * Np + c] = v[brev(k1, 6)] * w;
+    });
+}
+
+// Pass B: rows 64 k1 + n2 -> 64-point transforms over n2 -> rows k1 + 64 k2.
+__global__ void __launch_bounds__(64) k_colpass_b_reg(const cx<float> *__restrict__ in, cx<float> *__restrict__ out,
+                                                      const cx<float> *__restrict__ tw, int N, int logNp, int band_out,
+                                                      int inv) {
+    const int Np = 1 << logNp;
+    const int c = blockIdx.x * 64 + threadIdx.x, k1 = blockIdx.y;
+    cx<float> v[64];
+    static_for<64>([&](auto I) {
+        constexpr int n2 = decltype(I)::value;
+        v[n2] = in[(size_t)(64 * k1 + n2) * Np + c];
+    });
+    fft64_reg(v, tw, Np >> 6, inv != 0);
+    static_for<64>([&](auto K) {
+        constexpr int k2 = decltype(K)::value;
+        const int r = k1 + 64 * k2;
+        if (!band_out || in_band(r, N, Np)) out[(size_t)r * Np + c] = v[brev(k2, 6)];
+    });
+}
+
 int threads_for(int L, int CW) { return L * CW / 16 < 64 ? 64 : L * CW / 16; }
 
 template <typename T>
@@ -251,6 +327,16 @@ void colfft(ri_ctx *c, cx<T> *grid_io, cx<T> *grid_out, const cx<T> *tw, bool in
             hipStream_t s) {
     const int logNp = c->logNp, Np = c->Np;
     const int logN1 = (logNp + 1) / 2, logN2 = logNp / 2;
+    if constexpr (sizeof(T) == 4) {
+        if (logNp == 12) {   // 4096 = 64 x 64: both column passes in registers
+            hipLaunchKernelGGL(k_colpass_a_reg, dim3(Np / 64, 64), dim3(64), 0, s, (cx<float> *)grid_io,
+                               (const cx<float> *)tw, c->N, logNp, band_in ? 1 : 0, inv ? 1 : 0);
+            hipLaunchKernelGGL(k_colpass_b_reg, dim3(Np / 64, 64), dim3(64), 0, s, (const cx<float> *)grid_io,
+                               (cx<float> *)grid_out, (const cx<float> *)tw, c->N, logNp, band_out ? 1 : 0,
+                               inv ? 1 : 0);
+            return;
+        }
+    }
     int logCW = sizeof(T) == 4 ? 6 : 5;
     if ((1 << logCW) > Np) logCW = logNp;
     const int CW = 1 << logCW;

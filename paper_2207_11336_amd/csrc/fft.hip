@@ -247,11 +247,15 @@ __global__ void k_colpass_b(const cx<T> *__restrict__ in, cx<T> *__restrict__ ou
 }
 
 // ---------------------------------------------------------------------------
-// Column passes of the 4096-point FP32 transform (N1 = N2 = 64) in registers:
-// lane c of a one-wave workgroup holds the 64 points of column c, so every
-// load and store of the wave is one contiguous 512-byte row segment and no
-// LDS or barrier is involved. 64-point radix-2 decimation in frequency
-// (natural order in, bit-reversed out), twiddles from the FP64-computed table.
+// Column passes of the 4096-point transform (N1 = N2 = 64) in registers: a
+// one-wave workgroup takes 64/Q adjacent columns, Q lanes per column (Q = 1 in
+// FP32, 2 in FP64 so that a lane holds P = 64/Q points), so every load and
+// store of the wave is a contiguous 512-byte row segment and no LDS or barrier
+// is involved. 64-point radix-2 decimation in frequency: with Q = 2 the first
+// stage pairs lane l with lane l + 32 (point i with point i + 32, exchanged by
+// a lane shuffle), then each lane finishes a P-point transform of its half
+// (natural order in, bit-reversed out): lane half h holds frequencies Q k + h.
+// Twiddles come from the FP64-computed table.
 // ---------------------------------------------------------------------------
 template <typename F, int... I>
 __device__ __forceinline__ void static_for_(F &&f, std::integer_sequence<int, I...>) {
@@ -260,18 +264,19 @@ __device__ __forceinline__ void static_for_(F &&f, std::integer_sequence<int, I.
 template <int N, typename F>
 __device__ __forceinline__ void static_for(F &&f) { static_for_(f, std::make_integer_sequence<int, N>{}); }
 
-__device__ __forceinline__ void fft64_reg(cx<float> *v, const cx<float> *__restrict__ tw, int tw_mul, bool inv) {
-    static_for<6>([&](auto St) {
-        constexpr int span = 32 >> decltype(St)::value;
-        static_for<64>([&](auto J) {
+template <typename T, int P>
+__device__ __forceinline__ void fftp_reg(cx<T> *v, const cx<T> *__restrict__ tw, int tw_mul, bool inv) {
+    static_for<ilog2(P)>([&](auto St) {
+        constexpr int span = (P / 2) >> decltype(St)::value;
+        static_for<P>([&](auto J) {
             constexpr int j = decltype(J)::value;
             if constexpr ((j & span) == 0) {
-                const cx<float> a = v[j], b = v[j + span];
+                const cx<T> a = v[j], b = v[j + span];
                 v[j] = a + b;
-                cx<float> d = a - b;
-                constexpr int e = (j & (span - 1)) * (32 / span);
+                cx<T> d = a - b;
+                constexpr int e = (j & (span - 1)) * ((P / 2) / span);
                 if constexpr (e != 0) {
-                    cx<float> w = tw[e * tw_mul];
+                    cx<T> w = tw[e * tw_mul];
                     if (inv) w.y = -w.y;
                     d = d * w;
                 }
@@ -281,42 +286,68 @@ __device__ __forceinline__ void fft64_reg(cx<float> *v, const cx<float> *__restr
     });
 }
 
+template <typename T, int Q>
+__device__ __forceinline__ void fft64_lanes(cx<T> *v, int h, const cx<T> *__restrict__ tw, int Np, bool inv) {
+    constexpr int P = 64 / Q;
+    if constexpr (Q == 2) {
+        static_for<P>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            cx<T> o;
+            o.x = __shfl_xor(v[i].x, 32);
+            o.y = __shfl_xor(v[i].y, 32);
+            if (h == 0) {
+                v[i] = v[i] + o;
+            } else {
+                cx<T> d = o - v[i];
+                if constexpr (i != 0) {
+                    cx<T> w = tw[i * (Np >> 6)];
+                    if (inv) w.y = -w.y;
+                    d = d * w;
+                }
+                v[i] = d;
+            }
+        });
+    }
+    fftp_reg<T, P>(v, tw, Np / P, inv);
+}
+
 // Pass A in place: rows n2 + 64 n1 -> 64-point transforms over n1, times W_{N'}^{n2 k1}, rows n2 + 64 k1.
-__global__ void __launch_bounds__(64) k_colpass_a_reg(cx<float> *__restrict__ grid, const cx<float> *__restrict__ tw,
-                                                      int N, int logNp, int band_in, int inv) {
+template <typename T, int Q>
+__global__ void __launch_bounds__(64) k_colpass_a_reg(cx<T> *__restrict__ grid, const cx<T> *__restrict__ tw, int N,
+                                                      int logNp, int band_in, int inv) {
+    constexpr int P = 64 / Q, CPB = 64 / Q;
     const int Np = 1 << logNp;
-    const int c = blockIdx.x * 64 + threadIdx.x, n2 = blockIdx.y;
-    cx<float> v[64];
-    static_for<64>([&](auto I) {
-        constexpr int n1 = decltype(I)::value;
-        const int r = n2 + 64 * n1;
-        v[n1] = (!band_in || in_band(r, N, Np)) ? grid[(size_t)r * Np + c] : mk<float>(0.f, 0.f);
+    const int h = threadIdx.x / CPB, c = blockIdx.x * CPB + threadIdx.x % CPB, n2 = blockIdx.y;
+    cx<T> v[P];
+    static_for<P>([&](auto I) {
+        const int r = n2 + 64 * (h * P + decltype(I)::value);
+        v[I] = (!band_in || in_band(r, N, Np)) ? grid[(size_t)r * Np + c] : mk<T>((T)0, (T)0);
     });
-    fft64_reg(v, tw, Np >> 6, inv != 0);
-    static_for<64>([&](auto K) {
-        constexpr int k1 = decltype(K)::value;
-        cx<float> w = tw[n2 * k1];
+    fft64_lanes<T, Q>(v, h, tw, Np, inv != 0);
+    static_for<P>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        const int k1 = Q * k + h;
+        cx<T> w = tw[n2 * k1];
         if (inv) w.y = -w.y;
-        grid[(size_t)(n2 + 64 * k1) * Np + c] = v[brev(k1, 6)] * w;
+        grid[(size_t)(n2 + 64 * k1) * Np + c] = v[brev(k, ilog2(P))] * w;
     });
 }
 
 // Pass B: rows 64 k1 + n2 -> 64-point transforms over n2 -> rows k1 + 64 k2.
-__global__ void __launch_bounds__(64) k_colpass_b_reg(const cx<float> *__restrict__ in, cx<float> *__restrict__ out,
-                                                      const cx<float> *__restrict__ tw, int N, int logNp, int band_out,
+template <typename T, int Q>
+__global__ void __launch_bounds__(64) k_colpass_b_reg(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
+                                                      const cx<T> *__restrict__ tw, int N, int logNp, int band_out,
                                                       int inv) {
+    constexpr int P = 64 / Q, CPB = 64 / Q;
     const int Np = 1 << logNp;
-    const int c = blockIdx.x * 64 + threadIdx.x, k1 = blockIdx.y;
-    cx<float> v[64];
-    static_for<64>([&](auto I) {
-        constexpr int n2 = decltype(I)::value;
-        v[n2] = in[(size_t)(64 * k1 + n2) * Np + c];
-    });
-    fft64_reg(v, tw, Np >> 6, inv != 0);
-    static_for<64>([&](auto K) {
-        constexpr int k2 = decltype(K)::value;
-        const int r = k1 + 64 * k2;
-        if (!band_out || in_band(r, N, Np)) out[(size_t)r * Np + c] = v[brev(k2, 6)];
+    const int h = threadIdx.x / CPB, c = blockIdx.x * CPB + threadIdx.x % CPB, k1 = blockIdx.y;
+    cx<T> v[P];
+    static_for<P>([&](auto I) { v[I] = in[(size_t)(64 * k1 + h * P + decltype(I)::value) * Np + c]; });
+    fft64_lanes<T, Q>(v, h, tw, Np, inv != 0);
+    static_for<P>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        const int r = k1 + 64 * (Q * k + h);
+        if (!band_out || in_band(r, N, Np)) out[(size_t)r * Np + c] = v[brev(k, ilog2(P))];
     });
 }
 
@@ -327,15 +358,13 @@ void colfft(ri_ctx *c, cx<T> *grid_io, cx<T> *grid_out, const cx<T> *tw, bool in
             hipStream_t s) {
     const int logNp = c->logNp, Np = c->Np;
     const int logN1 = (logNp + 1) / 2, logN2 = logNp / 2;
-    if constexpr (sizeof(T) == 4) {
-        if (logNp == 12) {   // 4096 = 64 x 64: both column passes in registers
-            hipLaunchKernelGGL(k_colpass_a_reg, dim3(Np / 64, 64), dim3(64), 0, s, (cx<float> *)grid_io,
-                               (const cx<float> *)tw, c->N, logNp, band_in ? 1 : 0, inv ? 1 : 0);
-            hipLaunchKernelGGL(k_colpass_b_reg, dim3(Np / 64, 64), dim3(64), 0, s, (const cx<float> *)grid_io,
-                               (cx<float> *)grid_out, (const cx<float> *)tw, c->N, logNp, band_out ? 1 : 0,
-                               inv ? 1 : 0);
-            return;
-        }
+    if (logNp == 12) {   // 4096 = 64 x 64: both column passes in registers
+        constexpr int Q = sizeof(T) == 4 ? 1 : 2;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_colpass_a_reg<T, Q>), dim3(Np / (64 / Q), 64), dim3(64), 0, s, grid_io,
+                           tw, c->N, logNp, band_in ? 1 : 0, inv ? 1 : 0);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_colpass_b_reg<T, Q>), dim3(Np / (64 / Q), 64), dim3(64), 0, s,
+                           (const cx<T> *)grid_io, grid_out, tw, c->N, logNp, band_out ? 1 : 0, inv ? 1 : 0);
+        return;
     }
     int logCW = sizeof(T) == 4 ? 6 : 5;
     if ((1 << logCW) > Np) logCW = logNp;

@@ -118,6 +118,16 @@ def test_fp64_forward_sampled(full):
     e = rel(y[torch.as_tensor(idx, device=DEV)].cpu().numpy(), ref)
     print(f"FP64 Phi x on {idx.size} sampled visibilities rel {e:.2e}")
     assert e <= 1e-11
+    # the adjoint of data on the sampled visibilities only (the inverse FFT path)
+    rng = np.random.default_rng(77)
+    ys = rng.standard_normal(idx.size) + 1j * rng.standard_normal(idx.size)
+    yfull = torch.zeros(WL.M, dtype=torch.complex128, device=DEV)
+    yfull[torch.as_tensor(idx, device=DEV)] = torch.tensor(ys, device=DEV)
+    g = torch.empty_like(xt)
+    R.phi_adjoint(ctx, yfull, g)
+    e_a = rel(g.cpu().numpy(), _oracle_sub(uvw, idx).phi_adj(ys))
+    print(f"FP64 Re Phi^dagger y for data on the sampled visibilities rel {e_a:.2e}")
+    assert e_a <= 1e-11
 
 
 def test_cnn_whole_image_sampled_pixels():

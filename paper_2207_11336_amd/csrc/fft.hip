@@ -247,15 +247,13 @@ __global__ void k_colpass_b(const cx<T> *__restrict__ in, cx<T> *__restrict__ ou
 }
 
 // ---------------------------------------------------------------------------
-// Column passes of the 4096-point transform (N1 = N2 = 64) in registers: a
-// one-wave workgroup takes 64/Q adjacent columns, Q lanes per column (Q = 1 in
-// FP32, 2 in FP64 so that a lane holds P = 64/Q points), so every load and
-// store of the wave is a contiguous 512-byte row segment and no LDS or barrier
-// is involved. 64-point radix-2 decimation in frequency: with Q = 2 the first
-// stage pairs lane l with lane l + 32 (point i with point i + 32, exchanged by
-// a lane shuffle), then each lane finishes a P-point transform of its half
-// (natural order in, bit-reversed out): lane half h holds frequencies Q k + h.
-// Twiddles come from the FP64-computed table.
+// Column passes of the 4096- and 8192-point transforms (N1 = 64 or 128,
+// N2 = 64) in registers: a one-wave workgroup takes 64/Q adjacent columns, Q
+// lanes per column so that a lane holds at most 512 bytes of points (64 FP32
+// or 32 FP64 complex values), so every load and store of the wave is a
+// contiguous 512-byte row segment and no LDS or barrier is involved. Radix-2
+// decimation in frequency, natural order in, bit-reversed out; twiddles come
+// from the FP64-computed table.
 // ---------------------------------------------------------------------------
 template <typename F, int... I>
 __device__ __forceinline__ void static_for_(F &&f, std::integer_sequence<int, I...>) {
@@ -286,70 +284,84 @@ __device__ __forceinline__ void fftp_reg(cx<T> *v, const cx<T> *__restrict__ tw,
     });
 }
 
-template <typename T, int Q>
-__device__ __forceinline__ void fft64_lanes(cx<T> *v, int h, const cx<T> *__restrict__ tw, int Np, bool inv) {
-    constexpr int P = 64 / Q;
-    if constexpr (Q == 2) {
+// L-point transform of a column held by Q lanes (lane half h = 0 .. Q-1 holds
+// points h P .. h P + P - 1, P = L / Q, the lanes of one column CPB = 64 / Q
+// apart): the first log2 Q decimation-in-frequency stages pair lanes h and
+// h ^ (s / P) by shuffles (span s = L/2 .. P), the rest run in registers.
+// Afterwards point i of lane h holds frequency brev_P(i) Q + brev_Q(h).
+template <typename T, int L, int Q>
+__device__ __forceinline__ void fft_lanes(cx<T> *v, int h, const cx<T> *__restrict__ tw, int Np, bool inv) {
+    constexpr int P = L / Q, CPB = 64 / Q;
+    static_for<ilog2(Q)>([&](auto St) {
+        constexpr int s = (L / 2) >> decltype(St)::value;   // span in points, >= P
+        constexpr int hs = s / P;                            // partner distance in lane halves
+        const bool upper = (h & hs) != 0;
         static_for<P>([&](auto I) {
             constexpr int i = decltype(I)::value;
             cx<T> o;
-            o.x = __shfl_xor(v[i].x, 32);
-            o.y = __shfl_xor(v[i].y, 32);
-            if (h == 0) {
+            o.x = __shfl_xor(v[i].x, hs * CPB);
+            o.y = __shfl_xor(v[i].y, hs * CPB);
+            if (!upper) {
                 v[i] = v[i] + o;
             } else {
                 cx<T> d = o - v[i];
-                if constexpr (i != 0) {
-                    cx<T> w = tw[i * (Np >> 6)];
+                const int e = ((h * P + i) & (s - 1)) * ((L / 2) / s);   // W_{2s}^{j mod s} = W_L^{...}
+                if (e != 0) {
+                    cx<T> w = tw[e * (Np / L)];
                     if (inv) w.y = -w.y;
                     d = d * w;
                 }
                 v[i] = d;
             }
         });
-    }
+    });
     fftp_reg<T, P>(v, tw, Np / P, inv);
 }
 
-// Pass A in place: rows n2 + 64 n1 -> 64-point transforms over n1, times W_{N'}^{n2 k1}, rows n2 + 64 k1.
-template <typename T, int Q>
+// Pass A in place: rows n2 + N2 n1 -> L = N1-point transforms over n1, times W_{N'}^{n2 k1}, rows n2 + N2 k1.
+template <typename T, int L, int Q>
 __global__ void __launch_bounds__(64) k_colpass_a_reg(cx<T> *__restrict__ grid, const cx<T> *__restrict__ tw, int N,
                                                       int logNp, int band_in, int inv) {
-    constexpr int P = 64 / Q, CPB = 64 / Q;
-    const int Np = 1 << logNp;
+    constexpr int P = L / Q, CPB = 64 / Q;
+    const int Np = 1 << logNp, N2 = Np / L;
     const int h = threadIdx.x / CPB, c = blockIdx.x * CPB + threadIdx.x % CPB, n2 = blockIdx.y;
     cx<T> v[P];
     static_for<P>([&](auto I) {
-        const int r = n2 + 64 * (h * P + decltype(I)::value);
+        const int r = n2 + N2 * (h * P + decltype(I)::value);
         v[I] = (!band_in || in_band(r, N, Np)) ? grid[(size_t)r * Np + c] : mk<T>((T)0, (T)0);
     });
-    fft64_lanes<T, Q>(v, h, tw, Np, inv != 0);
-    static_for<P>([&](auto K) {
-        constexpr int k = decltype(K)::value;
-        const int k1 = Q * k + h;
+    fft_lanes<T, L, Q>(v, h, tw, Np, inv != 0);
+    const int hb = brev(h, ilog2(Q));
+    static_for<P>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const int k1 = brev(i, ilog2(P)) * Q + hb;
         cx<T> w = tw[n2 * k1];
         if (inv) w.y = -w.y;
-        grid[(size_t)(n2 + 64 * k1) * Np + c] = v[brev(k, ilog2(P))] * w;
+        grid[(size_t)(n2 + N2 * k1) * Np + c] = v[i] * w;
     });
 }
 
-// Pass B: rows 64 k1 + n2 -> 64-point transforms over n2 -> rows k1 + 64 k2.
-template <typename T, int Q>
+// Pass B: rows L k1 + n2 (L = N2) -> L-point transforms over n2 -> rows k1 + N1 k2.
+template <typename T, int L, int Q>
 __global__ void __launch_bounds__(64) k_colpass_b_reg(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
                                                       const cx<T> *__restrict__ tw, int N, int logNp, int band_out,
                                                       int inv) {
-    constexpr int P = 64 / Q, CPB = 64 / Q;
-    const int Np = 1 << logNp;
+    constexpr int P = L / Q, CPB = 64 / Q;
+    const int Np = 1 << logNp, N1 = Np / L;
     const int h = threadIdx.x / CPB, c = blockIdx.x * CPB + threadIdx.x % CPB, k1 = blockIdx.y;
     cx<T> v[P];
-    static_for<P>([&](auto I) { v[I] = in[(size_t)(64 * k1 + h * P + decltype(I)::value) * Np + c]; });
-    fft64_lanes<T, Q>(v, h, tw, Np, inv != 0);
-    static_for<P>([&](auto K) {
-        constexpr int k = decltype(K)::value;
-        const int r = k1 + 64 * (Q * k + h);
-        if (!band_out || in_band(r, N, Np)) out[(size_t)r * Np + c] = v[brev(k, ilog2(P))];
+    static_for<P>([&](auto I) { v[I] = in[(size_t)(L * k1 + h * P + decltype(I)::value) * Np + c]; });
+    fft_lanes<T, L, Q>(v, h, tw, Np, inv != 0);
+    const int hb = brev(h, ilog2(Q));
+    static_for<P>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const int r = k1 + N1 * (brev(i, ilog2(P)) * Q + hb);
+        if (!band_out || in_band(r, N, Np)) out[(size_t)r * Np + c] = v[i];
     });
 }
+
+template <typename T, int L>
+constexpr int lanes_per_column() { return (L * (int)sizeof(cx<T>)) / 512 < 1 ? 1 : (L * (int)sizeof(cx<T>)) / 512; }
 
 int threads_for(int L, int CW) { return L * CW / 16 < 64 ? 64 : L * CW / 16; }
 
@@ -358,11 +370,18 @@ void colfft(ri_ctx *c, cx<T> *grid_io, cx<T> *grid_out, const cx<T> *tw, bool in
             hipStream_t s) {
     const int logNp = c->logNp, Np = c->Np;
     const int logN1 = (logNp + 1) / 2, logN2 = logNp / 2;
-    if (logNp == 12) {   // 4096 = 64 x 64: both column passes in registers
-        constexpr int Q = sizeof(T) == 4 ? 1 : 2;
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_colpass_a_reg<T, Q>), dim3(Np / (64 / Q), 64), dim3(64), 0, s, grid_io,
-                           tw, c->N, logNp, band_in ? 1 : 0, inv ? 1 : 0);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_colpass_b_reg<T, Q>), dim3(Np / (64 / Q), 64), dim3(64), 0, s,
+    if (logNp == 12 || logNp == 13) {
+        // 4096 = 64 x 64 and 8192 = 128 x 64: both column passes in registers,
+        // at most 64 complex FP32 (32 FP64) points per lane
+        constexpr int QA4 = lanes_per_column<T, 64>(), QA8 = lanes_per_column<T, 128>();
+        constexpr int QB = lanes_per_column<T, 64>();
+        if (logNp == 12)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_colpass_a_reg<T, 64, QA4>), dim3(Np / (64 / QA4), 64), dim3(64), 0,
+                               s, grid_io, tw, c->N, logNp, band_in ? 1 : 0, inv ? 1 : 0);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_colpass_a_reg<T, 128, QA8>), dim3(Np / (64 / QA8), 64), dim3(64), 0,
+                               s, grid_io, tw, c->N, logNp, band_in ? 1 : 0, inv ? 1 : 0);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_colpass_b_reg<T, 64, QB>), dim3(Np / (64 / QB), Np / 64), dim3(64), 0, s,
                            (const cx<T> *)grid_io, grid_out, tw, c->N, logNp, band_out ? 1 : 0, inv ? 1 : 0);
         return;
     }

@@ -7,10 +7,13 @@
 // radix-16 passes (natural order in and out, twiddles from an FP64-computed
 // table). Only the N non-zero rows are transformed on the way in, and only
 // the N needed rows on the way out.
-// Columns: four-step decomposition N' = N1 * N2 over stripes of CW adjacent
-// columns, so every global access is a contiguous CW-element row segment:
+// Columns: four-step decomposition N' = N1 * N2 over stripes of adjacent
+// columns, so every global access is a contiguous row segment:
 //   pass A: N1-point transforms along rows n2 + N2*n1, times W_{N'}^{n2 k1};
 //   pass B: N2-point transforms along rows N2*k1 + n2, written to row k1 + N1*k2.
+// For N' = 4096 and 8192 each column's points stay in registers (a few lanes
+// per column, see k_colpass_a_reg); for the other sizes a stripe of CW
+// columns is transformed in LDS by Stockham passes.
 #include <utility>
 
 #include "ri_internal.h"

@@ -243,3 +243,39 @@ def test_solve_through_h_needs_h(case):
     with pytest.raises(R.RIError):
         R.pnp_solve(ctx, torch.zeros(uvw.shape[0], dtype=torch.complex64, device=DEV), opts,
                     torch.empty(N, N, device=DEV))
+
+
+def test_pnp_solve_through_h_with_the_cnn(case):
+    """PnP-FB (random He-normal CNN, facets; FP64 context) through H and over the
+    visibilities: the same rescaling alpha and, over four graph-replayed
+    iterations, the same iterates. FP64 keeps the two paths' differences far below
+    the BF16 rounding steps inside the network, so the iterates agree closely."""
+    from oracle import cnn as OC
+    from oracle import fb as OF
+    W, uvw, op, _ = case
+    x_true = synth.sky(N, seed=8, n_compact=8, n_ext=1)
+    y0 = op.phi(x_true)
+    tau = OF.tau_from_isnr(y0, 30.0)
+    y = y0 + OF.complex_noise(tau, synth.noise_normals(uvw.shape[0], synth.SEED_NOISE))
+    d = R.plan_desc(N, uvw.shape[0], cell_rad=CELL, w_max=W, n_wplanes=NPL, precision=64, g_mode=R.RI_G_OTF,
+                    facet_core=32, facet_halo=10)
+    ctx = R.ri_create(d, uvw)
+    params = OC.init_params(10, 64, seed=5)
+    vec = np.concatenate([np.concatenate([w_.ravel(), b_.ravel()]) for w_, b_ in params]).astype(np.float32)
+    R.ri_load_denoiser(ctx, torch.tensor(vec, device=DEV), 10)
+    R.ri_holo_build(ctx)
+    L, _ = R.ri_power_norm(ctx, max_it=300, rtol=1e-10)
+    yt = torch.tensor(y, dtype=torch.complex128, device=DEV)
+    out, reps = {}, {}
+    for use_holo in (0, 1):
+        opts = R.ri_solve_opts(max_iter=4, rel_tol=0.0, prox_kind=R.RI_PROX_CNN, tau=tau, sigma_train=1e-2, L=L,
+                               check_every=4, use_graph=1, use_holo=use_holo)
+        xs = torch.empty(N, N, dtype=torch.float64, device=DEV)
+        reps[use_holo] = R.pnp_solve(ctx, yt, opts, xs)
+        out[use_holo] = xs.cpu().numpy()
+    e = rel(out[1], out[0])
+    print(f"PnP x4 through H vs over the visibilities: {e:.2e}; alpha {reps[1].alpha:.6e} vs {reps[0].alpha:.6e}")
+    assert reps[0].fell_back == 0 and reps[1].fell_back == 0
+    assert reps[0].iters == 4 and reps[1].iters == 4
+    assert reps[1].alpha == pytest.approx(reps[0].alpha, rel=1e-12)
+    assert e <= 1e-6

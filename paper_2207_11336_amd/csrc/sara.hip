@@ -78,7 +78,9 @@ __device__ __forceinline__ void finalise(T *dst9, const T *w9, size_t i9, T val,
 // Column passes are register-blocked: a thread computes KB consecutive outputs
 // of one column from one window of inputs held in registers (2 KB + L - 2
 // inputs for analysis, KB + L/2 - 1 of each half for synthesis). Row passes
-// stage the row in LDS by coalesced loads, one output per lane per step. The
+// stage the row in LDS by coalesced loads; the analysis computes one output
+// per lane per step, the synthesis 8 consecutive outputs per lane from
+// 16-byte LDS windows (k_syn_rows, k_syn_final). The
 // filter length L is a template parameter (one instantiation per basis, chosen
 // from blockIdx.z).
 constexpr int KB = 8;
@@ -221,6 +223,7 @@ __global__ void __launch_bounds__(256) k_syn_cols(const T *__restrict__ v9, cons
 
 // Row synthesis of one staged row (low half A = s[0, half), high half D =
 // s[half, n)) at output j: sum_{t = j mod 2} h[t] A[k] + g[t] D[k], k = (j - t)/2 mod half.
+// Used for the coarse levels with n < 8 only.
 template <typename T, int L>
 __device__ __forceinline__ T syn_row_at(int b, const T *row_s, int j, int half) {
     const int hm = half - 1, j2 = j >> 1, par = j & 1;
@@ -233,75 +236,167 @@ __device__ __forceinline__ T syn_row_at(int b, const T *row_s, int j, int half) 
     return x;
 }
 
-// Row synthesis of level block n (not the last): tmp -> work. Workgroup: one
-// row of one basis staged in LDS.
+// Row synthesis of level block n < 8: tmp -> work. Workgroup: one row of one
+// basis staged in LDS, one output per lane.
 template <typename T>
-__global__ void __launch_bounds__(256) k_syn_rows(const T *__restrict__ tmp, T *__restrict__ work, int N, int n) {
-    extern __shared__ unsigned char smem_raw[];
-    T *row_s = reinterpret_cast<T *>(smem_raw);
+__global__ void __launch_bounds__(64) k_syn_rows_small(const T *__restrict__ tmp, T *__restrict__ work, int N,
+                                                       int n) {
+    __shared__ T row_s[8];
     const int b = blockIdx.z, row = blockIdx.y, half = n >> 1;
     const size_t NN = (size_t)N * N;
     const T *src = tmp + b * NN + (size_t)row * N;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) row_s[e] = src[e];
+    if (threadIdx.x < n) row_s[threadIdx.x] = src[threadIdx.x];
     __syncthreads();
     T *dst = work + b * NN + (size_t)row * N;
     with_length(b, [&](auto Lc) {
-        for (int j = threadIdx.x; j < n; j += blockDim.x) dst[j] = syn_row_at<T, decltype(Lc)::value>(b, row_s, j, half);
+        if (threadIdx.x < n) dst[threadIdx.x] = syn_row_at<T, decltype(Lc)::value>(b, row_s, threadIdx.x, half);
     });
+}
+
+// Register-blocked row synthesis (n >= 8). A row of one basis is staged in LDS
+// with a periodic halo of RH elements in front of each half:
+//   s[k] = A[(k - RH) mod half]  and  s[RH + half + k] = D[(k - RH) mod half],
+// k < RH + half. A lane computes the 8 consecutive outputs x[2u + par],
+// u = u0 .. u0 + 3 (u0 = 4 i for its block i), from the 12-element windows
+// s[u0 .. u0 + 12) of both halves, read as 16-byte vectors: A[u - s2] is
+// window element u - u0 + RH - s2 for s2 < L/2 <= 8.
+constexpr int RH = 8;
+constexpr int RWIN = 12;
+
+template <typename T>
+using vec16 = T __attribute__((ext_vector_type(16 / sizeof(T))));
+template <typename T>
+using vec8o = T __attribute__((ext_vector_type(8)));   // the 8 outputs of a lane block
+
+// Element e < n + 2 RH of the staged row: its source index in the row (low half, then high half).
+__device__ __forceinline__ int staged_src(int e, int half) {
+    const int hs = e >= RH + half ? 1 : 0;
+    const int k = e - hs * (RH + half);
+    return hs * half + ((k - RH) & (half - 1));
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_window(const T *p, T (&w)[RWIN]) {
+    constexpr int E = 16 / sizeof(T);
+#pragma unroll
+    for (int i = 0; i < RWIN / E; ++i) {
+        const vec16<T> v = reinterpret_cast<const vec16<T> *>(p)[i];
+#pragma unroll
+        for (int e = 0; e < E; ++e) w[i * E + e] = v[e];
+    }
+}
+
+// acc[2u + par] += sum_{s2 < L/2} h[par + 2 s2] A[u0 + u - s2] + g[par + 2 s2] D[u0 + u - s2].
+template <typename T, int L>
+__device__ __forceinline__ void syn_row_block(int b, const T *s, int half, int u0, T (&acc)[8]) {
+    T wa[RWIN], wd[RWIN];
+    lds_window<T>(s + u0, wa);
+    lds_window<T>(s + RH + half + u0, wd);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            T v = acc[2 * u + par];
+#pragma unroll
+            for (int s2 = 0; s2 < L / 2; ++s2) {
+                v = fma(fh<T>(b, par + 2 * s2), wa[u + RH - s2], v);
+                v = fma(fg<T>(b, par + 2 * s2), wd[u + RH - s2], v);
+            }
+            acc[2 * u + par] = v;
+        }
+    }
+}
+
+// 8 outputs to library-owned memory (the level buffers, 8-element aligned blocks).
+template <typename T>
+__device__ __forceinline__ void store8(T *p, const T (&v)[8]) {
+    vec8o<T> o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o[e] = v[e];
+    *reinterpret_cast<vec8o<T> *>(p) = o;
+}
+
+// Row synthesis of level block n (8 <= n < N): tmp -> work. Workgroup: one
+// row of one basis, n / 8 lanes (at least 64).
+template <typename T>
+__global__ void __launch_bounds__(256) k_syn_rows(const T *__restrict__ tmp, T *__restrict__ work, int N, int n) {
+    extern __shared__ unsigned char smem_raw[];
+    T *s = reinterpret_cast<T *>(smem_raw);
+    const int b = blockIdx.z, row = blockIdx.y, half = n >> 1, tid = threadIdx.x;
+    const size_t NN = (size_t)N * N;
+    const T *src = tmp + b * NN + (size_t)row * N;
+    for (int e = tid; e < n + 2 * RH; e += blockDim.x) s[e] = src[staged_src(e, half)];
+    __syncthreads();
+    if (8 * tid >= n) return;
+    T acc[8] = {};
+    with_length(b, [&](auto Lc) { syn_row_block<T, decltype(Lc)::value>(b, s, half, 4 * tid, acc); });
+    store8<T>(work + b * NN + (size_t)row * N + 8 * tid, acc);
 }
 
 // Last row synthesis (n = N), summed over the 8 bases plus the Dirac slot:
 // SYN_PLAIN: x = scale * s; SYN_PROX: x = max(0, z - scale * s) and the
 // Dirac dual update v0 = clip(v0 + scale * x, -t w0, t w0). Workgroup: one
-// row; the 8 bases' rows pass through LDS one after another, each lane
-// accumulating its pixels j = tid + 256 q in registers.
-constexpr int FINAL_MAXQ = 16;   // N <= 4096 with 256 lanes
-template <typename T, int MODE>
+// row, 256 lanes, each with NB blocks of 8 outputs (8 (tid + 256 ib)); the 8
+// bases' staged rows pass through LDS one after another, the next one loaded
+// into registers while the current one is used.
+template <typename T, int MODE, int NB>
 __global__ void __launch_bounds__(256) k_syn_final(const T *__restrict__ tmp, T *v9, const T *__restrict__ w9,
                                                    const T *__restrict__ z, T *__restrict__ x, int N, T scale,
                                                    T thr) {
     extern __shared__ unsigned char smem_raw[];
-    T *row_s = reinterpret_cast<T *>(smem_raw);
-    const int row = blockIdx.y, half = N >> 1, tid = threadIdx.x;
-    const int nq = (N + 255) >> 8;
+    T *s = reinterpret_cast<T *>(smem_raw);
+    constexpr int PQ = 8 * NB + 1;           // staged elements per lane: ceil((256 * 8 NB + 2 RH) / 256)
+    const int row = blockIdx.y, half = N >> 1, tid = threadIdx.x, ns = N + 2 * RH;
     const size_t NN = (size_t)N * N;
-    T acc[FINAL_MAXQ], pre[FINAL_MAXQ];
+    T acc[NB][8], pre[PQ];
+    int src[PQ];                             // the staging sources, the same for every basis
 #pragma unroll
-    for (int q = 0; q < FINAL_MAXQ; ++q) {
-        acc[q] = 0;
-        pre[q] = (q < nq && tid + 256 * q < N) ? tmp[(size_t)row * N + tid + 256 * q] : (T)0;
+    for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[ib][e] = 0;
+    const T *r0 = tmp + (size_t)row * N;
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+        const int e = tid + 256 * q;
+        src[q] = e < ns ? staged_src(e, half) : 0;
+        pre[q] = e < ns ? r0[src[q]] : (T)0;
     }
-    // the next basis's row is loaded into registers while the current one is used
     static_for<NW>([&](auto bc) {
         constexpr int b = decltype(bc)::value;
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < FINAL_MAXQ; ++q)
-            if (q < nq && tid + 256 * q < N) row_s[tid + 256 * q] = pre[q];
+        for (int q = 0; q < PQ; ++q)
+            if (tid + 256 * q < ns) s[tid + 256 * q] = pre[q];
         __syncthreads();
         if (b + 1 < NW) {
             const T *nxt = tmp + (b + 1) * NN + (size_t)row * N;
 #pragma unroll
-            for (int q = 0; q < FINAL_MAXQ; ++q)
-                if (q < nq && tid + 256 * q < N) pre[q] = nxt[tid + 256 * q];
+            for (int q = 0; q < PQ; ++q) {
+                const int e = tid + 256 * q;
+                if (e < ns) pre[q] = nxt[src[q]];
+            }
         }
 #pragma unroll
-        for (int q = 0; q < FINAL_MAXQ; ++q)
-            if (q < nq && tid + 256 * q < N) acc[q] += syn_row_at<T, 2 * (b + 1)>(b, row_s, tid + 256 * q, half);
+        for (int ib = 0; ib < NB; ++ib)
+            if (8 * (tid + 256 * ib) < N) syn_row_block<T, 2 * (b + 1)>(b, s, half, 4 * (tid + 256 * ib), acc[ib]);
     });
 #pragma unroll
-    for (int q = 0; q < FINAL_MAXQ; ++q) {
-        const int j = tid + 256 * q;
-        if (q >= nq || j >= N) break;
-        const size_t p = (size_t)row * N + j;
-        const T tot = v9[p] + acc[q];
-        if (MODE == SYN_PLAIN) {
-            x[p] = scale * tot;
-        } else {
-            const T xo = fmax((T)0, z[p] - scale * tot);
-            x[p] = xo;
-            const T lim = thr * w9[p];
-            v9[p] = fmin(fmax(v9[p] + scale * xo, -lim), lim);
+    for (int ib = 0; ib < NB; ++ib) {
+        const int j0 = 8 * (tid + 256 * ib);
+        if (j0 >= N) break;
+        // element accesses: v9, z and x may be caller buffers of any element alignment
+        const size_t p = (size_t)row * N + j0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const T tot = v9[p + e] + acc[ib][e];
+            if (MODE == SYN_PLAIN) {
+                x[p + e] = scale * tot;
+            } else {
+                const T xo = fmax((T)0, z[p + e] - scale * tot);
+                x[p + e] = xo;
+                const T lim = thr * w9[p + e];
+                v9[p + e] = fmin(fmax(v9[p + e] + scale * xo, -lim), lim);
+            }
         }
     }
 }
@@ -437,11 +532,19 @@ void synthesis(ri_ctx *c, T *v9, const T *z, T *x, T thr, hipStream_t s) {
         const int n = N >> l;
         hipLaunchKernelGGL(k_syn_cols<T>, dim3(cdiv(n, 64), cdiv(n, 4 * 2 * KB), NW), dim3(256), 0, s, v9, work, tmp,
                            N, n, l == LEVELS - 1 ? 1 : 0);
-        if (l > 0)
-            hipLaunchKernelGGL(k_syn_rows<T>, dim3(1, n, NW), dim3(256), sizeof(T) * n, s, tmp, work, N, n);
+        if (l > 0 && n >= 8)
+            hipLaunchKernelGGL(k_syn_rows<T>, dim3(1, n, NW), dim3(std::max(64, n / 8)), sizeof(T) * (n + 2 * RH), s,
+                               tmp, work, N, n);
+        else if (l > 0)
+            hipLaunchKernelGGL(k_syn_rows_small<T>, dim3(1, n, NW), dim3(64), 0, s, tmp, work, N, n);
     }
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_syn_final<T, MODE>), dim3(1, N), dim3(256), sizeof(T) * N, s, tmp, v9,
-                       (const T *)st.w, z, x, N, scale, thr);
+    const size_t lds = sizeof(T) * (N + 2 * RH);
+    if (N <= 2048)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_syn_final<T, MODE, 1>), dim3(1, N), dim3(256), lds, s, tmp, v9,
+                           (const T *)st.w, z, x, N, scale, thr);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_syn_final<T, MODE, 2>), dim3(1, N), dim3(256), lds, s, tmp, v9,
+                           (const T *)st.w, z, x, N, scale, thr);
 }
 
 }  // namespace

@@ -146,8 +146,15 @@ __device__ __forceinline__ void axis_weights(const TileArgs<T> &a, int m, int pl
     wave_sync();
 }
 
+// Minimum waves per SIMD the register allocation must allow: the FP32
+// on-the-fly variants fit 64 VGPRs without spilling, which lets 8 waves (two
+// workgroups more per CU) hide the LDS latency; the others are left free (1).
+template <typename T, bool OTF>
+constexpr int tiles_min_waves() { return std::is_same<T, float>::value && OTF ? 8 : 1; }
+
 template <typename T, int OP, bool OTF>
-__global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiles_min_waves<T, OTF>())))
+k_tiles(TileArgs<T> a) {
     // All LDS is dynamic and starts at byte 0: a static __shared__ variable
     // would shift the dynamic block by its size and misalign the 8-byte
     // atomics on the subgrid. Layout: Xs (input subgrid, T), Yr and Yi (output
@@ -161,10 +168,8 @@ __global__ void __launch_bounds__(256) k_tiles(TileArgs<T> a) {
     cx<T> *Xs = reinterpret_cast<cx<T> *>(smem_raw);
     double *Yr = reinterpret_cast<double *>(Xs + ((OP & OP_DEGRID) ? WW : 0));
     double *Yi = Yr + ((OP & OP_GRID) ? WW : 0);
-    T *kbs = reinterpret_cast<T *>(Yi + ((OP & OP_GRID) ? WW : 0));
-    cx<T> *wks = reinterpret_cast<cx<T> *>(kbs + GROUPS * SCR_KB);
-    cx<T> *gs = wks + GROUPS * SCR_W;
-    double *s_red = reinterpret_cast<double *>(gs + GROUPS * SCR_G);
+    cx<T> *wks = reinterpret_cast<cx<T> *>(Yi + ((OP & OP_GRID) ? WW : 0));
+    double *s_red = reinterpret_cast<double *>(wks + GROUPS * SCR_W);
     int &s_item = *reinterpret_cast<int *>(s_red + 4);
     const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
     cx<T> *wk = wks + grp * SCR_W;
@@ -471,11 +476,18 @@ TileArgs<T> make_args(ri_ctx *c, const View &v, Prec<T> &p) {
     return a;
 }
 
+// Dynamic LDS of one k_tiles workgroup on a W x W subgrid (the layout at the
+// kernel's top): X (cx<T>) when degridding, the FP64 real and imaginary planes
+// when gridding, the groups' w-taps, the reduction slots and the item index.
+size_t tiles_lds(size_t W, bool degrid, bool grid, size_t cx_bytes) {
+    const size_t WW = W * W;
+    return cx_bytes * WW * (degrid ? 1 : 0) + 2 * sizeof(double) * WW * (grid ? 1 : 0) +
+           cx_bytes * GROUPS * SCR_W + 4 * sizeof(double) + 16;
+}
+
 template <typename T, int OP, bool OTF>
 void launch_op(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
-    const size_t WW = (size_t)a.W * a.W;
-    size_t lds = sizeof(cx<T>) * WW * ((OP & OP_DEGRID) ? 1 : 0) + 2 * sizeof(double) * WW * ((OP & OP_GRID) ? 1 : 0);
-    lds += sizeof(T) * GROUPS * SCR_KB + sizeof(cx<T>) * GROUPS * (SCR_W + SCR_G) + 4 * sizeof(double) + 16;
+    const size_t lds = tiles_lds((size_t)a.W, (OP & OP_DEGRID) != 0, (OP & OP_GRID) != 0, sizeof(cx<T>));
     if (lds + 64 > (size_t)c->dev.lds_per_block)
         throw Error(RI_EUNSUPPORTED, "tile " + std::to_string(a.tile) + " needs " + std::to_string(lds) +
                                          " B of LDS per workgroup; device allows " +
@@ -490,6 +502,8 @@ void launch_op(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
 }  // namespace
 
 int tiles_partials(ri_ctx *c) { return c->dev.cu_count * 8; }
+
+size_t lds_for_tile(int tile, int H, int cx_bytes) { return tiles_lds((size_t)tile + 2 * H, true, true, cx_bytes); }
 
 template <typename T>
 void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, int op, bool otf, const cx<T> *y_sorted,

@@ -38,11 +38,6 @@ void require(bool ok, const std::string &msg) {
     if (!ok) throw Error(RI_EINVAL, msg);
 }
 
-size_t lds_for_tile(int tile, int H, int elem_bytes) {
-    const size_t W = (size_t)tile + 2 * H;
-    return W * W * elem_bytes + W * W * 16 + 16 * 16 * (elem_bytes / 2) + 16 * (12 + 36) * elem_bytes + 4 * 8 + 16;
-}
-
 int pick_tile(ri_ctx *c, int requested, int elem_bytes) {
     int t = requested > 0 ? requested : 16;
     if (t > c->Np) t = c->Np;

@@ -240,6 +240,9 @@ template <typename T> void holo_normal(ri_ctx *c, Prec<T> &p, const T *x, T *out
 // out[0] = dots[0] - 2 dots[1] + yy[0] (the residual norm from the normal operator).
 void holo_residual(double *out, const double *dots, const double *yy, hipStream_t s);
 int tiles_partials(ri_ctx *c);
+// Dynamic LDS bytes of a fused tile-kernel workgroup at tile side `tile` (subgrid tile + 2 H),
+// cx_bytes = 8 (FP32) or 16 (FP64).
+size_t lds_for_tile(int tile, int H, int cx_bytes);
 
 // image.hip
 template <typename T> void fill_zero(cx<T> *p, int64_t n, hipStream_t s);

@@ -221,7 +221,9 @@ typedef struct {
 
 /* y: dev [M] complex (caller's order) or NULL for the stored data.
  * x_out: dev [N][N] (context precision), the solution multiplied back by alpha.
- * Synchronous. */
+ * Synchronous: waits for all work already issued on the device (y and x_true
+ * may come from asynchronous calls on any stream), runs on a stream of its own
+ * and returns when x_out is written. */
 ri_status pnp_solve(ri_ctx *ctx, const void *y, const ri_solve_opts *opts, void *x_out,
                     ri_solve_report *report);
 

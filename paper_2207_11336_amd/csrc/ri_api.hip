@@ -321,6 +321,10 @@ double dirty_beam_peak(ri_ctx *c, hipStream_t s) {
 // replay, and read on the host every check_every iterations.
 template <typename T>
 bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_report *rep) {
+    // The caller's y, x_true and denoiser may still be in flight on any
+    // stream (the solve takes none): wait for all work issued so far, since
+    // the solve's own stream does not order itself after the others.
+    RI_CHECK_HIP(hipDeviceSynchronize());
     hipStream_t s = nullptr;
     RI_CHECK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     const int64_t n = (int64_t)c->N * c->N;

@@ -86,3 +86,30 @@ def test_graph_replay_matches_eager_iterations(prec):
     assert rel(xg, xe) <= tol
     assert rg.snr_db == pytest.approx(OF.snr_db(c.x, xg), abs=1e-3)
     print(f"prec {prec}: graph {rg.ms:.2f} ms vs eager {re_.ms:.2f} ms for {K} its; SNR {rg.snr_db:.3f} dB")
+
+
+def test_solve_waits_for_data_still_in_flight():
+    """pnp_solve takes no stream: data written by work still queued on the caller's
+    stream when it is called (here behind a spin kernel of fixed length) must be
+    the data it solves with. Reference: the same solve after a device sync."""
+    c = wide()
+    d = R.plan_desc(c.N, c.M, cell_rad=c.cell, w_max=c.W, n_wplanes=c.n_wplanes, precision=32,
+                    g_mode=R.RI_G_OTF)
+    ctx = R.ri_create(d, c.uvw)
+    L, _ = R.ri_power_norm(ctx, max_it=200, rtol=1e-9)
+    y = _vis(c.y, 32)
+    opts = R.ri_solve_opts(max_iter=6, rel_tol=0.0, prox_kind=R.RI_PROX_HAAR, tau=c.tau, sigma_train=0.0, L=L,
+                           check_every=6, use_graph=1, diverge_checks=0)
+    torch.cuda.synchronize()
+    x_ref = torch.empty((c.N, c.N), dtype=torch.float32, device=DEV)
+    R.pnp_solve(ctx, y, opts, x_ref)
+    y_late = torch.zeros_like(y)
+    torch.cuda.synchronize()
+    torch.cuda._sleep(20_000_000)          # a bounded spin on the current stream
+    y_late.copy_(y)                        # queued behind it
+    x = torch.empty_like(x_ref)
+    R.pnp_solve(ctx, y_late, opts, x)
+    e = rel(x.cpu().numpy(), x_ref.cpu().numpy())
+    print(f"solve on data still in flight vs after a sync: {e:.2e}; |x| {float(torch.linalg.vector_norm(x)):.3e}")
+    assert float(torch.linalg.vector_norm(x_ref)) > 0.0
+    assert e <= 1e-5

@@ -5,7 +5,8 @@
 // Layout: grid row-major [ky][kx], wrap-centred (pixel n at cell n mod N').
 // Rows: one workgroup per image row, the whole N'-point row in LDS, Stockham
 // radix-16 passes (natural order in and out, twiddles from an FP64-computed
-// table). Only the N non-zero rows are transformed on the way in, and only
+// table); the first pass reads global memory and the last one writes it
+// directly. Only the N non-zero rows are transformed on the way in, and only
 // the N needed rows on the way out.
 // Columns: four-step decomposition N' = N1 * N2 over stripes of adjacent
 // columns, so every global access is a contiguous row segment:
@@ -138,6 +139,69 @@ __device__ void fft_lds(cx<T> *s, int logL, int logCW, const cx<T> *__restrict__
 
 __device__ __forceinline__ bool in_band(int r, int N, int Np) { return r < N / 2 || r >= Np - N / 2; }
 
+// Row transforms (one row of L = N' points per workgroup) read their input
+// straight into the first pass and write their output straight from the last:
+// the first pass (radix 16, Ns = 1, no twiddles) takes inputs j + r L/16 of
+// group j from ld(index) and leaves 16 j + r in LDS; the last pass (radix R,
+// Ns = L/R, twiddle step j) hands outputs j + r Ns to st(index, value). Both
+// index patterns run contiguously over j, so the global accesses coalesce; the
+// passes between are the LDS Stockham passes. Same arithmetic as fft_lds.
+template <typename T, bool PAD, typename Load>
+__device__ __forceinline__ void row_first_pass(cx<T> *s, int L, bool inv, Load &&ld) {
+    const int ng = L / 16;
+    for (int j = threadIdx.x; j < ng; j += blockDim.x) {
+        cx<T> v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = ld(j + r * ng);
+        dft_reg<T, 16>(v, inv);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s[pidx<PAD>(16 * j + r)] = v[r];
+    }
+    __syncthreads();
+}
+
+template <typename T, int R, bool PAD, typename Store>
+__device__ __forceinline__ void row_last_pass(const cx<T> *s, int L, const cx<T> *__restrict__ tw, bool inv,
+                                              Store &&st) {
+    const int Ns = L / R;
+    for (int j = threadIdx.x; j < Ns; j += blockDim.x) {
+        cx<T> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = s[pidx<PAD>(j + r * Ns)];
+        if (j != 0) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cx<T> w = tw[j * r];
+                if (inv) w.y = -w.y;
+                v[r] = v[r] * w;
+            }
+        }
+        dft_reg<T, R>(v, inv);
+#pragma unroll
+        for (int r = 0; r < R; ++r) st(j + r * Ns, v[r]);
+    }
+}
+
+// Whole row, logL >= 5: the first pass, radix-16 LDS passes, the last pass.
+template <typename T, bool PAD, typename Load, typename Store>
+__device__ __forceinline__ void row_fft(cx<T> *s, int logL, const cx<T> *__restrict__ tw, bool inv, Load &&ld,
+                                        Store &&st) {
+    const int L = 1 << logL;
+    row_first_pass<T, PAD>(s, L, inv, ld);
+    int Ns = 16, rem = logL - 4;
+    while (rem > 4) {
+        stockham_pass<T, 16, PAD>(s, L, 0, Ns, tw, 1, inv);
+        Ns <<= 4;
+        rem -= 4;
+    }
+    switch (rem) {
+        case 4: row_last_pass<T, 16, PAD>(s, L, tw, inv, st); break;
+        case 3: row_last_pass<T, 8, PAD>(s, L, tw, inv, st); break;
+        case 2: row_last_pass<T, 4, PAD>(s, L, tw, inv, st); break;
+        default: row_last_pass<T, 2, PAD>(s, L, tw, inv, st); break;
+    }
+}
+
 // Z then the row DFT of image row iy (blockIdx.x), written to grid row (iy - N/2) mod N'.
 // With a w-stack's phase screen (chirp != NULL) the padded image is x c_s.
 template <typename T, bool PAD>
@@ -148,25 +212,20 @@ __global__ void k_zpad_rowfft(const T *__restrict__ x, cx<T> *__restrict__ grid,
     const int Np = 1 << logNp;
     const int iy = blockIdx.x;
     const T cy = icorr[iy];
-    for (int gx = threadIdx.x; gx < Np; gx += blockDim.x) {
+    const T *xr = x + (size_t)iy * N;
+    const cx<T> *chr = chirp ? chirp + (size_t)iy * N : nullptr;
+    auto ld = [&](int gx) -> cx<T> {
         const int ix = (gx + N / 2) & (Np - 1);
-        cx<T> v = mk<T>((T)0, (T)0);
-        if (ix < N) {
-            const T a = x[(size_t)iy * N + ix] * icorr[ix] * cy;
-            if (chirp) {
-                const cx<T> ch = chirp[(size_t)iy * N + ix];
-                v = mk<T>(a * ch.x, a * ch.y);
-            } else {
-                v = mk<T>(a, (T)0);
-            }
+        if (ix >= N) return mk<T>((T)0, (T)0);
+        const T a = xr[ix] * icorr[ix] * cy;
+        if (chr) {
+            const cx<T> ch = chr[ix];
+            return mk<T>(a * ch.x, a * ch.y);
         }
-        s[pidx<PAD>(gx)] = v;
-    }
-    __syncthreads();
-    fft_lds<T, PAD>(s, logNp, 0, tw, 1, false);
-    const int gy = (iy - N / 2) & (Np - 1);
-    cx<T> *row = grid + (size_t)gy * Np;
-    for (int k = threadIdx.x; k < Np; k += blockDim.x) row[k] = s[pidx<PAD>(k)];
+        return mk<T>(a, (T)0);
+    };
+    cx<T> *row = grid + (size_t)((iy - N / 2) & (Np - 1)) * Np;
+    row_fft<T, PAD>(s, logNp, tw, false, ld, [&](int k, cx<T> v) { row[k] = v; });
 }
 
 // Inverse row DFT of grid row (iy - N/2) mod N', then crop, correction, real part:
@@ -181,24 +240,23 @@ __global__ void k_irowfft_crop(const cx<T> *__restrict__ grid, T *__restrict__ o
     cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
     const int Np = 1 << logNp;
     const int iy = blockIdx.x;
-    const int gy = (iy - N / 2) & (Np - 1);
-    const cx<T> *row = grid + (size_t)gy * Np;
-    for (int k = threadIdx.x; k < Np; k += blockDim.x) s[pidx<PAD>(k)] = row[k];
-    __syncthreads();
-    fft_lds<T, PAD>(s, logNp, 0, tw, 1, true);
+    const cx<T> *row = grid + (size_t)((iy - N / 2) & (Np - 1)) * Np;
     const T cy = icorr[iy];
-    for (int ix = threadIdx.x; ix < N; ix += blockDim.x) {
-        const int gx = (ix - N / 2) & (Np - 1);
-        const cx<T> v = s[pidx<PAD>(gx)];
+    T *orow = out + (size_t)iy * N;
+    const cx<T> *chr = chirp ? chirp + (size_t)iy * N : nullptr;
+    auto st = [&](int gx, cx<T> v) {
+        const int ix = (gx + N / 2) & (Np - 1);   // the crop: image column ix < N
+        if (ix >= N) return;
         T re = v.x;
-        if (chirp) {
-            const cx<T> ch = chirp[(size_t)iy * N + ix];
+        if (chr) {
+            const cx<T> ch = chr[ix];
             re = v.x * ch.x + v.y * ch.y;
         }
         const T val = re * icorr[ix] * cy;
-        if (accumulate) out[(size_t)iy * N + ix] += val;
-        else out[(size_t)iy * N + ix] = val;
-    }
+        if (accumulate) orow[ix] += val;
+        else orow[ix] = val;
+    };
+    row_fft<T, PAD>(s, logNp, tw, true, [&](int k) { return row[k]; }, st);
 }
 
 // Four-step pass A (in place): rows n2 + N2*n1 of stripe [x0, x0+CW).

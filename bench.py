@@ -381,7 +381,6 @@ def main():
     ap.add_argument("--holo-only", action="store_true", help="only the holographic measurement")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the FB time-to-SNR run")
     ap.add_argument("--fb-iters", type=int, default=300)
     ap.add_argument("--no-pnp", action="store_true", help="skip the denoiser training and the PnP-FB run")

@@ -157,3 +157,23 @@ def test_empty_and_single_visibility():
             from oracle import phi as OP
             op = OP.Operator(N, uvw, cell=cell, W=W, n_wplanes=33)
             assert rel(g.cpu().numpy(), op.phi_adj_phi(synth.random_image(N, 1))) <= 1e-11
+
+
+@pytest.mark.parametrize("N", [16, 32, 64, 256])
+def test_small_grids_every_row_pass_shape(N):
+    """Phi^dagger Phi (FP64) against the oracle on grids of N' = 32, 64, 128 and 512
+    points: the row transforms' last pass is radix 2, 4, 8 and 2 (after a middle
+    radix-16 pass), the first pass radix 16 in every case."""
+    cell = 60 * synth.ARCSEC
+    W = 2 * 3.0 / (2 * N * N * cell ** 2)
+    uvw = synth.random_uvw(60, 2.0, W, seed=11)
+    d = R.plan_desc(N, 60, cell_rad=cell, w_max=W, n_wplanes=33, precision=64, g_mode=R.RI_G_OTF)
+    ctx = R.ri_create(d, uvw)
+    xs = synth.random_image(N, 4)
+    g = _img(np.zeros((N, N)), 64)
+    R.ri_gradient(ctx, _img(xs, 64), "none", g)
+    from oracle import phi as OP
+    op = OP.Operator(N, uvw, cell=cell, W=W, n_wplanes=33)
+    e = rel(g.cpu().numpy(), op.phi_adj_phi(xs))
+    print(f"N {N}: Phi^dagger Phi rel err {e:.2e}")
+    assert e <= 1e-12

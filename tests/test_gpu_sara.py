@@ -192,3 +192,46 @@ def test_full_size_dictionary_c1():
     print(f"C1 dictionary: reconstruction {e_pr:.2e}, energy {e_en:.2e}, adjoint {e_adj:.2e}, "
           f"db1 {e1:.2e}, db8 {e8:.2e}")
     assert e_pr <= 2e-6 and e_en <= 2e-6 and e_adj <= 1e-6 and e1 <= 2e-6 and e8 <= 2e-6
+
+
+def test_full_size_dictionary_c4():
+    """4096^2, FP32 (the last row synthesis takes two 8-output blocks per lane at
+    this size): Psi Psi^dagger x = x, ||Psi^dagger x|| = ||x||, the adjoint identity,
+    the db1 slot against the oracle over the whole image, and two prox
+    sub-iterations from v = 0 against the same step composed from the checked
+    analysis and synthesis: x1 = max(0, z - Psi clip(Psi^dagger max(0, z), +-t))."""
+    n = 4096
+    ctx = _ctx(n, 32)
+    x = synth.sky(n, seed=3, n_compact=64, n_ext=4).astype(np.float32).astype(np.float64)
+    xt = torch.tensor(x, dtype=torch.float32, device=DEV)
+    c = torch.empty(9, n, n, dtype=torch.float32, device=DEV)
+    R.ri_sara_analysis(ctx, xt, c)
+    xr = torch.empty_like(xt)
+    R.ri_sara_synthesis(ctx, c, xr)
+    e_pr = rel(xr.cpu().numpy(), x)
+    e_en = abs(float(torch.linalg.vector_norm(c.double())) / np.linalg.norm(x) - 1)
+    d = torch.randn(9, n, n, device=DEV)
+    xd = torch.empty_like(xt)
+    R.ri_sara_synthesis(ctx, d, xd)
+    lhs, rhs = float(torch.sum(c.double() * d.double())), float(torch.sum(xt.double() * xd.double()))
+    e_adj = abs(lhs - rhs) / (float(torch.linalg.vector_norm(c.double())) * float(torch.linalg.vector_norm(d.double())))
+    e1 = rel(c[1].cpu().numpy(), S.dwt2(x, S.daubechies(1)) / 3)
+    del d, xd
+    # prox: two sub-iterations from the fresh state (v = 0, w = 1)
+    t = 0.3 * float(x.max()) / 3
+    R.ri_sara_setup(ctx, 2)
+    z = xt - 0.05 * float(x.max())
+    out = torch.empty_like(xt)
+    R.denoise(ctx, z, out, R.RI_PROX_SARA, t)
+    x0 = torch.clamp(z, min=0.0)
+    v1 = torch.empty_like(c)
+    R.ri_sara_analysis(ctx, x0, v1)
+    v1.clamp_(-t, t)
+    sv = torch.empty_like(xt)
+    R.ri_sara_synthesis(ctx, v1, sv)
+    ref = torch.clamp(z - sv, min=0.0)
+    e_px = float(torch.linalg.vector_norm((out - ref).double()) / torch.linalg.vector_norm(ref.double()))
+    print(f"C4 dictionary: reconstruction {e_pr:.2e}, energy {e_en:.2e}, adjoint {e_adj:.2e}, db1 {e1:.2e}, "
+          f"prox step vs composed {e_px:.2e}")
+    assert e_pr <= 2e-6 and e_en <= 2e-6 and e_adj <= 1e-6 and e1 <= 2e-6
+    assert e_px <= 1e-5

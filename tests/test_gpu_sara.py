@@ -182,7 +182,7 @@ def test_full_size_dictionary_c1():
     R.ri_sara_synthesis(ctx, c, xr)
     e_pr = rel(xr.cpu().numpy(), x)
     e_en = abs(float(torch.linalg.vector_norm(c.double())) / np.linalg.norm(x) - 1)
-    d = torch.randn(9, n, n, dtype=_ft(prec), device=DEV)
+    d = torch.randn(9, n, n, device=DEV)
     xd = torch.empty_like(xt)
     R.ri_sara_synthesis(ctx, d, xd)
     lhs, rhs = float(torch.sum(c.double() * d.double())), float(torch.sum(xt.double() * xd.double()))

@@ -184,14 +184,15 @@ void do_fb_step(ri_ctx *c, const T *x_in, const void *y, double gamma, int kind,
 }
 
 // Main view at tile T (FP64 fractions when G is stored or the context is
-// FP64), plus the CSR G in that view's order.
+// FP64), plus the CSR G in that view's order. The holographic matrix and the
+// SARA state are grid- and image-level and do not depend on the view's
+// visibility order, so they are kept.
 void build_main_view(ri_ctx *c, int tile) {
     const bool f64frac = c->d.g_mode == RI_G_CSR || c->d.precision == 64;
     free_view(c, c->view);
     if (c->csr.val) {
-        dev_free(c, c->csr.rowptr); dev_free(c, c->csr.val);
-    holo_free(c);
-    sara_free(c);
+        dev_free(c, c->csr.rowptr);
+        dev_free(c, c->csr.val);
         c->csr = CSR();
     }
     build_view(c, c->view, tile, f64frac ? 8 : 4);

@@ -2,8 +2,9 @@
 (test infrastructure only).
 
 Paper passages followed: appendix C (a DnCNN-type denoiser D trained with the
-l1 loss E||D(u + sigma n) - u||_1 of eq. C1; the firm-nonexpansiveness
-penalty is not part of this oracle), appendix D (the denoiser is applied to
+l1 loss E||D(u + sigma n) - u||_1 of eq. C1; the relaxed firm-nonexpansiveness
+penalty through the Jacobian products below; the optimiser, which the paper
+does not name, is Adam), appendix D (the denoiser is applied to
 image facets independently thanks to its compact receptive field).
 
 Readings (the paper gives only "a simple DnCNN"): L layers of 3x3
@@ -20,8 +21,9 @@ subtraction stay in full precision. In the backward pass the pre-activation
 gradients of layers L-1..1 are rounded to bfloat16 where the GPU stores them.
 
 Parity: the forward convolution is pinned against scipy.signal.correlate2d,
-the analytic gradients against central finite differences in FP64
-(tests/test_oracle_cnn.py).
+the analytic gradients against central finite differences in FP64, Adam
+against a hand-computed three-step example and the constant-gradient closed
+form (tests/test_oracle_cnn.py).
 """
 from __future__ import annotations
 
@@ -136,6 +138,35 @@ def l1_loss(D: np.ndarray, u: np.ndarray) -> float:
 def l1_dnet(D: np.ndarray, u: np.ndarray) -> np.ndarray:
     """d loss / d net(z) for D = z - net(z): -sign(D - u) / numel."""
     return -np.sign(D - u) / D.size
+
+
+def adam_step(p: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, t: int, lr: float,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam update (Kingma and Ba 2015), the optimiser of the training
+    (the paper names none; this reading is the build's). With the moment
+    estimates m, v (zero before the first step) and the step count t >= 1:
+      m <- beta1 m + (1 - beta1) g,  v <- beta2 v + (1 - beta2) g^2,
+      p <- p - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
+    Returns (p, m, v) as new arrays."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return p - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+def flatten_params(params) -> np.ndarray:
+    """The parameter vector in the library's layout: per layer W[c_out][c_in][3][3], then b[c_out]."""
+    return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params])
+
+
+def unflatten_params(vec: np.ndarray, like) -> list:
+    out, o = [], 0
+    for w, b in like:
+        nw, nb = w.size, b.size
+        out.append((vec[o:o + nw].reshape(w.shape).copy(), vec[o + nw:o + nw + nb].copy()))
+        o += nw + nb
+    return out
 
 
 def denoise_facets(params, z: np.ndarray, core: int, halo: int, bf16: bool = False) -> np.ndarray:

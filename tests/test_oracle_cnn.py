@@ -178,3 +178,34 @@ def test_jvp_param_grad_matches_central_differences():
         bp[0] += 1e-3
         assert f([p if k != l else (w, bp) for k, p in enumerate(ps)]) == pytest.approx(f(ps), rel=1e-12)
         assert np.all(gr[l][1] == 0)
+
+
+def test_adam_three_steps_by_hand():
+    """Adam (beta1 0.9, beta2 0.999, eps 1e-8, lr 0.1) on a scalar from p = 1
+    with gradients 0.5, -1, 2, worked by hand:
+      t=1: m = 0.05, v = 0.00025, m^ = 0.5, v^ = 0.25,
+           p = 1 - 0.1 * 0.5 / (0.5 + 1e-8) = 0.900000002;
+      t=2: m = 0.045 - 0.1 = -0.055, v = 0.00024975 + 0.001 = 0.00124975,
+           m^ = -0.055 / 0.19 = -0.2894736842, v^ = 0.00124975 / 0.001999 = 0.6251875938,
+           p = 0.900000002 + 0.1 * 0.2894736842 / (0.7906886516 + 1e-8) = 0.9366103542;
+      t=3: m = -0.0495 + 0.2 = 0.1505, v = 0.00124850025 + 0.004 = 0.00524850025,
+           m^ = 0.1505 / 0.271 = 0.5553505535, v^ = 0.00524850025 / 0.002997001 = 1.7512507503,
+           p = 0.9366103542 - 0.1 * 0.5553505535 / (1.3233483027 + 1e-8) = 0.8946447927."""
+    p, m, v = np.array([1.0]), np.zeros(1), np.zeros(1)
+    want = [0.900000002, 0.93661035424056560, 0.89464479271810477]
+    for t, (g, w) in enumerate(zip((0.5, -1.0, 2.0), want), 1):
+        p, m, v = C.adam_step(p, np.array([g]), m, v, t, 0.1)
+        assert p[0] == pytest.approx(w, rel=1e-15, abs=1e-15)
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g the bias corrections give m^ = g and
+    v^ = g^2 at every step, so each step moves p by exactly lr g / (|g| + eps);
+    a missing or wrong correction (or a beta slip) breaks this at t >= 2."""
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(50) * 10.0 ** rng.uniform(-6, 2, 50)
+    p0 = rng.standard_normal(50)
+    p, m, v = p0.copy(), np.zeros(50), np.zeros(50)
+    for t in range(1, 6):
+        p, m, v = C.adam_step(p, g, m, v, t, 1e-3)
+        np.testing.assert_allclose(p, p0 - t * 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-13, atol=1e-16)

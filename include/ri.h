@@ -125,6 +125,27 @@ ri_status ri_set_data(ri_ctx *ctx, const void *y, ri_stream stream);
 ri_status ri_gradient(ri_ctx *ctx, const void *x, const void *y, void *g, double *r2,
                       ri_stream stream);
 
+/* ri_gradient without any device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same gradient, ||Phi x - y||^2 and arguments as
+ * ri_gradient, but every work buffer of its kernels (the two oversampled
+ * grids per w-stack, the persistent launch's work counter, the FP64 partial
+ * sums) lies in a workspace compiled into the library, RI_NOALLOC_SCRATCH_BYTES
+ * per device, held by each GPU the library runs on until the process ends.
+ * A y in the caller's order is read in place (no staging copy).
+ * The call allocates nothing: no hipMalloc, hipFree or allocating library
+ * routine. Limits and errors: RI_EINVAL when the context's buffers do not
+ * fit the workspace (about 2 x w-stacks x N'^2 complex cells plus 20 KB:
+ * FP32 up to N' = 2048, FP64 up to N' = 1024 without w-stacking), or while
+ * kernel timing (ri_profile) is on. Every call on a GPU shares that GPU's one
+ * workspace: calls that overlap in time on one GPU (other host threads, other
+ * streams, other contexts) race and corrupt each other's results; serialise
+ * them, e.g. on one stream. The workspace keeps the last call's contents;
+ * each call clears what must start at zero itself. */
+#define RI_NOALLOC_SCRATCH_BYTES ((int64_t)72 << 20)
+ri_status ri_gradient_noalloc(ri_ctx *ctx, const void *x, const void *y, void *g, double *r2,
+                              ri_stream stream);
+
 /* L = ||Re{Phi^dagger Phi}||_S by the power method in FP64 on the device
  * (appendix A), whatever the context precision: x <- A x / ||A x||, stop when
  * the relative change of ||A x|| is <= rtol or after max_it applications.

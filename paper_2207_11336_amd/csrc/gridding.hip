@@ -272,6 +272,7 @@ k_tiles(TileArgs<T> a) {
                 } else if (OP == OP_FUSED) {
                     r = acc;
                     if (a.ysorted) r = r - a.ysorted[m];
+                    else if (a.yuser) r = r - a.yuser[a.perm[m]];
                     if (lane == 0) r2 += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
                 } else {
                     r = a.yuser[a.perm[m]];
@@ -331,6 +332,7 @@ k_tiles(TileArgs<T> a) {
                 } else if (OP == OP_FUSED) {
                     r = acc;
                     if (a.ysorted) r = r - a.ysorted[m];
+                    else if (a.yuser) r = r - a.yuser[a.perm[m]];
                     if (lane == 0) r2 += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
                 } else {
                     r = a.yuser[a.perm[m]];
@@ -507,7 +509,7 @@ size_t lds_for_tile(int tile, int H, int cx_bytes) { return tiles_lds((size_t)ti
 
 template <typename T>
 void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, int op, bool otf, const cx<T> *y_sorted,
-                  const cx<T> *y_user, cx<T> *y_out_user, double *r2_partials, hipStream_t s) {
+                  const cx<T> *y_user, cx<T> *y_out_user, double *r2_partials, hipStream_t s, int32_t *counter) {
     if (c->M == 0 || v.n_items == 0) {
         if (op == OP_FUSED && r2_partials) fill_zero_f64(r2_partials, c->n_partials, s);
         return;
@@ -519,11 +521,12 @@ void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, int op, bool otf, const 
     a.yuser = y_user;
     a.yout = y_out_user;
     a.r2part = r2_partials;
+    a.counter = counter ? counter : c->d_counter;
     if (!otf) {
         a.rowptr = c->csr.rowptr;
         a.gval = (const cx<T> *)c->csr.val;
     }
-    fill_zero_i32(c->d_counter, 1, s);
+    fill_zero_i32(a.counter, 1, s);
     ProfScope prof(c, PROF_TILES, s);
     if (otf) {
         if (op == OP_DEGRID) launch_op<T, OP_DEGRID, true>(c, a, s);
@@ -578,9 +581,9 @@ void fill_holo(ri_ctx *c, const View &v, hipStream_t s) {
 }
 
 template void launch_tiles<float>(ri_ctx *, const View &, Prec<float> &, int, bool, const cx<float> *,
-                                  const cx<float> *, cx<float> *, double *, hipStream_t);
+                                  const cx<float> *, cx<float> *, double *, hipStream_t, int32_t *);
 template void launch_tiles<double>(ri_ctx *, const View &, Prec<double> &, int, bool, const cx<double> *,
-                                   const cx<double> *, cx<double> *, double *, hipStream_t);
+                                   const cx<double> *, cx<double> *, double *, hipStream_t, int32_t *);
 template void fill_csr<float>(ri_ctx *, hipStream_t);
 template void fill_csr<double>(ri_ctx *, hipStream_t);
 template void fill_holo<float>(ri_ctx *, const View &, hipStream_t);

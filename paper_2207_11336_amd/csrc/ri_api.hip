@@ -585,6 +585,7 @@ ri_status ri_create(const ri_plan_desc *desc, const double *uvw, ri_ctx **out) {
         }
         auto t0 = std::chrono::steady_clock::now();
         RI_CHECK_HIP(hipGetDevice(&c->device));
+        noalloc_init_device(c->device);
         hipDeviceProp_t prop;
         RI_CHECK_HIP(hipGetDeviceProperties(&prop, c->device));
         c->dev.cu_count = prop.multiProcessorCount;

@@ -214,9 +214,14 @@ template <typename T> void adj_fft_crop(ri_ctx *c, Prec<T> &p, T *x, hipStream_t
 
 // gridding.hip
 enum { OP_DEGRID = 1, OP_GRID = 2, OP_FUSED = 3 };
+// The persistent uv-tile launch. OP_FUSED subtracts y_sorted (internal order)
+// or else y_user (caller's order, read through the view's permutation), or
+// nothing when both are NULL. counter: the launch's work counter (NULL: the
+// context's).
 template <typename T> void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, int op, bool otf,
                                         const cx<T> *y_sorted, const cx<T> *y_user,
-                                        cx<T> *y_out_user, double *r2_partials, hipStream_t s);
+                                        cx<T> *y_out_user, double *r2_partials, hipStream_t s,
+                                        int32_t *counter = nullptr);
 template <typename T> void fill_csr(ri_ctx *c, hipStream_t s);
 // Accumulate G^H G of the visibilities of v (FP64 fractions) into c->holo.val (zeroed).
 template <typename T> void fill_holo(ri_ctx *c, const View &v, hipStream_t s);
@@ -243,6 +248,10 @@ int tiles_partials(ri_ctx *c);
 // Dynamic LDS bytes of a fused tile-kernel workgroup at tile side `tile` (subgrid tile + 2 H),
 // cx_bytes = 8 (FP32) or 16 (FP64).
 size_t lds_for_tile(int tile, int H, int cx_bytes);
+
+// noalloc.hip: the allocation-free gradient's workspace
+void noalloc_init_device(int device);          // once per device, with it current (ri_create)
+size_t noalloc_scratch_bytes(const ri_ctx *c); // workspace bytes the context's gradient needs
 
 // image.hip
 template <typename T> void fill_zero(cx<T> *p, int64_t n, hipStream_t s);

@@ -28,7 +28,8 @@ EXPORTS = ("ri_create", "ri_destroy", "ri_last_error", "phi_forward", "phi_adjoi
            "ri_cnn_get_params", "ri_cnn_forward", "ri_cnn_grad", "ri_cnn_train_step", "ri_cnn_jvp", "ri_cnn_vjp",
            "ri_cnn_fne_norm", "ri_cnn_jvp_grad", "ri_cnn_train_step_fne", "ri_holo_build", "ri_holo_release",
            "ri_holo_apply", "ri_holo_normal", "ri_holo_get_stats", "ri_sara_setup", "ri_sara_reweight",
-           "ri_sara_analysis", "ri_sara_synthesis", "ri_sara_get_state")
+           "ri_sara_analysis", "ri_sara_synthesis", "ri_sara_get_state", "ri_gradient_noalloc")
+RI_NOALLOC_SCRATCH_BYTES = 72 << 20
 
 
 class RIError(RuntimeError):
@@ -99,6 +100,8 @@ def load() -> ctypes.CDLL:
     L.phi_adjoint.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]; L.phi_adjoint.restype = st
     L.ri_set_data.argtypes = [c_void_p, c_void_p, c_void_p]; L.ri_set_data.restype = st
     L.ri_gradient.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]; L.ri_gradient.restype = st
+    L.ri_gradient_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.ri_gradient_noalloc.restype = st
     L.ri_power_norm.argtypes = [c_void_p, c_int32, c_double, c_void_p, POINTER(c_double), POINTER(c_int32), c_void_p]
     L.ri_power_norm.restype = st
     L.denoise.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_double, c_void_p]; L.denoise.restype = st
@@ -291,6 +294,14 @@ def ri_gradient(ctx: Context, x, y, g, r2=None, stream=None):
     r2p = _dev(r2, torch.float64, 1, "r2") if r2 is not None else None
     _check(ctx, load().ri_gradient(ctx.handle, _image(ctx, x, "x"), _data_arg(ctx, y), _image(ctx, g, "g"),
                                    r2p, _stream(stream)))
+
+
+def ri_gradient_noalloc(ctx: Context, x, y, g, r2=None, stream=None):
+    """ri_gradient with every work buffer in the library's static device workspace (no allocation)."""
+    import torch
+    r2p = _dev(r2, torch.float64, 1, "r2") if r2 is not None else None
+    _check(ctx, load().ri_gradient_noalloc(ctx.handle, _image(ctx, x, "x"), _data_arg(ctx, y),
+                                           _image(ctx, g, "g"), r2p, _stream(stream)))
 
 
 def ri_power_norm(ctx: Context, max_it: int = 500, rtol: float = 1e-8, x0=None, stream=None, allow_notconv=True):
@@ -560,3 +571,4 @@ def ri_cnn_train_step(net: Cnn, clean, sigma: float, seed: int, lr: float, loss=
     cp, B, h, w = _batch(net, clean, "clean")
     lp = _dev(loss, torch.float64, 1, "loss") if loss is not None else None
     _check_cnn(net, load().ri_cnn_train_step(net.handle, cp, B, h, w, sigma, seed, lr, lp, _stream(stream)))
+

@@ -306,24 +306,29 @@ k_tiles(TileArgs<T> a) {
                     }
                 }
             } else {
-                const int64_t rp = a.rowptr[m];
+                // stored row: lane l holds entries t = l + 16 i (row-major over the
+                // window); its columns follow from the window. The window cell
+                // (ay, ax) of entry t advances by 16 entries per slot without a
+                // division: 16 = q16 S + (16 - q16 S), q16 = floor(16 / S).
+                const cx<T> *gp = a.gval + a.rowptr[m];
                 cx<T> wv[MAXI];
-                int li[MAXI];
 #pragma unroll
                 for (int i = 0; i < MAXI; ++i) {
-                    wv[i] = mk<T>((T)0, (T)0);
-                    li[i] = base;
                     const int t = lane + 16 * i;
-                    if (i < NI && t < SS) {
-                        // entry t of the row is window cell (t / S, t % S): its
-                        // column is implied by the row's window, only the value is stored
-                        wv[i] = a.gval[rp + t];
-                        const int ay = t / S;
-                        li[i] = base + ay * W + (t - ay * S);
-                        if (OP & OP_DEGRID) acc = acc + wv[i] * Xs[li[i]];
-                    }
+                    wv[i] = mk<T>((T)0, (T)0);
+                    if (i < NI && t < SS) wv[i] = gp[t];
                 }
+                const int q16 = S <= 8 ? 2 : (S <= 16 ? 1 : 0);
+                const int ay0 = (lane >= S) + (lane >= 2 * S), ax0 = lane - ay0 * S;
                 if (OP & OP_DEGRID) {
+                    int ay = ay0, ax = ax0;
+#pragma unroll
+                    for (int i = 0; i < MAXI; ++i) {
+                        if (i < NI && lane + 16 * i < SS) acc = acc + wv[i] * Xs[base + ay * W + ax];
+                        ax += 16 - q16 * S;
+                        ay += q16;
+                        if (ax >= S) { ax -= S; ++ay; }
+                    }
                     acc.x = sum16(acc.x);
                     acc.y = sum16(acc.y);
                 }
@@ -338,13 +343,18 @@ k_tiles(TileArgs<T> a) {
                     r = a.yuser[a.perm[m]];
                 }
                 if (OP & OP_GRID) {
+                    int ay = ay0, ax = ax0;
 #pragma unroll
                     for (int i = 0; i < MAXI; ++i) {
                         if (i < NI && lane + 16 * i < SS) {
                             const cx<T> c = mulc(r, wv[i]);
-                            lds_add(&Yr[li[i]], (double)c.x);
-                            lds_add(&Yi[li[i]], (double)c.y);
+                            const int o = base + ay * W + ax;
+                            lds_add(&Yr[o], (double)c.x);
+                            lds_add(&Yi[o], (double)c.y);
                         }
+                        ax += 16 - q16 * S;
+                        ay += q16;
+                        if (ax >= S) { ax -= S; ++ay; }
                     }
                 }
             }

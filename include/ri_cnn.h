@@ -62,6 +62,15 @@ ri_status ri_cnn_forward(ri_cnn *net, const float *z, float *out, int32_t batch,
 ri_status ri_cnn_grad(ri_cnn *net, const float *z, const float *g, int32_t batch, int32_t h, int32_t w,
                       float *grads, ri_stream stream);
 
+/* A training batch drawn from a pool of clean patches resident on the device:
+ * out[b] = patch p_b of pool in orientation o_b, one of the eight symmetries
+ * of the square (transpose, row reversal, column reversal), with (p_b, o_b)
+ * from a counter-based generator keyed by (seed, b). pool: dev
+ * [n_pool][side][side] FP32; out: dev [batch][side][side]. The network is
+ * only used for its error message. */
+ri_status ri_cnn_sample_batch(ri_cnn *net, const float *pool, int64_t n_pool, int32_t side, int32_t batch,
+                              uint64_t seed, float *out, ri_stream stream);
+
 /* One training step: noisy = clean + sigma n with n ~ N(0,1) from a
  * counter-based generator keyed by (seed, pixel index), D(noisy), loss
  * mean|D - clean| (FP64, written to loss if non-NULL, dev double[1]),
@@ -98,14 +107,19 @@ ri_status ri_cnn_jvp_grad(ri_cnn *net, const float *z, const float *v, const flo
 /* One training step with the relaxed firm-nonexpansiveness penalty (appendix
  * C; the paper relaxes the constraint of its training loss into a soft
  * penalty whose form it does not give): loss mean|D(u + sigma n) - u| +
- * lambda max(||J_{2D - I}(u + sigma n)||_S^2, 1 - eps), the norm estimated by
+ * lambda max(||J_{2D - I}(z)||_S^2, 1 - eps), the norm estimated by
  * power_iters iterations on J^T J warm-started from the previous call's
  * vector (a seeded normal at the first call), the penalty's gradient through
- * ri_cnn_jvp_grad's pass, one Adam update. loss, fne_sq: optional dev
- * double[1] (the l1 term, and the squared norm estimate). */
+ * ri_cnn_jvp_grad's pass, one Adam update. The Jacobian is taken at
+ * z = u + sigma n (point RI_FNE_AT_INPUT) or at z = rho u + (1 - rho)
+ * D(u + sigma n), rho uniform in [0, 1) per batch item from the seed
+ * (RI_FNE_AT_MIX: points between the clean images and their denoised versions,
+ * the sampling of the relaxed scheme the paper cites). loss, fne_sq: optional
+ * dev double[1] (the l1 term, and the squared norm estimate). */
+enum { RI_FNE_AT_INPUT = 0, RI_FNE_AT_MIX = 1 };
 ri_status ri_cnn_train_step_fne(ri_cnn *net, const float *clean, int32_t batch, int32_t h, int32_t w, float sigma,
-                                uint64_t seed, float lr, float lambda, float eps, int32_t power_iters, double *loss,
-                                double *fne_sq, ri_stream stream);
+                                uint64_t seed, float lr, float lambda, float eps, int32_t power_iters, int32_t point,
+                                double *loss, double *fne_sq, ri_stream stream);
 
 #ifdef __cplusplus
 }

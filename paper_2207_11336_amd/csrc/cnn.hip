@@ -705,13 +705,18 @@ __global__ void k_reduce_rows(const float *__restrict__ part, int nrows, int str
     out[e] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
 }
 
+// Adam (beta1 0.9, beta2 0.999, eps 1e-8) with the bias corrections
+// c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t) from the host (FP64). The
+// weights 1 - beta are written as their own FP32 constants: 1.f - 0.999f
+// would carry the rounding of 0.999f (1.3e-5 of the result) into every
+// second-moment update.
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ gr, float *__restrict__ m,
                        float *__restrict__ v, int64_t n, float lr, float c1, float c2) {
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float b1 = 0.9f, omb1 = 0.1f, b2 = 0.999f, omb2 = 0.001f, eps = 1e-8f;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const float gi = gr[i];
-        const float mi = b1 * m[i] + (1.f - b1) * gi;
-        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        const float mi = b1 * m[i] + omb1 * gi;
+        const float vi = b2 * v[i] + omb2 * gi * gi;
         m[i] = mi;
         v[i] = vi;
         p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
@@ -742,6 +747,39 @@ __global__ void k_noisy(const float *__restrict__ clean, float *__restrict__ noi
 __global__ void k_normal(float *__restrict__ v, int64_t n, uint64_t seed) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         v[i] = normal_at(seed, (uint64_t)i);
+}
+
+// Training batch from a resident pool of patches: item b is patch
+// p = (d >> 3) mod n_pool in orientation d & 7 (bit 0: transpose, bit 1: rows
+// reversed, bit 2: columns reversed; the eight symmetries of the square),
+// d = mix64 of (seed, b). Training images have no preferred orientation.
+__global__ void k_sample_batch(const float *__restrict__ pool, int64_t n_pool, int side, int batch, uint64_t seed,
+                               float *__restrict__ out) {
+    const int64_t per = (int64_t)side * side, n = per * batch;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(i / per);
+        const int r = (int)(i - (int64_t)b * per), y = r / side, x = r - y * side;
+        const uint64_t d = mix64(seed * 0x9E6C63D0676A9A99ull + (uint64_t)b);
+        const int64_t p = (int64_t)((d >> 3) % (uint64_t)n_pool);
+        int sy = y, sx = x;
+        if (d & 1) { const int t = sy; sy = sx; sx = t; }
+        if (d & 2) sy = side - 1 - sy;
+        if (d & 4) sx = side - 1 - sx;
+        out[i] = pool[p * per + (int64_t)sy * side + sx];
+    }
+}
+
+// out = rho_b clean + (1 - rho_b) D over item b of a batch (per_item pixels
+// each), rho_b uniform in [0, 1) from mix64 of (seed, b): the points between
+// the clean images and their denoised noisy versions where the relaxed
+// firm-nonexpansiveness penalty evaluates the Jacobian.
+__global__ void k_mix(const float *__restrict__ clean, const float *__restrict__ D, float *__restrict__ out,
+                      int64_t n, int64_t per_item, uint64_t seed) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = (uint64_t)(i / per_item);
+        const float rho = (float)(mix64(seed * 0xA24BAED4963EE407ull + b) >> 40) * (1.0f / 16777216.0f);
+        out[i] = rho * clean[i] + (1.f - rho) * D[i];
+    }
 }
 
 // out = a - 2 t (the map I - 2 J_net applied through its Jacobian product t).
@@ -1252,6 +1290,18 @@ ri_status ri_cnn_grad(ri_cnn *n, const float *z, const float *g, int32_t B, int3
     });
 }
 
+ri_status ri_cnn_sample_batch(ri_cnn *n, const float *pool, int64_t n_pool, int32_t side, int32_t batch,
+                              uint64_t seed, float *out, ri_stream stream) {
+    if (!n || !pool || !out) return RI_EINVAL;
+    return cnn_guard(n, [&] {
+        if (n_pool < 1 || side < 1 || batch < 1) throw Error(RI_EINVAL, "n_pool, side and batch must be >= 1");
+        const int64_t total = (int64_t)batch * side * side;
+        hipLaunchKernelGGL(k_sample_batch, dim3(gridn(total)), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                           pool, n_pool, (int)side, (int)batch, seed, out);
+        RI_CHECK_HIP(hipGetLastError());
+    });
+}
+
 ri_status ri_cnn_train_step(ri_cnn *n, const float *clean, int32_t B, int32_t h, int32_t w, float sigma,
                             uint64_t seed, float lr, double *loss, ri_stream stream) {
     if (!n || !clean) return RI_EINVAL;
@@ -1347,13 +1397,14 @@ ri_status ri_cnn_jvp_grad(ri_cnn *n, const float *z, const float *v, const float
 }
 
 ri_status ri_cnn_train_step_fne(ri_cnn *n, const float *clean, int32_t B, int32_t h, int32_t w, float sigma,
-                                uint64_t seed, float lr, float lambda, float eps, int32_t power_iters, double *loss,
-                                double *fne_sq, ri_stream stream) {
+                                uint64_t seed, float lr, float lambda, float eps, int32_t power_iters, int32_t point,
+                                double *loss, double *fne_sq, ri_stream stream) {
     if (!n || !clean) return RI_EINVAL;
     return cnn_guard(n, [&] {
         if (!n->training) throw Error(RI_EINVAL, "network created without training buffers");
         if (!(sigma >= 0.f) || !(lr > 0.f) || !(lambda >= 0.f) || !(eps >= 0.f && eps < 1.f) || power_iters < 0)
             throw Error(RI_EINVAL, "sigma >= 0, lr > 0, lambda >= 0, 0 <= eps < 1, power_iters >= 0 required");
+        if (point != RI_FNE_AT_INPUT && point != RI_FNE_AT_MIX) throw Error(RI_EINVAL, "point must be 0 or 1");
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
         check_shape(n, B, h, w);
         ensure_tangent(n);
@@ -1364,8 +1415,15 @@ ri_status ri_cnn_train_step_fne(ri_cnn *n, const float *clean, int32_t B, int32_
         hipLaunchKernelGGL(k_l1, dim3(1024), dim3(256), 0, s, n->D, clean, n->g, np, n->part);
         if (loss) reduce_partials(n->part, 1024, 1, 1, loss, s);
         backward(n, n->zin, n->g, B, h, w, s);
-        // ||J_{2D - I}(z)||_S at the training input by power iterations on
-        // J^T J, warm-started from the previous step's vector
+        if (point == RI_FNE_AT_MIX) {
+            // the Jacobian at rho u + (1 - rho) D(u + sigma n): the network's
+            // activations there (the l1 gradients above are already taken)
+            hipLaunchKernelGGL(k_mix, dim3(gridn(np)), dim3(256), 0, s, clean, n->D, n->zin, np, (int64_t)h * w,
+                               seed ^ 0x5851F42D4C957F2Dull);
+            forward(n, n->zin, n->D, B, h, w, CnnGeo(), s);
+        }
+        // ||J_{2D - I}(z)||_S at z (the training input, or the mixed point) by
+        // power iterations on J^T J, warm-started from the previous step's vector
         float *v = n->fv, *t = n->D, *a = n->g;
         if (!n->fv_ready) {
             hipLaunchKernelGGL(k_normal, dim3(gridn(np)), dim3(256), 0, s, v, np, seed ^ 0x9E3779B97F4A7C15ull);

@@ -28,7 +28,8 @@ EXPORTS = ("ri_create", "ri_destroy", "ri_last_error", "phi_forward", "phi_adjoi
            "ri_cnn_get_params", "ri_cnn_forward", "ri_cnn_grad", "ri_cnn_train_step", "ri_cnn_jvp", "ri_cnn_vjp",
            "ri_cnn_fne_norm", "ri_cnn_jvp_grad", "ri_cnn_train_step_fne", "ri_holo_build", "ri_holo_release",
            "ri_holo_apply", "ri_holo_normal", "ri_holo_get_stats", "ri_sara_setup", "ri_sara_reweight",
-           "ri_sara_analysis", "ri_sara_synthesis", "ri_sara_get_state", "ri_gradient_noalloc")
+           "ri_sara_analysis", "ri_sara_synthesis", "ri_sara_get_state", "ri_gradient_noalloc",
+           "ri_cnn_sample_batch")
 RI_NOALLOC_SCRATCH_BYTES = 72 << 20
 
 
@@ -140,6 +141,9 @@ def load() -> ctypes.CDLL:
     L.ri_cnn_train_step.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, ctypes.c_float,
                                     ctypes.c_uint64, ctypes.c_float, c_void_p, c_void_p]
     L.ri_cnn_train_step.restype = st
+    L.ri_cnn_sample_batch.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_int32, ctypes.c_uint64, c_void_p,
+                                      c_void_p]
+    L.ri_cnn_sample_batch.restype = st
     for f in (L.ri_cnn_jvp, L.ri_cnn_vjp):
         f.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p]
         f.restype = st
@@ -151,7 +155,7 @@ def load() -> ctypes.CDLL:
     L.ri_cnn_jvp_grad.restype = st
     L.ri_cnn_train_step_fne.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, ctypes.c_float,
                                         ctypes.c_uint64, ctypes.c_float, ctypes.c_float, ctypes.c_float, c_int32,
-                                        c_void_p, c_void_p, c_void_p]
+                                        c_int32, c_void_p, c_void_p, c_void_p]
     L.ri_cnn_train_step_fne.restype = st
     _lib = L
     return L
@@ -555,15 +559,19 @@ def ri_cnn_jvp_grad(net: Cnn, z, v, u, grads, stream=None):
                                            _dev(grads, torch.float32, net.n_params, "grads"), _stream(stream)))
 
 
+RI_FNE_AT_INPUT, RI_FNE_AT_MIX = 0, 1
+
+
 def ri_cnn_train_step_fne(net: Cnn, clean, sigma: float, seed: int, lr: float, lam: float, eps: float = 0.05,
-                          power_iters: int = 2, loss=None, fne_sq=None, stream=None):
-    """Training step with the relaxed firm-nonexpansiveness penalty."""
+                          power_iters: int = 2, loss=None, fne_sq=None, stream=None, point: int = RI_FNE_AT_INPUT):
+    """Training step with the relaxed firm-nonexpansiveness penalty (Jacobian at the
+    noisy input, or at random points between the clean and the denoised images)."""
     import torch
     cp, B, h, w = _batch(net, clean, "clean")
     lp = _dev(loss, torch.float64, 1, "loss") if loss is not None else None
     fp = _dev(fne_sq, torch.float64, 1, "fne_sq") if fne_sq is not None else None
     _check_cnn(net, load().ri_cnn_train_step_fne(net.handle, cp, B, h, w, sigma, seed, lr, lam, eps, power_iters,
-                                                 lp, fp, _stream(stream)))
+                                                 point, lp, fp, _stream(stream)))
 
 
 def ri_cnn_train_step(net: Cnn, clean, sigma: float, seed: int, lr: float, loss=None, stream=None):
@@ -572,3 +580,16 @@ def ri_cnn_train_step(net: Cnn, clean, sigma: float, seed: int, lr: float, loss=
     lp = _dev(loss, torch.float64, 1, "loss") if loss is not None else None
     _check_cnn(net, load().ri_cnn_train_step(net.handle, cp, B, h, w, sigma, seed, lr, lp, _stream(stream)))
 
+
+def ri_cnn_sample_batch(net: Cnn, pool, seed: int, out, stream=None):
+    """out[b] = a pool patch in one of the square's eight orientations, both drawn from (seed, b)."""
+    import torch
+    if pool is None or pool.dim() != 3 or out is None or out.dim() != 3:
+        raise ValueError("pool and out must be [n, side, side] tensors")
+    n, side, side2 = pool.shape
+    B, h, w = out.shape
+    if side != side2 or (h, w) != (side, side):
+        raise ValueError(f"pool {tuple(pool.shape)} and out {tuple(out.shape)} must hold square patches of one side")
+    pp = _dev(pool, torch.float32, pool.numel(), "pool")
+    op = _dev(out, torch.float32, out.numel(), "out")
+    _check_cnn(net, load().ri_cnn_sample_batch(net.handle, pp, n, side, B, seed, op, _stream(stream)))

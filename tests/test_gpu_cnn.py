@@ -365,3 +365,31 @@ def test_training_is_deterministic():
         torch.cuda.synchronize()
         out.append(p.cpu())
     assert torch.equal(out[0], out[1])
+
+
+def test_sample_batch_draws_pool_patches_in_the_eight_orientations():
+    """ri_cnn_sample_batch: every item is some pool patch in one of the eight
+    symmetries of the square (exact copy), and over a batch the draws cover
+    several patches and orientations."""
+    rng = np.random.default_rng(4)
+    n, side, B = 7, 32, 64
+    pool = rng.standard_normal((n, side, side)).astype(np.float32)
+    net = R.ri_cnn_create(layers=3, max_batch=1, max_h=16, max_w=16)
+    pt = torch.tensor(pool, device=DEV)
+    out = torch.full((B, side, side), float("nan"), device=DEV)
+    R.ri_cnn_sample_batch(net, pt, 12345, out)
+    got = out.cpu().numpy()
+    net.close()
+    seen = set()
+    for b in range(B):
+        match = None
+        for p in range(n):
+            for o in range(8):
+                v = pool[p].T if o & 1 else pool[p]
+                v = v[::-1, :] if o & 2 else v
+                v = v[:, ::-1] if o & 4 else v
+                if np.array_equal(got[b], v):
+                    match = (p, o)
+        assert match is not None, b
+        seen.add(match)
+    assert len({p for p, _ in seen}) >= 5 and len({o for _, o in seen}) >= 6

@@ -125,10 +125,13 @@ def test_jvp_param_grad_matches_oracle():
     assert max(errs) <= 3e-2
 
 
-def test_penalty_lowers_the_jacobian_norm():
+@pytest.mark.parametrize("point", [R.RI_FNE_AT_INPUT, R.RI_FNE_AT_MIX], ids=["at-input", "at-mix"])
+def test_penalty_lowers_the_jacobian_norm(point):
     """The relaxed firm-nonexpansiveness penalty (lambda 1e-3, every fourth
-    step, four warm-started power iterations) lowers ||J_{2D - I}||_S of the
-    trained network on held-out noisy patches."""
+    step, four warm-started power iterations), with the Jacobian taken at the
+    noisy inputs or at random points between the clean and the denoised
+    images, lowers ||J_{2D - I}||_S of the trained network on held-out noisy
+    patches."""
     from paper_2207_11336_amd.train import train_denoiser
     sig = 1e-2
     patches = torch.tensor(synth.training_patches(512, 64, seed=synth.SEED_TRAIN), device=DEV)
@@ -138,10 +141,11 @@ def test_penalty_lowers_the_jacobian_norm():
     norms = {}
     for lam in (0.0, 1e-3):
         params, _ = train_denoiser(patches, sig, steps=1500, batch=16, lr=1e-3, lr_min=1e-5, fne_lambda=lam,
-                                   fne_iters=4, fne_every=4)
+                                   fne_iters=4, fne_every=4, fne_point=point)
         net = R.ri_cnn_create(layers=L, max_batch=4, max_h=64, max_w=64, training=True)
         R.ri_cnn_set_params(net, params)
         norms[lam] = R.ri_cnn_fne_norm(net, noisy, iters=30, seed=3)
         net.close()
-    print(f"||J_(2D-I)||_S on held-out noisy patches: plain l1 {norms[0.0]:.3f}, with the penalty {norms[1e-3]:.3f}")
+    print(f"||J_(2D-I)||_S on held-out noisy patches: plain l1 {norms[0.0]:.3f}, with the penalty {norms[1e-3]:.3f} "
+          f"(point {point})")
     assert norms[1e-3] < 0.85 * norms[0.0]

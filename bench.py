@@ -93,24 +93,120 @@ def otf_tile_flops(nnz: int, M: int) -> float:
     return 16.0 * nnz + 68.0 * sum_s + 344.0 * M
 
 
-def cpu_baseline(wl, uvw, n_sample: int):
-    """The FP64 oracle's Phi^dagger Phi (Phi, then Re Phi^dagger) on the first
-    n_sample visibilities of the workload, whole 4096^2 FFTs included."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(wl, uvw, n_sample: int, n_single: int, with_extra: bool = True):
+    """The FP64 oracle, as it stands, on the host cores:
+      * value: Phi^dagger Phi (Phi, then Re Phi^dagger, two 4096^2 FFTs
+        included) on the first n_sample visibilities of the workload, median
+        of 5 runs after one warm-up, all threads;
+      * single_thread: the same on the first n_single visibilities, 1 thread;
+      * extra (with_extra): the oracle's 200-iteration plain FB on the
+        narrow-field workload (C0), one full-size gradient (all M
+        visibilities, i.e. one FB iteration's operator work), its Haar prox
+        at the image size, and the CNN denoiser at 256^2, from which the
+        per-iteration FB and PnP times at the full size are extrapolated
+        (labelled as such)."""
     import numpy as np
 
     import synth
+    from oracle import cnn as OC
+    from oracle import fb as OF
     from oracle import phi as OP
     op = OP.Operator(wl.N, uvw[:n_sample], cell=wl.cell_rad, W=wl.W, n_wplanes=wl.n_wplanes)
     x = synth.sky(wl.N)
+    nthr = OP.num_threads()
+    op.grad(x)
     times = []
-    for _ in range(3):
+    for _ in range(5):
         t0 = time.perf_counter()
         op.grad(x)
         times.append(time.perf_counter() - t0)
-    t = sorted(times)[1]
-    return {"value": n_sample / t, "unit": "visibilities/s", "cores": OP.num_threads(), "kind": "oracle",
-            "sample": f"FP64 oracle Phi^dagger Phi on the first {n_sample:,} of {wl.M:,} visibilities of "
-                      f"{wl.name} (two {2 * wl.N}^2 FFTs included), median of 3 runs, {t:.2f} s each"}
+    t = float(np.median(times))
+    del op
+    op1 = OP.Operator(wl.N, uvw[:n_single], cell=wl.cell_rad, W=wl.W, n_wplanes=wl.n_wplanes)
+    OP.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        op1.grad(x)
+        t1 = time.perf_counter() - t0
+    finally:
+        OP.set_num_threads(nthr)
+    del op1
+    out = {"value": n_sample / t, "unit": "visibilities/s", "cores": nthr, "kind": "oracle",
+           "sample": f"FP64 oracle Phi^dagger Phi on the first {n_sample:,} of {wl.M:,} visibilities of "
+                     f"{wl.name} (two {2 * wl.N}^2 FFTs included), median of 5 runs after 1 warm-up, "
+                     f"{t:.2f} s each on {nthr} threads",
+           "runs_s": times, "cpu_model": cpu_model(),
+           "single_thread": {"value": n_single / t1, "unit": "visibilities/s", "seconds": t1,
+                             "sample": f"first {n_single:,} visibilities, 1 thread, one run"}}
+    if not with_extra:
+        return out
+    extra = {}
+    # C0: the oracle's own 200-iteration plain FB (FP64, Haar-l1 + positivity)
+    w0 = synth.C0
+    u0 = synth.uvw(w0)
+    op0 = OP.Operator(w0.N, u0, cell=w0.cell_rad, W=0.0, n_wplanes=1)
+    x0 = synth.sky(w0.N)
+    y0 = op0.phi(x0)
+    tau0 = OF.tau_from_isnr(y0, 40.0)
+    y0 = y0 + OF.complex_noise(tau0, synth.noise_normals(w0.M, synth.SEED_NOISE))
+    L0, _ = OF.power_norm(op0.phi_adj_phi, synth.power_start(w0.N), max_it=60, rtol=1e-8)
+    t0 = time.perf_counter()
+    _, hist = OF.fb(op0, y0, L0, OF.threshold(tau0, L0), 200, x_true=x0)
+    extra["c0_fb200_s"] = time.perf_counter() - t0
+    extra["c0_fb200_snr_db"] = hist[-1]["snr_db"]
+    del op0
+    # full-size gradient (one FB iteration's operator work), measured
+    opf = OP.Operator(wl.N, uvw, cell=wl.cell_rad, W=wl.W, n_wplanes=wl.n_wplanes)
+    t0 = time.perf_counter()
+    opf.grad(x)
+    t_grad = time.perf_counter() - t0
+    del opf
+    t0 = time.perf_counter()
+    OF.prox_haar_pos(x, 1e-3)
+    t_prox = time.perf_counter() - t0
+    ps = OC.init_params(10, 64, seed=1)
+    zt = synth.sky(256)[None]
+    t0 = time.perf_counter()
+    OC.forward(ps, zt, bf16=False)
+    t_cnn256 = time.perf_counter() - t0
+    t_cnn = t_cnn256 * (wl.N / 256) ** 2
+    extra.update({"full_gradient_s": t_grad, "haar_prox_s": t_prox, "cnn_256_s": t_cnn256,
+                  "fb_iter_s": t_grad + t_prox, "pnp_iter_s_extrapolated": t_grad + t_cnn,
+                  "note": f"fb_iter_s = measured full gradient over all {wl.M:,} visibilities + measured Haar prox "
+                          f"at {wl.N}^2; pnp_iter_s_extrapolated = the same gradient + the CNN timed at 256^2 "
+                          f"scaled by ({wl.N}/256)^2 (extrapolated); 500-iteration runs would take "
+                          f"{500 * (t_grad + t_prox) / 3600:.2f} h (FB) and "
+                          f"{500 * (t_grad + t_cnn) / 3600:.2f} h (PnP), extrapolated"})
+    out["extra"] = extra
+    return out
+
+
+# The paper's own costs (its Table 2 and section on computational cost), as
+# context for the measured numbers: other hardware (the Cirrus cluster's CPUs
+# plus one GPU), real MeerKAT data, MATLAB; not a target.
+PAPER_CONTEXT = {
+    "source": "Dabbech et al. 2022 (arXiv 2207.11336), table of computational costs; Cirrus HPC, CPU and GPU "
+              "models not stated; 4096^2 images, 1.68 arcsec cells",
+    "sparse_matrix_build_cpu_h": {"1053 MHz (~532 M visibilities, 240 CPUs)": 427,
+                                  "1399 MHz (~673 M visibilities, 280 CPUs)": 652},
+    "airi_imaging": {"1053 MHz": "480 CPU h (99 CPUs) + 5 GPU h (1 GPU)",
+                     "1399 MHz": "1028 CPU h (180 CPUs) + 6 GPU h (1 GPU)"},
+    "usara_imaging_cpu_h": {"1053 MHz": 1120, "1399 MHz": 2377},
+    "clean_imaging_cpu_h": {"1053 MHz": 132, "1399 MHz": 236},
+    "derived_airi_wall_h": "about 4.8 h and 5.7 h (CPU hours / CPUs allocated)",
+    "sparse_operator_memory_gb": {"G_p -> H_p, 1053 MHz": "470 -> 81", "1399 MHz": "645 -> 159"},
+}
 
 
 def cnn_flops(n_pixels: int, layers: int = 10, ch: int = 64) -> float:
@@ -166,38 +262,70 @@ def run_usara(args, R, ctx, x_true, target, solve):
     return res
 
 
-def run_pnp(args, R, synth, ctx, noise, x_true, L):
-    """PnP-FB against plain FB on the blocked problem at the denoiser's dynamic
-    range. The visibility noise is set so that the rescaled image-domain noise
-    level tau / (alpha0 sqrt(2L)) equals the training level sigma (eqs. C2-C3,
-    alpha0 = dirty peak / dirty-beam peak); the network is trained at sigma on
-    synthetic patches by the library's own kernels; then plain FB (Haar-l1 +
-    positivity, threshold tau / sqrt(2L)) and PnP-FB (the CNN as D) run the
-    same number of hipGraph-replayed iterations from 0 with FP64 SNR traces."""
-    import numpy as np
+def dirty_peak_ratio(R, ctx, x_true):
+    """alpha0 = max(Re Phi^dagger Phi x) / max(Re Phi^dagger Phi delta), the
+    dirty-image peak over the dirty-beam peak of noiseless data (appendix F)."""
     import torch
-
-    from paper_2207_11336_amd.train import train_denoiser
     N = x_true.shape[0]
-    sigma = args.pnp_sigma
-    y = torch.empty_like(noise)
+    y = torch.empty(ctx.M, dtype=torch.complex64, device=x_true.device)
     R.phi_forward(ctx, x_true, y)
     dirty = torch.empty_like(x_true)
     R.phi_adjoint(ctx, y, dirty)
     delta = torch.zeros_like(x_true)
     delta[N // 2, N // 2] = 1.0
-    yd = torch.empty_like(y)
-    R.phi_forward(ctx, delta, yd)
+    R.phi_forward(ctx, delta, y)
     beam = torch.empty_like(x_true)
-    R.phi_adjoint(ctx, yd, beam)
-    alpha0 = float(dirty.max()) / float(beam.max())
-    tau = sigma * alpha0 * math.sqrt(2.0 * L)
-    y += noise * (tau / math.sqrt(2))
-    del yd, beam, dirty, delta
-    isnr = 20 * math.log10(float(torch.linalg.vector_norm((y - noise * (tau / math.sqrt(2))).to(torch.complex128)))
-                           / (math.sqrt(y.numel()) * tau))
-    log(f"PnP data: alpha0 {alpha0:.4e}, sigma {sigma:.1e} -> tau {tau:.4e} (input SNR {isnr:.1f} dB)")
-    K = args.pnp_iters
+    R.phi_adjoint(ctx, y, beam)
+    return float(dirty.max()) / float(beam.max())
+
+
+def train_pnp_denoiser(args, synth, sigma, device):
+    """The learned denoiser of the PnP runs, trained at sigma by the library's
+    own kernels on the configured training set: 'grf' (C3's database:
+    exponentiated Gaussian random fields plus point sources, dynamic range
+    1e4, 256^2 patches) or 'blobs' (Gaussian sources, 128^2 patches)."""
+    import torch
+
+    from paper_2207_11336_amd.train import train_denoiser
+    side = 256 if args.train_set == "grf" else 128
+    if args.train_patches <= 0:
+        args.train_patches = 20000 if args.train_set == "grf" else 1024
+    t0 = time.perf_counter()
+    if args.train_set == "grf":
+        host = synth.grf_patches(args.train_patches, side)
+    else:
+        host = synth.training_patches(args.train_patches, side)
+    gen_s = time.perf_counter() - t0
+    patches = torch.tensor(host, device=device)
+    del host
+    batch = max(1, args.train_batch * 128 * 128 // (side * side))
+    log(f"training set '{args.train_set}': {args.train_patches} patches of {side}^2 ({gen_s:.1f} s to draw), "
+        f"batch {batch}, {args.train_steps} steps at sigma {sigma:.1e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    params, hist = train_denoiser(patches, sigma, steps=args.train_steps, batch=batch, lr=args.train_lr,
+                                  lr_min=args.train_lr / 100, log_every=max(1, args.train_steps // 4), log=log,
+                                  fne_lambda=args.fne_lambda, fne_iters=4, fne_every=args.fne_every,
+                                  fne_point=args.fne_point)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del patches
+    torch.cuda.empty_cache()
+    info = {"train_set": args.train_set, "train_patches": args.train_patches, "patch_side": side,
+            "train_steps": args.train_steps, "train_batch": batch, "train_s": train_s, "draw_s": gen_s,
+            "train_tflops": 3 * cnn_flops(args.train_steps * batch * side * side) / train_s / 1e12,
+            "train_final_loss": hist[-1][1] if hist else None, "fne_lambda": args.fne_lambda,
+            "fne_point": ["noisy input", "clean/denoised mix"][args.fne_point], "sigma_train": sigma}
+    return params, info, side
+
+
+def run_pnp_leg(args, R, ctx, y, tau, x_true, L, K, with_usara):
+    """Plain FB (Haar-l1 + positivity, threshold tau / sqrt(2L)) and PnP-FB
+    (the loaded CNN as D, alpha from eqs. C2-C3 by the library) on the same
+    data, K hipGraph-replayed iterations each from 0, FP64 SNR traces; the
+    target is FB's final SNR - 0.5 dB."""
+    import numpy as np
+    import torch
 
     def solve(kind, sig_train, reweight_every=0):
         trace = np.zeros((K, 4))
@@ -209,19 +337,55 @@ def run_pnp(args, R, synth, ctx, noise, x_true, L):
         solve.x = xs
         return rep, trace
 
+    marks = (10, 50, 100, 200, 300, 500, 1000)
     fb_rep, fb_tr = solve(R.RI_PROX_HAAR, 0.0)
-    log(f"FB x{fb_rep.iters} at sigma {sigma:.0e}: {fb_rep.ms:.1f} ms, SNR {fb_rep.snr_db:.2f} dB")
-    usara = None if args.no_usara else run_usara(args, R, ctx, x_true, fb_rep.snr_db - 0.5, solve)
-    patches = torch.tensor(synth.training_patches(args.train_patches, 128), device=x_true.device)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    params, hist = train_denoiser(patches, sigma, steps=args.train_steps, batch=args.train_batch, lr=args.train_lr,
-                                  lr_min=args.train_lr / 100, log_every=max(1, args.train_steps // 4), log=log,
-                                  fne_lambda=args.fne_lambda, fne_iters=4, fne_every=args.fne_every)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    del patches
-    train_flops = 3 * cnn_flops(args.train_steps * args.train_batch * 128 * 128)
+    target = fb_rep.snr_db - 0.5
+    usara = run_usara(args, R, ctx, x_true, target, solve) if with_usara else None
+    try:
+        rep, tr = solve(R.RI_PROX_CNN, args.pnp_sigma)
+    except R.RIError as e:
+        log(f"PnP solve failed: {e}")
+        return {"error": str(e), "fb_final_snr_db": fb_rep.snr_db}, None
+    hit = np.nonzero(tr[:rep.iters, 2] >= target)[0]
+    fb_hit = np.nonzero(fb_tr[:fb_rep.iters, 2] >= target)[0]
+    res = {"iters": rep.iters, "alpha": rep.alpha, "sigma_rescaled": tau / (rep.alpha * math.sqrt(2 * L)),
+           "fb_ms": fb_rep.ms, "fb_final_snr_db": fb_rep.snr_db, "pnp_ms": rep.ms, "pnp_final_snr_db": rep.snr_db,
+           "pnp_ms_per_iter": rep.ms / max(1, rep.iters), "fb_ms_per_iter": fb_rep.ms / max(1, fb_rep.iters),
+           "fell_back": rep.fell_back, "target_snr_db": target,
+           "pnp_ms_to_target": float(tr[hit[0], 3]) if hit.size else None,
+           "fb_ms_to_target": float(fb_tr[fb_hit[0], 3]) if fb_hit.size else None,
+           "pnp_its_to_target": int(hit[0]) + 1 if hit.size else None,
+           "fb_residual2": fb_rep.final_residual2, "pnp_residual2": rep.final_residual2,
+           "pnp_snr_at": {str(k): round(float(tr[k - 1, 2]), 3) for k in marks if k <= rep.iters},
+           "fb_snr_at": {str(k): round(float(fb_tr[k - 1, 2]), 3) for k in marks if k <= fb_rep.iters},
+           "usara": usara}
+    log(f"PnP x{rep.iters}: {rep.ms:.1f} ms ({res['pnp_ms_per_iter']:.3f} ms/it), SNR {rep.snr_db:.2f} dB vs FB "
+        f"{fb_rep.snr_db:.2f} dB; residual^2 {rep.final_residual2:.4e} vs {fb_rep.final_residual2:.4e}; to "
+        f"{target:.2f} dB: PnP {res['pnp_ms_to_target']} ms vs FB {res['fb_ms_to_target']} ms; fell back "
+        f"{rep.fell_back}")
+    log(f"SNR trace FB {res['fb_snr_at']}  PnP {res['pnp_snr_at']}")
+    return res, solve.x / rep.alpha
+
+
+def run_pnp(args, R, synth, ctx, noise, x_true, L, tau40):
+    """PnP-FB against plain FB on the blocked problem (C2's 64 blocks), one
+    network trained once at sigma_train = args.pnp_sigma (dynamic range 1e4)
+    on the configured training set, two data configurations:
+      * 'C3-40dB' (the workload as specified): C1's data at 40 dB input SNR;
+        alpha = max(dirty peak / beta, tau / (sigma_train sqrt(2L))) (eqs.
+        C2-C3, appendix F); the rescaled noise level tau / (alpha sqrt(2L)) then
+        lies far below sigma_train, i.e. the network regularises more than the
+        data need;
+      * 'C3-renoised-sigma1e-4': the visibility noise raised until the
+        rescaled noise level equals sigma_train (tau = sigma alpha0 sqrt(2L)),
+        the data the network is matched to (input SNR about -13 dB per
+        visibility); uSARA runs on these data too."""
+    import torch
+    N = x_true.shape[0]
+    sigma = args.pnp_sigma
+    K = args.pnp_iters
+    alpha0 = dirty_peak_ratio(R, ctx, x_true)
+    params, train_info, side = train_pnp_denoiser(args, synth, sigma, x_true.device)
     R.ri_load_denoiser(ctx, params, 10)
     # denoiser throughput on the whole image (facets as configured)
     z = x_true.clone()
@@ -236,59 +400,55 @@ def run_pnp(args, R, synth, ctx, noise, x_true, L):
     den_ms = e0.elapsed_time(e1) / 5
     core = args.facet_core if 0 < args.facet_core < N else N
     halo = args.facet_halo if 0 < args.facet_core < N else 0
-    side = (core + 2 * halo + 15) // 16 * 16
+    tside = (core + 2 * halo + 15) // 16 * 16
     nf = ((N + core - 1) // core) ** 2
-    den_tfs = cnn_flops(nf * side * side) / (den_ms * 1e-3) / 1e12
-    log(f"denoiser: {den_ms:.3f} ms per application ({nf} tile(s) of {side}^2), {den_tfs:.1f} TFLOP/s")
-    try:
-        rep, tr = solve(R.RI_PROX_CNN, sigma)
-    except R.RIError as e:
-        log(f"PnP solve failed: {e}")
-        return {"error": str(e), "sigma": sigma, "train_s": train_s}
+    den_tfs = cnn_flops(nf * tside * tside) / (den_ms * 1e-3) / 1e12
+    log(f"denoiser: {den_ms:.3f} ms per application ({nf} tile(s) of {tside}^2), {den_tfs:.1f} TFLOP/s")
+    legs = {}
+    fixed = {}
+    y0 = torch.empty_like(noise)
+    R.phi_forward(ctx, x_true, y0)
+    norm_y0 = float(torch.linalg.vector_norm(y0.to(torch.complex128)))
+    for name, tau, with_usara in (("C3-40dB", tau40, False),
+                                  ("C3-renoised-sigma1e-4", sigma * alpha0 * math.sqrt(2.0 * L), not args.no_usara)):
+        y = y0 + noise * (tau / math.sqrt(2))
+        isnr = 20 * math.log10(norm_y0 / (math.sqrt(y.numel()) * tau))
+        log(f"[{name}] tau {tau:.4e} (input SNR {isnr:.1f} dB), alpha0 {alpha0:.4e}, image-domain noise "
+            f"tau/sqrt(2L) {tau / math.sqrt(2 * L):.3e}")
+        res, xfix = run_pnp_leg(args, R, ctx, y, tau, x_true, L, K, with_usara)
+        res.update({"tau": tau, "input_snr_db": isnr, "alpha0": alpha0})
+        legs[name] = res
+        if xfix is not None:
+            fixed[name] = xfix
+        del y
+    del y0
     # firm nonexpansiveness of the trained network (appendix C), measured:
-    # ||J_{2D - I}||_S on noisy held-out patches and at the PnP fixed point
-    # (the final iterate in the network's scaled domain, x / alpha)
-    fnet = R.ri_cnn_create(layers=10, max_batch=4, max_h=128, max_w=128, training=True)
+    # ||J_{2D - I}||_S on noisy held-out patches and at each leg's PnP fixed
+    # point (the final iterate in the network's scaled domain, x / alpha)
+    fnet = R.ri_cnn_create(layers=10, max_batch=4, max_h=side, max_w=side, training=True)
     R.ri_cnn_set_params(fnet, params)
-    held = torch.tensor(synth.training_patches(4, 128, seed=97), device=x_true.device)
+    if args.train_set == "grf":
+        held = torch.tensor(synth.grf_patches(4, side, seed=97), device=x_true.device)
+    else:
+        held = torch.tensor(synth.training_patches(4, side, seed=97), device=x_true.device)
     held = (held + sigma * torch.randn(held.shape, device=held.device, generator=torch.Generator(
         device=held.device).manual_seed(11))).contiguous()
     fne_patches = R.ri_cnn_fne_norm(fnet, held, iters=30, seed=5)
     fnet.close()
     fnet = R.ri_cnn_create(layers=10, max_batch=1, max_h=N, max_w=N, training=True)
     R.ri_cnn_set_params(fnet, params)
-    fne_fixed = R.ri_cnn_fne_norm(fnet, (solve.x / rep.alpha)[None].contiguous(), iters=30, seed=5)
+    fne_fixed = {k: R.ri_cnn_fne_norm(fnet, v[None].contiguous(), iters=30, seed=5) for k, v in fixed.items()}
     fnet.close()
     torch.cuda.empty_cache()
-    log(f"||J_(2D-I)||_S of the trained network: {fne_patches:.3f} on noisy held-out patches, "
-        f"{fne_fixed:.3f} at the PnP fixed point (FNE needs <= 1)")
-    target = fb_rep.snr_db - 0.5
-    hit = np.nonzero(tr[:rep.iters, 2] >= target)[0]
-    fb_hit = np.nonzero(fb_tr[:fb_rep.iters, 2] >= target)[0]
-    marks = (10, 50, 100, 200, 300, 500, 1000)
-    res = {"sigma": sigma, "tau": tau, "input_snr_db": isnr, "alpha": rep.alpha, "iters": rep.iters,
-           "fb_ms": fb_rep.ms, "fb_final_snr_db": fb_rep.snr_db, "pnp_ms": rep.ms, "pnp_final_snr_db": rep.snr_db,
-           "pnp_ms_per_iter": rep.ms / max(1, rep.iters), "fb_ms_per_iter": fb_rep.ms / max(1, fb_rep.iters),
-           "fell_back": rep.fell_back, "target_snr_db": target,
-           "pnp_ms_to_target": float(tr[hit[0], 3]) if hit.size else None,
-           "fb_ms_to_target": float(fb_tr[fb_hit[0], 3]) if fb_hit.size else None,
-           "pnp_its_to_target": int(hit[0]) + 1 if hit.size else None,
-           "fb_residual2": fb_rep.final_residual2, "pnp_residual2": rep.final_residual2,
-           "pnp_snr_at": {str(k): round(float(tr[k - 1, 2]), 3) for k in marks if k <= rep.iters},
-           "fb_snr_at": {str(k): round(float(fb_tr[k - 1, 2]), 3) for k in marks if k <= fb_rep.iters},
-           "denoiser_ms": den_ms, "denoiser_tflops": den_tfs, "denoiser_tiles": nf, "denoiser_tile_side": side,
-           "denoiser_roofline": {"bound": "mfma", "achieved": den_tfs, "peak": BF16_PEAK_TFS, "unit": "TFLOP/s",
-                                 "frac": den_tfs / BF16_PEAK_TFS, "flops_per_application": cnn_flops(nf * side * side),
-                                 "kernels": "k_conv_in, 7 x k_conv64<0>, k_conv64<2>, k_conv_sum (one application)"},
-           "fne_norm_patches": fne_patches, "fne_norm_fixed_point": fne_fixed, "fne_lambda": args.fne_lambda,
-           "train_steps": args.train_steps, "train_batch": args.train_batch, "train_s": train_s,
-           "train_tflops": train_flops / train_s / 1e12, "train_final_loss": hist[-1][1] if hist else None,
-           "usara": usara}
-    log(f"PnP x{rep.iters}: {rep.ms:.1f} ms ({res['pnp_ms_per_iter']:.3f} ms/it), SNR {rep.snr_db:.2f} dB vs FB "
-        f"{fb_rep.snr_db:.2f} dB; to {target:.2f} dB: PnP {res['pnp_ms_to_target']} ms vs FB "
-        f"{res['fb_ms_to_target']} ms; fell back {rep.fell_back}")
-    log(f"SNR trace FB {res['fb_snr_at']}  PnP {res['pnp_snr_at']}")
-    return res
+    log(f"||J_(2D-I)||_S of the trained network: {fne_patches:.3f} on noisy held-out patches, at the PnP fixed "
+        f"points {({k: round(v, 3) for k, v in fne_fixed.items()})} (FNE needs <= 1)")
+    return {"sigma_train": sigma, "iters": K, "legs": legs, **train_info,
+            "denoiser_ms": den_ms, "denoiser_tflops": den_tfs, "denoiser_tiles": nf, "denoiser_tile_side": tside,
+            "denoiser_roofline": {"bound": "mfma", "achieved": den_tfs, "peak": BF16_PEAK_TFS, "unit": "TFLOP/s",
+                                  "frac": den_tfs / BF16_PEAK_TFS,
+                                  "flops_per_application": cnn_flops(nf * tside * tside),
+                                  "kernels": "k_conv_in, 7 x k_conv64<0>, k_conv64<2>, k_conv_sum (one application)"},
+            "fne_norm_patches": fne_patches, "fne_norm_fixed_point": fne_fixed}
 
 
 def run_holo(args, R, wl, uvw, x_true, L=None, tau=None):
@@ -380,7 +540,11 @@ def main():
                     help="skip building the holographic matrix H = G^H G and timing Phi^dagger Phi through it")
     ap.add_argument("--holo-only", action="store_true", help="only the holographic measurement")
     ap.add_argument("--cpu-sample", type=int, default=8_000_000,
-                    help="visibilities of the CPU oracle baseline (three timed runs, about 15 s on 16 cores)")
+                    help="visibilities of the CPU oracle baseline (warm-up + five timed runs, about 20 s on 16 cores)")
+    ap.add_argument("--cpu-single", type=int, default=1_000_000,
+                    help="visibilities of the CPU oracle's single-thread run")
+    ap.add_argument("--cpu-no-extra", action="store_true",
+                    help="skip the oracle's C0 FB x200, full-size gradient and CNN timings")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the FB time-to-SNR run")
     ap.add_argument("--fb-iters", type=int, default=300)
@@ -390,11 +554,19 @@ def main():
     ap.add_argument("--train-lr", type=float, default=2e-4)
     ap.add_argument("--pnp-sigma", type=float, default=1e-4,
                     help="image-domain noise level of the PnP comparison (1 / target dynamic range)")
-    ap.add_argument("--train-batch", type=int, default=16)
-    ap.add_argument("--train-patches", type=int, default=1024)
+    ap.add_argument("--train-batch", type=int, default=16,
+                    help="patches per training step at 128^2 (scaled down for larger patches: 4 at 256^2)")
+    ap.add_argument("--train-set", default="blobs", choices=["grf", "blobs"],
+                    help="denoiser training images: Gaussian-source patches of 128^2 (default) or exponentiated "
+                         "Gaussian random fields of 256^2 (the configured database)")
+    ap.add_argument("--train-patches", type=int, default=0,
+                    help="training patches (0: 1,024 for blobs, 20,000 for grf)")
     ap.add_argument("--fne-lambda", type=float, default=1e-6,
                     help="weight of the relaxed firm-nonexpansiveness penalty in the denoiser training (0: off)")
     ap.add_argument("--fne-every", type=int, default=4, help="penalised training step every this many steps")
+    ap.add_argument("--fne-point", type=int, default=0, choices=[0, 1],
+                    help="where the penalty takes the Jacobian: 0 the noisy training input, 1 random points between "
+                         "the clean and the denoised images")
     ap.add_argument("--facet-core", type=int, default=None,
                     help="CNN facet core side (0: whole image in one tile; default: the workload's)")
     ap.add_argument("--facet-halo", type=int, default=None)
@@ -567,20 +739,28 @@ def main():
     results = {m: run_mode(m) for m in modes}
     best = max(results.values(), key=lambda r: r["rate"])
     value, ms_step = best["rate"], best["ms_step"]
-    if best["mode"] == "csr":
-        bytes_launch = csr_tile_bytes(best["nnz"], M, wl.Np)
-        achieved = bytes_launch / (best["tile_ms"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("csr", best["tile"]),
-                "kernel": "k_tiles<float, fused, csr>",
-                "bytes_per_launch": bytes_launch, "avg_launch_ms": best["tile_ms"]}
-    else:
-        flops = otf_tile_flops(best["nnz"], M)
-        achieved = flops / (best["tile_ms"] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_VALU_PEAK_TFS, "traffic": measured_traffic("otf", best["tile"]),
-                "kernel": "k_tiles<float, fused, otf>",
-                "flops_per_launch": flops, "avg_launch_ms": best["tile_ms"]}
+
+    def roofline(r):
+        """The fused tile kernel of one G mode against its bound. Stored G is
+        HBM-bound (algorithmic bytes of csr_tile_bytes); on the fly it is bound
+        by its FP32 arithmetic (otf_tile_flops), and its HBM rate (24 B per
+        visibility plus one grid read and one grid write) is given beside."""
+        if r["mode"] == "csr":
+            b = csr_tile_bytes(r["nnz"], M, wl.Np)
+            ach = b / (r["tile_ms"] * 1e-3) / 1e9
+            return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("csr", r["tile"]),
+                    "kernel": "k_tiles<float, fused, csr>", "bytes_per_launch": b, "avg_launch_ms": r["tile_ms"]}
+        fl = otf_tile_flops(r["nnz"], M)
+        ach = fl / (r["tile_ms"] * 1e-3) / 1e12
+        hb = 24.0 * M + 16.0 * wl.Np * wl.Np
+        return {"bound": "alu", "achieved": ach, "peak": FP32_VALU_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": ach / FP32_VALU_PEAK_TFS, "traffic": measured_traffic("otf", r["tile"]),
+                "kernel": "k_tiles<float, fused, otf>", "flops_per_launch": fl, "avg_launch_ms": r["tile_ms"],
+                "hbm_bytes_per_launch": hb, "hbm_frac": hb / (r["tile_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+    roof = roofline(best)
+    roof_other = {m: roofline(r) for m, r in results.items() if r is not best}
     extra = {f"{m}_fb_step_vis_per_s": r["rate"] for m, r in results.items()}
     extra.update({f"{m}_tile_ms": r["tile_ms"] for m, r in results.items()})
     extra.update({f"{m}_tile": r["tile"] for m, r in results.items()})
@@ -617,7 +797,7 @@ def main():
         log(f"FB x{K} on {st_b.n_blocks} blocks (graph): {rep.ms:.1f} ms, {rep.ms / max(1, rep.iters):.3f} ms/it, "
             f"SNR {rep.snr_db:.2f} dB")
         if not args.no_pnp:
-            pnp = run_pnp(args, R, synth, ctxb, noise[torch.as_tensor(perm, device=dev)], x_true, L)
+            pnp = run_pnp(args, R, synth, ctxb, noise[torch.as_tensor(perm, device=dev)], x_true, L, shared["tau"])
         ctxb.close()
         del yb
         torch.cuda.empty_cache()
@@ -627,8 +807,9 @@ def main():
     cpu = None
     if not args.no_cpu:
         log(f"CPU oracle baseline on {args.cpu_sample:,} visibilities ...")
-        cpu = cpu_baseline(wl, uvw, args.cpu_sample)
-        log(f"CPU oracle: {cpu['value']:.4e} vis/s on {cpu['cores']} threads")
+        cpu = cpu_baseline(wl, uvw, args.cpu_sample, args.cpu_single, with_extra=not args.cpu_no_extra)
+        log(f"CPU oracle: {cpu['value']:.4e} vis/s on {cpu['cores']} threads ({cpu['cpu_model']}); 1 thread "
+            f"{cpu['single_thread']['value']:.4e} vis/s; extra {cpu.get('extra')}")
 
     out = {
         "metric": METRIC, "value": value, "unit": "visibilities/s", "n_gpus": 1, "steps": args.steps,
@@ -637,10 +818,12 @@ def main():
         "config": {"workload": wl.name, "N": N, "grid": wl.Np, "M": M, "g_mode": best["mode"], "nnz": st_nnz,
                    "w_stacks": max(args.wstacks, 1),
                    "tile": best["tile"], "step": "fb_step: fused gradient + Haar-l1 prox + FP64 norms",
+                   "roofline_other_modes": roof_other,
                    "fp64_gram_vis_per_s": fp64_rate, "plan_s": plan_s, "L": L, "snr_db": snr, **extra,
                    "fb_time_to_snr": fb_trace, "pnp": pnp, "holographic": holo},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "paper_context": PAPER_CONTEXT,
     }
     print(json.dumps(out), flush=True)
 

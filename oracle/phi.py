@@ -64,6 +64,8 @@ def lib() -> ctypes.CDLL:
         L.or_dft_c.argtypes = [i, i64, p, d, i, p, p]
         L.or_dft_adj_c.argtypes = [i, i64, p, d, i, p, p]
         L.or_num_threads.restype = i
+        L.or_set_num_threads.argtypes = [i]
+        L.or_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -74,6 +76,10 @@ def _ptr(a: np.ndarray):
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().or_set_num_threads(int(n))
 
 
 # ----------------------------------------------------------------------------

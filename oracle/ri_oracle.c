@@ -403,3 +403,16 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the following parallel regions, for timing: every sum above is
+ * taken in the same order whatever the thread count (per visibility, per FFT
+ * row or column, and per grid cell in visibility order), so results do not
+ * depend on it. */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

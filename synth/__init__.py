@@ -200,6 +200,59 @@ def training_patches(n: int, size: int, seed: int = SEED_TRAIN) -> np.ndarray:
     return out
 
 
+def _grf_chunk(seed_seq, count: int, size: int, log_k: np.ndarray, dynamic_range: float) -> np.ndarray:
+    rng = np.random.default_rng(seed_seq)
+    beta = rng.uniform(2.0, 4.0, size=(count, 1, 1)).astype(np.float32)
+    amp = np.exp(-0.5 * beta * log_k)              # |spectrum| = k^(-beta/2): power ~ k^-beta
+    amp[:, 0, 0] = 0.0
+    shape = (count, size, size // 2 + 1)
+    spec = rng.standard_normal(shape, dtype=np.float32) * amp \
+        + 1j * (rng.standard_normal(shape, dtype=np.float32) * amp)
+    g = np.fft.irfft2(spec, s=(size, size), axes=(1, 2))
+    lo = g.min(axis=(1, 2), keepdims=True)
+    hi = g.max(axis=(1, 2), keepdims=True)
+    g = (g - lo) / (hi - lo)                       # rescaled to [0, 1]
+    u = np.expm1(g * np.float32(math.log(dynamic_range))) / np.float32(dynamic_range - 1.0)
+    for i in range(count):
+        npt = int(rng.integers(0, 21))
+        ys, xs = rng.integers(0, size, npt), rng.integers(0, size, npt)
+        np.add.at(u[i], (ys, xs), (10.0 ** rng.uniform(-4.0, 0.0, npt)).astype(np.float32))
+    u /= u.max(axis=(1, 2), keepdims=True)
+    return u.astype(np.float32)
+
+
+def grf_patches(n: int, size: int, seed: int = SEED_TRAIN, dynamic_range: float = 1e4,
+                workers: int | None = None) -> np.ndarray:
+    """High-dynamic-range training images, float32 [n, size, size], positive,
+    peak 1 (the normalised database of the learned denoiser's training).
+
+    Per patch: a Gaussian random field g with power spectrum ~ k^-beta,
+    beta ~ U[2, 4], rescaled to [0, 1], exponentiated as
+    u = (D^g - 1) / (D - 1) with D the dynamic range (1e4), plus 0..20 point
+    sources (uniform integer positions, peaks 10^U[-4, 0]); the patch is then
+    divided by its peak. Chunks of 250 patches draw from independent child
+    seeds of ``seed`` (numpy SeedSequence.spawn), so the result does not
+    depend on ``workers`` (threads; default min(16, cpu count))."""
+    from concurrent.futures import ThreadPoolExecutor
+    import os
+    ky = np.fft.fftfreq(size)[:, None]
+    kx = np.fft.rfftfreq(size)[None, :]
+    k = np.hypot(ky, kx)
+    k[0, 0] = 1.0
+    log_k = np.log(k).astype(np.float32)
+    chunk = 250
+    starts = list(range(0, n, chunk))
+    seqs = np.random.SeedSequence(seed).spawn(len(starts))
+    out = np.empty((n, size, size), dtype=np.float32)
+    nw = workers or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max(1, nw)) as ex:
+        jobs = ex.map(lambda a: _grf_chunk(a[1], min(chunk, n - a[0]), size, log_k, dynamic_range),
+                      zip(starts, seqs))
+        for s0, u in zip(starts, jobs):
+            out[s0:s0 + u.shape[0]] = u
+    return out
+
+
 # ----------------------------------------------------------------------------
 # Array geometry and earth-rotation synthesis (Thompson-Moran-Swenson)
 # ----------------------------------------------------------------------------

@@ -73,6 +73,18 @@ __device__ __forceinline__ T kb_weight(T t, const TileArgs<T> &a) {
     return p;
 }
 
+// kappa(t) for |t| <= 7/2 (the window's taps): no branch, z clamped at 0.
+template <typename T>
+__device__ __forceinline__ T kb_weight_in(T t, const TileArgs<T> &a) {
+    const T u = t * (T)(2.0 / 7.0);
+    const T z = fmax((T)1 - u * u, (T)0);
+    constexpr int K = sizeof(T) == 4 ? 22 : 32;
+    T p = a.kbc[K - 1];
+#pragma unroll
+    for (int k = K - 2; k >= 0; --k) p = p * z + a.kbc[k];
+    return p;
+}
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -198,9 +210,18 @@ k_tiles(TileArgs<T> a) {
         }
         __syncthreads();
 
+        // the group's next record (and on the fly its fraction: lane l < 8 the
+        // u one, 8.. the v one) is loaded one visibility ahead
+        uint2 rec_n = make_uint2(0u, 0u);
+        T f_n = (T)0;
+        if (grp < item.vc) {
+            rec_n = a.rec[item.vb + grp];
+            if (OTF) f_n = a.frac[2 * (size_t)(item.vb + grp) + (lane >> 3)];
+        }
         for (int vi = grp; vi < item.vc; vi += GROUPS) {
             const int m = item.vb + vi;
-            const uint2 rec = a.rec[m];
+            const uint2 rec = rec_n;
+            const T f = f_n;
             const int cu = (int)(rec.x & 0xFFFFu), cv = (int)(rec.x >> 16);
             const int pl = (int)(rec.y & 0xFFFFu), h = (int)((rec.y >> 16) & 0xFu);
             const int S = 2 * h + 7, SS = S * S;
@@ -219,11 +240,18 @@ k_tiles(TileArgs<T> a) {
                 // row weight g_v[ay] is broadcast from lane ay. For S = 17,
                 // column 16 is taken row-wise (lane l: row l) and the corner
                 // (16, 16) by lane 0, which keeps the 16 lanes balanced.
-                const T fu = a.frac[2 * (size_t)m], fv = a.frac[2 * (size_t)m + 1];
-                T kbr = (T)0;
-                if (lane < 7) kbr = kb_weight<T>(fu - (T)(lane - 3), a);
-                else if (lane >= 8 && lane < 15) kbr = kb_weight<T>(fv - (T)(lane - 11), a);
+                // the plane's w-taps first, then the next visibility's record and
+                // fraction (loads complete in order, so waiting for the taps
+                // leaves the prefetch in flight)
                 if (lane <= 2 * h) wk[lane] = a.wtaps[(size_t)pl * (2 * a.hmax + 1) + a.hmax - h + lane];
+                if (vi + GROUPS < item.vc) {
+                    rec_n = a.rec[m + GROUPS];
+                    f_n = a.frac[2 * (size_t)(m + GROUPS) + (lane >> 3)];
+                }
+                // one Horner series for all 14 taps (lanes 7 and 15 compute an
+                // unused value): lane j < 8 evaluates kappa(f_u - (j - 3)),
+                // lane 8 + j kappa(f_v - (j - 3))
+                const T kbr = (lane & 7) < 7 ? kb_weight_in<T>(f - (T)((lane & 7) - 3), a) : (T)0;
                 wave_sync();
                 cx<T> gu = mk<T>((T)0, (T)0), gv = gu, gu16 = gu, gv16 = gu;
                 static_for<7>([&](auto J) {
@@ -310,6 +338,7 @@ k_tiles(TileArgs<T> a) {
                 // window); its columns follow from the window. The window cell
                 // (ay, ax) of entry t advances by 16 entries per slot without a
                 // division: 16 = q16 S + (16 - q16 S), q16 = floor(16 / S).
+                if (vi + GROUPS < item.vc) rec_n = a.rec[m + GROUPS];
                 const cx<T> *gp = a.gval + a.rowptr[m];
                 cx<T> wv[MAXI];
 #pragma unroll

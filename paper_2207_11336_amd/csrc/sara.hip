@@ -77,13 +77,17 @@ __device__ __forceinline__ void finalise(T *dst9, const T *w9, size_t i9, T val,
 
 // Column passes are register-blocked: a thread computes KB consecutive outputs
 // of one column from one window of inputs held in registers (2 KB + L - 2
-// inputs for analysis, KB + L/2 - 1 of each half for synthesis). Row passes
+// inputs for analysis, KB + L/2 - 1 of each half for synthesis); KB is 8 on
+// the finest level and smaller on the coarse ones, whose few columns would
+// otherwise leave most of the device idle (col_block below). Row passes
 // stage the row in LDS by coalesced loads; the analysis computes one output
 // per lane per step, the synthesis 8 consecutive outputs per lane from
 // 16-byte LDS windows (k_syn_rows, k_syn_final). The
 // filter length L is a template parameter (one instantiation per basis, chosen
 // from blockIdx.z).
-constexpr int KB = 8;
+// Column block of level side n: 8 outputs per thread at the finest levels, 4
+// at n = 1024, 2 below (more workgroups for the small coarse levels).
+inline int col_block(int n) { return n >= 2048 ? 8 : (n >= 1024 ? 4 : 2); }
 
 // f(std::integral_constant<int, L>) for the filter length L = 2 (b + 1) of basis b.
 template <typename F>
@@ -132,7 +136,7 @@ __global__ void __launch_bounds__(256) k_ana_rows(const T *__restrict__ in, int6
 // Column analysis: tmp -> low-low block into work (unless last) and every
 // other coefficient finalised into dst9 (slot b + 1). Thread: column col,
 // outputs k0 .. k0 + KB - 1 of both halves.
-template <typename T, int FIN>
+template <typename T, int FIN, int KB>
 __global__ void __launch_bounds__(256) k_ana_cols(const T *__restrict__ tmp, T *__restrict__ work, T *dst9,
                                                   const T *__restrict__ w9, int N, int n, int last, T scale, T par) {
     const int b = blockIdx.z;
@@ -174,7 +178,7 @@ __global__ void k_ana_dirac(const T *__restrict__ x, T *dst9, int64_t n, T scale
 // Synthesis of 2 KB consecutive outputs i0 .. i0 + 2 KB - 1 (i0 even) along one
 // axis from the low half A and the high half D (element k at A[k * stride]):
 // x[i] = sum_{t = i mod 2} h[t] A[k] + g[t] D[k], k = (i - t)/2 mod half.
-template <typename T, int L>
+template <typename T, int L, int KB>
 __device__ __forceinline__ void syn_block(int b, const T *A, const T *D, size_t stride, int i0, int half, T *x) {
     constexpr int S2 = L / 2, NA = KB + S2 - 1;
     const int kb0 = (i0 >> 1) - S2 + 1, hm = half - 1;
@@ -203,7 +207,7 @@ __device__ __forceinline__ void syn_block(int b, const T *A, const T *D, size_t 
 // Column synthesis of level block n: the coarse block (rows and columns < n/2)
 // from work (or from the coefficients at the coarsest level), the rest from
 // the coefficients v9 (slot b + 1) -> tmp. Thread: column col, rows i0 .. i0 + 2 KB - 1.
-template <typename T>
+template <typename T, int KB>
 __global__ void __launch_bounds__(256) k_syn_cols(const T *__restrict__ v9, const T *__restrict__ work,
                                                   T *__restrict__ tmp, int N, int n, int coarsest) {
     const int b = blockIdx.z;
@@ -214,7 +218,9 @@ __global__ void __launch_bounds__(256) k_syn_cols(const T *__restrict__ v9, cons
     const T *cf = v9 + (size_t)(b + 1) * NN + col;
     const T *lo = (!coarsest && col < half) ? work + b * NN + col : cf;
     T x[2 * KB];
-    with_length(b, [&](auto Lc) { syn_block<T, decltype(Lc)::value>(b, lo, cf + (size_t)half * N, N, i0, half, x); });
+    with_length(b, [&](auto Lc) {
+        syn_block<T, decltype(Lc)::value, KB>(b, lo, cf + (size_t)half * N, N, i0, half, x);
+    });
     T *dst = tmp + b * NN + col;
 #pragma unroll
     for (int u = 0; u < 2 * KB; ++u)
@@ -516,8 +522,17 @@ void analysis(ri_ctx *c, const T *x, T *dst9, T par, bool dirac, hipStream_t s) 
         const T *in = l == 0 ? x : work;
         const int64_t in_bs = l == 0 ? 0 : (int64_t)N * N;
         hipLaunchKernelGGL(k_ana_rows<T>, dim3(1, n, NW), dim3(256), sizeof(T) * n, s, in, in_bs, tmp, N, n);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ana_cols<T, FIN>), dim3(cdiv(n, 64), cdiv(n / 2, 4 * KB), NW),
-                           dim3(256), 0, s, tmp, work, dst9, w9, N, n, l == LEVELS - 1 ? 1 : 0, scale, par);
+        const int kb = col_block(n), last = l == LEVELS - 1 ? 1 : 0;
+        const dim3 g(cdiv(n, 64), cdiv(n / 2, 4 * kb), NW);
+        if (kb == 8)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ana_cols<T, FIN, 8>), g, dim3(256), 0, s, tmp, work, dst9, w9, N, n,
+                               last, scale, par);
+        else if (kb == 4)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ana_cols<T, FIN, 4>), g, dim3(256), 0, s, tmp, work, dst9, w9, N, n,
+                               last, scale, par);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ana_cols<T, FIN, 2>), g, dim3(256), 0, s, tmp, work, dst9, w9, N, n,
+                               last, scale, par);
     }
 }
 
@@ -530,8 +545,14 @@ void synthesis(ri_ctx *c, T *v9, const T *z, T *x, T thr, hipStream_t s) {
     T *work = (T *)st.work, *tmp = (T *)st.tmp;
     for (int l = LEVELS - 1; l >= 0; --l) {
         const int n = N >> l;
-        hipLaunchKernelGGL(k_syn_cols<T>, dim3(cdiv(n, 64), cdiv(n, 4 * 2 * KB), NW), dim3(256), 0, s, v9, work, tmp,
-                           N, n, l == LEVELS - 1 ? 1 : 0);
+        const int kb = col_block(n), coarsest = l == LEVELS - 1 ? 1 : 0;
+        const dim3 g(cdiv(n, 64), cdiv(n, 4 * 2 * kb), NW);
+        if (kb == 8)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_syn_cols<T, 8>), g, dim3(256), 0, s, v9, work, tmp, N, n, coarsest);
+        else if (kb == 4)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_syn_cols<T, 4>), g, dim3(256), 0, s, v9, work, tmp, N, n, coarsest);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_syn_cols<T, 2>), g, dim3(256), 0, s, v9, work, tmp, N, n, coarsest);
         if (l > 0 && n >= 8)
             hipLaunchKernelGGL(k_syn_rows<T>, dim3(1, n, NW), dim3(std::max(64, n / 8)), sizeof(T) * (n + 2 * RH), s,
                                tmp, work, N, n);

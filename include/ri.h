@@ -54,7 +54,7 @@ typedef enum {
     RI_FELLBACK = 1       /* pnp_solve detected divergence and finished with the Haar prox */
 } ri_status;
 
-enum { RI_G_CSR = 0, RI_G_OTF = 1 };
+enum { RI_G_CSR = 0, RI_G_OTF = 1, RI_G_SEP = 2 };
 enum { RI_PROX_HAAR = 0, RI_PROX_CNN = 1, RI_PROX_SARA = 2 };
 
 /* Plan description. All sizes explicit; nothing is read through globals. */
@@ -69,7 +69,10 @@ typedef struct {
     int32_t g_mode;        /* RI_G_CSR: G stored row by row: the complex values of each row's
                               window in window order, int64 row pointers; the columns follow
                               from the window and are not stored;
-                              RI_G_OTF: G rows computed on the fly from the KB and w-tables */
+                              RI_G_OTF: G rows computed on the fly from the KB and w-tables;
+                              RI_G_SEP: each row stored as its two axis factors (a row is
+                              g_v[ay] g_u[ax] on its window): 17 (g_u, g_v) pairs per
+                              visibility, 34 complex values, computed once in FP64 */
     int32_t precision;     /* 32 or 64: element type of Phi, Phi^dagger and the FFT */
     int32_t tile;          /* uv tile side in grid cells (8..128, divides N'); 0 => autotuned at
                               ri_create among 8, 16, 32 by timing fused gradient passes */
@@ -93,8 +96,9 @@ typedef struct {
  * grid cell and fraction in FP64 (p = omega N'/(2 pi), c = floor(p + 1/2)),
  * its w-plane, the least-squares w-kernel table, the kernel-correction and
  * twiddle tables, sorts the visibilities by (block, uv tile, support), forms
- * the work items of the persistent launches and, for RI_G_CSR, fills the CSR
- * G on the device (appendix E: "computed only once"). uvw: host, M x 3 doubles.
+ * the work items of the persistent launches and, for RI_G_CSR (RI_G_SEP), fills
+ * the stored G (its axis factors) on the device (appendix E: the sparse
+ * matrices are computed once). uvw: host, M x 3 doubles.
  * Synchronous. On success *out owns all device memory it allocated. */
 ri_status ri_create(const ri_plan_desc *desc, const double *uvw, ri_ctx **out);
 void ri_destroy(ri_ctx *ctx);

@@ -55,7 +55,20 @@ struct TileArgs {
     const cx<T> *yuser;
     cx<T> *yout;
     double *r2part;
+    const cx<T> *sepw;             // stored axis factors (RI_G_SEP): per visibility 17 (g_u, g_v) pairs
 };
+
+// The stored axis factors of visibility m (internal order): lane c < 16 takes
+// (g_u[c], g_v[c]), every lane the pair of index 16; zero past the window.
+template <typename T>
+__device__ __forceinline__ void sep_load(const cx<T> *sepw, int m, int lane, cx<T> &gu, cx<T> &gv, cx<T> &gu16,
+                                         cx<T> &gv16) {
+    const cx<T> *p = sepw + (size_t)m * 34;
+    gu = p[2 * lane];
+    gv = p[2 * lane + 1];
+    gu16 = p[32];
+    gv16 = p[33];
+}
 
 // Kaiser-Bessel weight kappa(t) = I0(beta sqrt(z)) / I0(beta) with
 // z = 1 - (2t/7)^2: the I0 power series is a power series in z, evaluated by
@@ -161,12 +174,14 @@ __device__ __forceinline__ void axis_weights(const TileArgs<T> &a, int m, int pl
 // Minimum waves per SIMD the register allocation must allow: the FP32
 // on-the-fly variants fit 64 VGPRs without spilling, which lets 8 waves (two
 // workgroups more per CU) hide the LDS latency; the others are left free (1).
-template <typename T, bool OTF>
-constexpr int tiles_min_waves() { return std::is_same<T, float>::value && OTF ? 8 : 1; }
+template <typename T, int GM>
+constexpr int tiles_min_waves() { return std::is_same<T, float>::value && GM != RI_G_CSR ? 8 : 1; }
 
-template <typename T, int OP, bool OTF>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiles_min_waves<T, OTF>())))
+// GM: RI_G_CSR (stored rows), RI_G_OTF (weights computed), RI_G_SEP (stored axis factors).
+template <typename T, int OP, int GM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiles_min_waves<T, GM>())))
 k_tiles(TileArgs<T> a) {
+    constexpr bool OTF = GM == RI_G_OTF, SEP = GM == RI_G_SEP;
     // All LDS is dynamic and starts at byte 0: a static __shared__ variable
     // would shift the dynamic block by its size and misalign the 8-byte
     // atomics on the subgrid. Layout: Xs (input subgrid, T), Yr and Yi (output
@@ -214,9 +229,11 @@ k_tiles(TileArgs<T> a) {
         // u one, 8.. the v one) is loaded one visibility ahead
         uint2 rec_n = make_uint2(0u, 0u);
         T f_n = (T)0;
+        cx<T> su_n = mk<T>((T)0, (T)0), sv_n = su_n, su16_n = su_n, sv16_n = su_n;
         if (grp < item.vc) {
             rec_n = a.rec[item.vb + grp];
             if (OTF) f_n = a.frac[2 * (size_t)(item.vb + grp) + (lane >> 3)];
+            if (SEP) sep_load(a.sepw, item.vb + grp, lane, su_n, sv_n, su16_n, sv16_n);
         }
         for (int vi = grp; vi < item.vc; vi += GROUPS) {
             const int m = item.vb + vi;
@@ -229,7 +246,19 @@ k_tiles(TileArgs<T> a) {
             const int NI = (SS + 15) >> 4;
             cx<T> acc = mk<T>((T)0, (T)0);
             cx<T> r;
-            if (OTF) {
+            if (OTF || SEP) {
+                cx<T> gu = mk<T>((T)0, (T)0), gv = gu, gu16 = gu, gv16 = gu;
+                if (SEP) {
+                    // stored factors, loaded one visibility ahead
+                    gu = su_n;
+                    gv = sv_n;
+                    gu16 = su16_n;
+                    gv16 = sv16_n;
+                    if (vi + GROUPS < item.vc) {
+                        rec_n = a.rec[m + GROUPS];
+                        sep_load(a.sepw, m + GROUPS, lane, su_n, sv_n, su16_n, sv16_n);
+                    }
+                } else {
                 // G row from its separable axis weights, all in registers:
                 // lanes 0..6 hold the u-axis KB weights kappa(f_u - (j - 3)),
                 // lanes 8..14 the v-axis ones; lane c then forms
@@ -253,7 +282,6 @@ k_tiles(TileArgs<T> a) {
                 // lane 8 + j kappa(f_v - (j - 3))
                 const T kbr = (lane & 7) < 7 ? kb_weight_in<T>(f - (T)((lane & 7) - 3), a) : (T)0;
                 wave_sync();
-                cx<T> gu = mk<T>((T)0, (T)0), gv = gu, gu16 = gu, gv16 = gu;
                 static_for<7>([&](auto J) {
                     constexpr int j = decltype(J)::value;
                     const T ku = row_share<j>(kbr), kv = row_share<8 + j>(kbr);
@@ -268,6 +296,7 @@ k_tiles(TileArgs<T> a) {
                     const cx<T> w0 = wk[0];
                     gu16 = scale(w0, row_share<6>(kbr));
                     gv16 = scale(w0, row_share<14>(kbr));
+                }
                 }
                 const bool col = lane < S;
                 if (OP & OP_DEGRID) {
@@ -437,6 +466,33 @@ __global__ void __launch_bounds__(256) k_fill_csr(TileArgs<double> a, int64_t M,
     }
 }
 
+// Axis-factor fill: per visibility its two axis weight vectors (FP64
+// arithmetic, rounded to T), as pairs (g_u[c], g_v[c]) for c < 17, zero past S.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill_sep(TileArgs<double> a, int64_t M, cx<T> *out) {
+    __shared__ double kbs[GROUPS * SCR_KB];
+    __shared__ cx<double> wks[GROUPS * SCR_W];
+    __shared__ cx<double> gs[GROUPS * SCR_G];
+    const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
+    double *kbg = kbs + grp * SCR_KB;
+    cx<double> *wk = wks + grp * SCR_W;
+    cx<double> *gg = gs + grp * SCR_G;
+    for (int64_t m = (int64_t)blockIdx.x * GROUPS + grp; m < M; m += (int64_t)gridDim.x * GROUPS) {
+        const uint2 rec = a.rec[m];
+        const int pl = (int)(rec.y & 0xFFFFu), h = (int)((rec.y >> 16) & 0xFu);
+        const int S = 2 * h + 7;
+        axis_weights<double>(a, (int)m, pl, h, S, lane, kbg, wk, gg);
+        cx<T> *o = out + (size_t)m * 34;
+        for (int cidx = lane; cidx < 17; cidx += 16) {
+            const cx<double> u = cidx < S ? gg[cidx] : mk<double>(0.0, 0.0);
+            const cx<double> w = cidx < S ? gg[18 + cidx] : mk<double>(0.0, 0.0);
+            o[2 * cidx] = mk<T>((T)u.x, (T)u.y);
+            o[2 * cidx + 1] = mk<T>((T)w.x, (T)w.y);
+        }
+        wave_sync();
+    }
+}
+
 // H = G^H G (appendix E), row by row of G: every pair of cells k, k + d of
 // the window with d in the stored upper half (dy > 0, or dy = 0 and dx >= 0)
 // adds conj(G[m, k]) G[m, k + d] = conj(g_v[ay] g_u[ax]) g_v[by] g_u[bx] to
@@ -526,7 +582,7 @@ size_t tiles_lds(size_t W, bool degrid, bool grid, size_t cx_bytes) {
            cx_bytes * GROUPS * SCR_W + 4 * sizeof(double) + 16;
 }
 
-template <typename T, int OP, bool OTF>
+template <typename T, int OP, int GM>
 void launch_op(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
     const size_t lds = tiles_lds((size_t)a.W, (OP & OP_DEGRID) != 0, (OP & OP_GRID) != 0, sizeof(cx<T>));
     if (lds + 64 > (size_t)c->dev.lds_per_block)
@@ -536,7 +592,7 @@ void launch_op(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
     int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / (lds + 1024)));
     int nwg = std::min(c->dev.cu_count * per_cu, std::max(1, a.n_items));
     if (nwg > c->n_partials) nwg = c->n_partials;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tiles<T, OP, OTF>), dim3(nwg), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tiles<T, OP, GM>), dim3(nwg), dim3(256), lds, s, a);
     if (OP == OP_FUSED && nwg < c->n_partials) fill_zero_f64(a.r2part + nwg, c->n_partials - nwg, s);
 }
 
@@ -546,8 +602,15 @@ int tiles_partials(ri_ctx *c) { return c->dev.cu_count * 8; }
 
 size_t lds_for_tile(int tile, int H, int cx_bytes) { return tiles_lds((size_t)tile + 2 * H, true, true, cx_bytes); }
 
+template <typename T, int GM>
+void launch_mode(ri_ctx *c, TileArgs<T> &a, int op, hipStream_t s) {
+    if (op == OP_DEGRID) launch_op<T, OP_DEGRID, GM>(c, a, s);
+    else if (op == OP_GRID) launch_op<T, OP_GRID, GM>(c, a, s);
+    else launch_op<T, OP_FUSED, GM>(c, a, s);
+}
+
 template <typename T>
-void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, int op, bool otf, const cx<T> *y_sorted,
+void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, int op, int gm, const cx<T> *y_sorted,
                   const cx<T> *y_user, cx<T> *y_out_user, double *r2_partials, hipStream_t s, int32_t *counter) {
     if (c->M == 0 || v.n_items == 0) {
         if (op == OP_FUSED && r2_partials) fill_zero_f64(r2_partials, c->n_partials, s);
@@ -561,21 +624,20 @@ void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, int op, bool otf, const 
     a.yout = y_out_user;
     a.r2part = r2_partials;
     a.counter = counter ? counter : c->d_counter;
-    if (!otf) {
+    if (gm == RI_G_CSR) {
+        if (!c->csr.val || c->csr.val_bytes != (int)sizeof(cx<T>)) throw Error(RI_EINVAL, "no stored G of this precision");
         a.rowptr = c->csr.rowptr;
         a.gval = (const cx<T> *)c->csr.val;
+    } else if (gm == RI_G_SEP) {
+        if (!c->sep.w || c->sep.val_bytes != (int)sizeof(cx<T>))
+            throw Error(RI_EINVAL, "no stored axis factors of this precision");
+        a.sepw = (const cx<T> *)c->sep.w;
     }
     fill_zero_i32(a.counter, 1, s);
     ProfScope prof(c, PROF_TILES, s);
-    if (otf) {
-        if (op == OP_DEGRID) launch_op<T, OP_DEGRID, true>(c, a, s);
-        else if (op == OP_GRID) launch_op<T, OP_GRID, true>(c, a, s);
-        else launch_op<T, OP_FUSED, true>(c, a, s);
-    } else {
-        if (op == OP_DEGRID) launch_op<T, OP_DEGRID, false>(c, a, s);
-        else if (op == OP_GRID) launch_op<T, OP_GRID, false>(c, a, s);
-        else launch_op<T, OP_FUSED, false>(c, a, s);
-    }
+    if (gm == RI_G_OTF) launch_mode<T, RI_G_OTF>(c, a, op, s);
+    else if (gm == RI_G_SEP) launch_mode<T, RI_G_SEP>(c, a, op, s);
+    else launch_mode<T, RI_G_CSR>(c, a, op, s);
     RI_CHECK_HIP(hipGetLastError());
 }
 
@@ -604,6 +666,24 @@ void fill_csr(ri_ctx *c, hipStream_t s) {
     }
 }
 
+// Stored axis factors (RI_G_SEP): per visibility of the main view, in its
+// internal order, the pairs (g_u[c], g_v[c]) for c = 0..16 (FP64 weights
+// rounded to T, zero past the window), 34 complex values.
+template <typename T>
+void fill_sep(ri_ctx *c, hipStream_t s) {
+    const View &v = c->view;
+    if (v.frac_bytes != 8) throw Error(RI_EINVAL, "axis-factor fill needs FP64 fractions");
+    c->sep.val_bytes = (int)sizeof(cx<T>);
+    c->sep.w = dev_alloc(c, sizeof(cx<T>) * 34 * (size_t)std::max<int64_t>(1, c->M));
+    ensure_prec<double>(c, c->p64);
+    TileArgs<double> a = make_args<double>(c, v, c->p64);
+    if (c->M > 0) {
+        int nwg = (int)std::min<int64_t>((c->M + GROUPS - 1) / GROUPS, (int64_t)c->dev.cu_count * 16);
+        hipLaunchKernelGGL(k_fill_sep<T>, dim3(nwg), dim3(256), 0, s, a, c->M, (cx<T> *)c->sep.w);
+        RI_CHECK_HIP(hipGetLastError());
+    }
+}
+
 template <typename T>
 void fill_holo(ri_ctx *c, const View &v, hipStream_t s) {
     if (v.frac_bytes != 8) throw Error(RI_EINVAL, "holographic build needs FP64 fractions");
@@ -619,10 +699,12 @@ void fill_holo(ri_ctx *c, const View &v, hipStream_t s) {
     }
 }
 
-template void launch_tiles<float>(ri_ctx *, const View &, Prec<float> &, int, bool, const cx<float> *,
+template void launch_tiles<float>(ri_ctx *, const View &, Prec<float> &, int, int, const cx<float> *,
                                   const cx<float> *, cx<float> *, double *, hipStream_t, int32_t *);
-template void launch_tiles<double>(ri_ctx *, const View &, Prec<double> &, int, bool, const cx<double> *,
+template void launch_tiles<double>(ri_ctx *, const View &, Prec<double> &, int, int, const cx<double> *,
                                    const cx<double> *, cx<double> *, double *, hipStream_t, int32_t *);
+template void fill_sep<float>(ri_ctx *, hipStream_t);
+template void fill_sep<double>(ri_ctx *, hipStream_t);
 template void fill_csr<float>(ri_ctx *, hipStream_t);
 template void fill_csr<double>(ri_ctx *, hipStream_t);
 template void fill_holo<float>(ri_ctx *, const View &, hipStream_t);

@@ -55,7 +55,7 @@ void gradient_in_workspace(ri_ctx *c, unsigned char *ws, const T *x, const void 
     }
     fwd_zpad_fft<T>(c, p, x, s);
     fill_zero<T>(p.gridA, (int64_t)c->P * c->Np * c->Np, s);
-    launch_tiles<T>(c, c->view, p, OP_FUSED, c->d.g_mode == RI_G_OTF, y_sorted, y_user, nullptr, part, s,
+    launch_tiles<T>(c, c->view, p, OP_FUSED, c->d.g_mode, y_sorted, y_user, nullptr, part, s,
                     counter);
     adj_fft_crop<T>(c, p, g, s);
     if (r2) reduce_partials(part, c->n_partials, 1, 1, r2, s);

@@ -82,24 +82,24 @@ template <typename T>
 void do_forward(ri_ctx *c, const T *x, cx<T> *y, hipStream_t s) {
     Prec<T> &p = prec<T>(c);
     fwd_zpad_fft<T>(c, p, x, s);
-    launch_tiles<T>(c, c->view, p, OP_DEGRID, c->d.g_mode == RI_G_OTF, nullptr, nullptr, y, nullptr, s);
+    launch_tiles<T>(c, c->view, p, OP_DEGRID, c->d.g_mode, nullptr, nullptr, y, nullptr, s);
 }
 
 template <typename T>
 void do_adjoint(ri_ctx *c, const cx<T> *y, T *x, hipStream_t s) {
     Prec<T> &p = prec<T>(c);
     fill_zero<T>(p.gridA, (int64_t)c->P * c->Np * c->Np, s);
-    launch_tiles<T>(c, c->view, p, OP_GRID, c->d.g_mode == RI_G_OTF, nullptr, y, nullptr, nullptr, s);
+    launch_tiles<T>(c, c->view, p, OP_GRID, c->d.g_mode, nullptr, y, nullptr, nullptr, s);
     adj_fft_crop<T>(c, p, x, s);
 }
 
 // g = Re{Phi^dagger (Phi x - y)} with y in internal order (or none); r2 partials in tile_part.
 template <typename T>
-void do_gradient(ri_ctx *c, const View &v, bool otf, const T *x, const cx<T> *y_sorted, T *g, hipStream_t s) {
+void do_gradient(ri_ctx *c, const View &v, int gm, const T *x, const cx<T> *y_sorted, T *g, hipStream_t s) {
     Prec<T> &p = prec<T>(c);
     fwd_zpad_fft<T>(c, p, x, s);
     fill_zero<T>(p.gridA, (int64_t)c->P * c->Np * c->Np, s);
-    launch_tiles<T>(c, v, p, OP_FUSED, otf, y_sorted, nullptr, nullptr, tile_part(c), s);
+    launch_tiles<T>(c, v, p, OP_FUSED, gm, y_sorted, nullptr, nullptr, tile_part(c), s);
     adj_fft_crop<T>(c, p, g, s);
 }
 
@@ -140,7 +140,7 @@ void fb_step_sorted(ri_ctx *c, const T *x_in, const cx<T> *ys, double gamma, int
         }
         axpby<T>(p.img0, p.img0, (T)1, holo_dirty, (T)(-1), nn, s);
     } else {
-        do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, x_in, ys, p.img0, s);
+        do_gradient<T>(c, c->view, c->d.g_mode, x_in, ys, p.img0, s);
     }
     if (kind == RI_PROX_HAAR) {
         const int nwg = ((c->N / 16) * (c->N / 16) + 3) / 4;
@@ -188,17 +188,24 @@ void do_fb_step(ri_ctx *c, const T *x_in, const void *y, double gamma, int kind,
 // SARA state are grid- and image-level and do not depend on the view's
 // visibility order, so they are kept.
 void build_main_view(ri_ctx *c, int tile) {
-    const bool f64frac = c->d.g_mode == RI_G_CSR || c->d.precision == 64;
+    const bool f64frac = c->d.g_mode != RI_G_OTF || c->d.precision == 64;
     free_view(c, c->view);
     if (c->csr.val) {
         dev_free(c, c->csr.rowptr);
         dev_free(c, c->csr.val);
         c->csr = CSR();
     }
+    if (c->sep.w) {
+        dev_free(c, c->sep.w);
+        c->sep = Sep();
+    }
     build_view(c, c->view, tile, f64frac ? 8 : 4);
     if (c->d.g_mode == RI_G_CSR) {
         if (c->d.precision == 32) fill_csr<float>(c, nullptr);
         else fill_csr<double>(c, nullptr);
+    } else if (c->d.g_mode == RI_G_SEP) {
+        if (c->d.precision == 32) fill_sep<float>(c, nullptr);
+        else fill_sep<double>(c, nullptr);
     }
 }
 
@@ -220,10 +227,10 @@ void autotune_tile(ri_ctx *c) {
         if (t > c->Np || c->Np % t) continue;
         if (lds_for_tile(t, c->H, eb) > (size_t)c->dev.lds_per_block) continue;
         build_main_view(c, t);
-        do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, p.img1, nullptr, p.img0, nullptr);
+        do_gradient<T>(c, c->view, c->d.g_mode, p.img1, nullptr, p.img0, nullptr);
         RI_CHECK_HIP(hipEventRecord(e0, nullptr));
         for (int r = 0; r < 3; ++r)
-            do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, p.img1, nullptr, p.img0, nullptr);
+            do_gradient<T>(c, c->view, c->d.g_mode, p.img1, nullptr, p.img0, nullptr);
         RI_CHECK_HIP(hipEventRecord(e1, nullptr));
         RI_CHECK_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -268,7 +275,7 @@ double power_iteration(ri_ctx *c, int max_it, double rtol, const double *x0, int
     *conv = false;
     int it = 0;
     for (it = 1; it <= max_it; ++it) {
-        do_gradient<double>(c, v, true, x, nullptr, y, s);
+        do_gradient<double>(c, v, RI_G_OTF, x, nullptr, y, s);
         dot_partials<double>(y, y, n, img_part(c), s);
         reduce_partials(img_part(c), 1024, 1, 1, ss, s);
         scale_by_inv_sqrt(y, ss, n, s);
@@ -293,7 +300,7 @@ double dirty_peak(ri_ctx *c, const cx<T> *ys, hipStream_t s) {
     Prec<T> &p = prec<T>(c);
     const int64_t n = (int64_t)c->N * c->N;
     fill_real<T>(p.img1, n, (T)0, s);
-    do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, p.img1, ys, p.img0, s);
+    do_gradient<T>(c, c->view, c->d.g_mode, p.img1, ys, p.img0, s);
     axpby<T>(p.img0, p.img0, (T)-1, nullptr, (T)0, n, s);
     max_value<T>(p.img0, n, img_part(c), c->d_scalars, s);
     RI_CHECK_HIP(hipMemcpyAsync(c->h_pinned, c->d_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -309,7 +316,7 @@ double dirty_beam_peak(ri_ctx *c, hipStream_t s) {
     const int64_t n = (int64_t)c->N * c->N;
     fill_real<T>(p.img1, n, (T)0, s);
     fill_real<T>(p.img1 + (int64_t)(c->N / 2) * c->N + c->N / 2, 1, (T)1, s);
-    do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, p.img1, nullptr, p.img0, s);
+    do_gradient<T>(c, c->view, c->d.g_mode, p.img1, nullptr, p.img0, s);
     max_value<T>(p.img0, n, img_part(c), c->d_scalars, s);
     RI_CHECK_HIP(hipMemcpyAsync(c->h_pinned, c->d_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
     RI_CHECK_HIP(hipStreamSynchronize(s));
@@ -387,7 +394,7 @@ bool solve(ri_ctx *c, const void *y, const ri_solve_opts &o, T *x_out, ri_solve_
             hdirty = (T *)dev_alloc(c, sizeof(T) * n); owned.push_back(hdirty);
             hyy = (double *)dev_alloc(c, sizeof(double)); owned.push_back(hyy);
             fill_real<T>(xa, n, (T)0, s);
-            do_gradient<T>(c, c->view, c->d.g_mode == RI_G_OTF, xa, ys, hdirty, s);
+            do_gradient<T>(c, c->view, c->d.g_mode, xa, ys, hdirty, s);
             reduce_partials(tile_part(c), tiles_partials(c), 1, 1, hyy, s);
             axpby<T>(hdirty, hdirty, (T)(-1), nullptr, (T)0, n, s);
         }
@@ -547,7 +554,8 @@ ri_status ri_create(const ri_plan_desc *desc, const double *uvw, ri_ctx **out) {
         require(d.n_wplanes >= 1 && d.n_wplanes % 2 == 1 && d.n_wplanes <= 65535, "n_wplanes must be odd, <= 65535");
         require(std::isfinite(d.w_max) && d.w_max >= 0.0, "w_max must be finite and >= 0");
         require(d.w_max == 0.0 || (std::isfinite(d.cell_rad) && d.cell_rad > 0.0), "cell_rad must be > 0");
-        require(d.g_mode == RI_G_CSR || d.g_mode == RI_G_OTF, "g_mode must be RI_G_CSR or RI_G_OTF");
+        require(d.g_mode == RI_G_CSR || d.g_mode == RI_G_OTF || d.g_mode == RI_G_SEP,
+                "g_mode must be RI_G_CSR, RI_G_OTF or RI_G_SEP");
         require(d.precision == 32 || d.precision == 64, "precision must be 32 or 64");
         require(d.tile == 0 || (d.tile >= 8 && d.tile <= 128 && Np % d.tile == 0), "tile must be 0 or divide N'");
         require(d.M >= 0 && d.M < (int64_t)1 << 31, "M must be in [0, 2^31)");
@@ -623,6 +631,7 @@ void ri_destroy(ri_ctx *c) {
     free_view(c, c->view);
     free_view(c, c->view64);
     dev_free(c, c->csr.rowptr); dev_free(c, c->csr.val);
+    dev_free(c, c->sep.w);
     holo_free(c);
     auto freep = [c](auto &p) {
         dev_free(c, p.icorr); dev_free(c, p.tw); dev_free(c, p.wtaps); dev_free(c, p.gridA); dev_free(c, p.gridB);
@@ -682,10 +691,10 @@ ri_status ri_gradient(ri_ctx *c, const void *x, const void *y, void *g, double *
         require(x && g, "x or g is NULL");
         if (c->d.precision == 32) {
             const cx<float> *ys = resolve_data<float>(c, y, st(s));
-            do_gradient<float>(c, c->view, c->d.g_mode == RI_G_OTF, (const float *)x, ys, (float *)g, st(s));
+            do_gradient<float>(c, c->view, c->d.g_mode, (const float *)x, ys, (float *)g, st(s));
         } else {
             const cx<double> *ys = resolve_data<double>(c, y, st(s));
-            do_gradient<double>(c, c->view, c->d.g_mode == RI_G_OTF, (const double *)x, ys, (double *)g, st(s));
+            do_gradient<double>(c, c->view, c->d.g_mode, (const double *)x, ys, (double *)g, st(s));
         }
         if (r2) reduce_partials(tile_part(c), tiles_partials(c), 1, 1, r2, st(s));
         RI_CHECK_HIP(hipGetLastError());

@@ -66,6 +66,13 @@ struct CSR {
     int val_bytes = 0;
 };
 
+// G stored as its separable axis factors (RI_G_SEP): per visibility, in the
+// main view's internal order, 17 pairs (g_u[c], g_v[c]) of complex weights.
+struct Sep {
+    void *w = nullptr;            // cx<T>[M][17][2]
+    int val_bytes = 0;
+};
+
 // Tables and work buffers of one precision.
 template <typename T> struct Prec {
     bool ready = false;
@@ -147,6 +154,7 @@ struct ri_ctx {
     ri::View view64;                      // FP64 OTF view for the power iteration (if needed)
     bool view64_is_main = false;
     ri::CSR csr;
+    ri::Sep sep;
     ri::Holo holo;
     ri::SaraState sara;
 
@@ -214,15 +222,17 @@ template <typename T> void adj_fft_crop(ri_ctx *c, Prec<T> &p, T *x, hipStream_t
 
 // gridding.hip
 enum { OP_DEGRID = 1, OP_GRID = 2, OP_FUSED = 3 };
-// The persistent uv-tile launch. OP_FUSED subtracts y_sorted (internal order)
+// The persistent uv-tile launch with G in mode g_mode (RI_G_CSR, RI_G_OTF or
+// RI_G_SEP; the stored forms must exist in T). OP_FUSED subtracts y_sorted (internal order)
 // or else y_user (caller's order, read through the view's permutation), or
 // nothing when both are NULL. counter: the launch's work counter (NULL: the
 // context's).
-template <typename T> void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, int op, bool otf,
+template <typename T> void launch_tiles(ri_ctx *c, const View &v, Prec<T> &p, int op, int g_mode,
                                         const cx<T> *y_sorted, const cx<T> *y_user,
                                         cx<T> *y_out_user, double *r2_partials, hipStream_t s,
                                         int32_t *counter = nullptr);
 template <typename T> void fill_csr(ri_ctx *c, hipStream_t s);
+template <typename T> void fill_sep(ri_ctx *c, hipStream_t s);
 // Accumulate G^H G of the visibilities of v (FP64 fractions) into c->holo.val (zeroed).
 template <typename T> void fill_holo(ri_ctx *c, const View &v, hipStream_t s);
 

@@ -17,7 +17,7 @@ import numpy as np
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libri.so")
 
 RI_OK, RI_EINVAL, RI_ENOMEM, RI_EDEVICE, RI_EUNSUPPORTED, RI_ENOTCONV, RI_FELLBACK = 0, -1, -2, -3, -4, -5, 1
-RI_G_CSR, RI_G_OTF = 0, 1
+RI_G_CSR, RI_G_OTF, RI_G_SEP = 0, 1, 2
 RI_PROX_HAAR, RI_PROX_CNN, RI_PROX_SARA = 0, 1, 2
 RI_NO_DATA = c_void_p(-1 & 0xFFFFFFFFFFFFFFFF)
 

@@ -44,7 +44,7 @@ def test_haar_denoise_matches_oracle(prec, t):
     assert err <= (2e-6 if prec == 32 else 1e-14)
 
 
-@pytest.mark.parametrize("prec,mode", [(32, R.RI_G_CSR), (32, R.RI_G_OTF), (64, R.RI_G_OTF)])
+@pytest.mark.parametrize("prec,mode", [(32, R.RI_G_CSR), (32, R.RI_G_OTF), (32, R.RI_G_SEP), (64, R.RI_G_OTF)])
 def test_fb_step_matches_oracle(prec, mode):
     c = wide()
     ctx = _ctx(c, prec, mode)

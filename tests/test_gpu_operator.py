@@ -19,7 +19,8 @@ import paper_2207_11336_amd.ri as R  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-MODES = [(64, R.RI_G_OTF), (64, R.RI_G_CSR), (32, R.RI_G_CSR), (32, R.RI_G_OTF)]
+MODES = [(64, R.RI_G_OTF), (64, R.RI_G_CSR), (64, R.RI_G_SEP), (32, R.RI_G_CSR), (32, R.RI_G_OTF),
+         (32, R.RI_G_SEP)]
 TOL_PHI = {32: 5e-6, 64: 1e-11}
 TOL_GRAM = {32: 1e-5, 64: 1e-11}
 

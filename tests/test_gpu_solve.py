@@ -35,7 +35,7 @@ def _blocked_case():
     return c, c.uvw[perm], offs
 
 
-@pytest.mark.parametrize("prec,mode", [(32, R.RI_G_CSR), (32, R.RI_G_OTF), (64, R.RI_G_OTF)])
+@pytest.mark.parametrize("prec,mode", [(32, R.RI_G_CSR), (32, R.RI_G_OTF), (32, R.RI_G_SEP), (64, R.RI_G_OTF)])
 def test_blocks_sum_to_monolithic_operator(prec, mode):
     c, uvw_b, offs = _blocked_case()
     mk = lambda uvw, nb, bo: R.ri_create(R.plan_desc(c.N, c.M, cell_rad=c.cell, w_max=c.W, n_wplanes=c.n_wplanes,

@@ -55,6 +55,7 @@ typedef enum {
 } ri_status;
 
 enum { RI_G_CSR = 0, RI_G_OTF = 1, RI_G_SEP = 2 };
+enum { RI_GRID_GATHER = 0, RI_GRID_SCATTER = 1 };
 enum { RI_PROX_HAAR = 0, RI_PROX_CNN = 1, RI_PROX_SARA = 2 };
 
 /* Plan description. All sizes explicit; nothing is read through globals. */
@@ -90,6 +91,13 @@ typedef struct {
                               phase screen exp(-2 pi i w_p (sqrt(1 - l^2 - m^2) - 1)) in Z and has
                               its own FFT pair; the w-plane table then spans the residual
                               [-W/P, W/P]. Costs P FFT pairs and 2P grids per pass. */
+    int32_t grid_form;     /* how G^H accumulates a work item's subgrid. RI_GRID_GATHER (0, the
+                              default): in FP32 with G on the fly or as stored axis factors and a
+                              subgrid side tile + 2 (hmax + 3) <= 32, every wave keeps the whole
+                              subgrid in FP32 registers and gathers its visibilities' separable
+                              contributions (no LDS atomics); other cases fall back to the scatter
+                              form. RI_GRID_SCATTER (1): each visibility's window is added into
+                              FP64 LDS planes by atomics. The two differ by FP32 rounding order. */
 } ri_plan_desc;
 
 /* Build a context: validates the description, computes every visibility's

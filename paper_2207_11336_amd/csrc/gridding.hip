@@ -35,6 +35,13 @@ constexpr int SCR_KB = 16;         // per-group KB scratch (two axes x 8), T
 constexpr int SCR_W = 12;          // per-group w-taps (2 hmax + 1 <= 11), cx<T>
 constexpr int SCR_G = 36;          // per-group axis weights (two axes x 18), cx<T>
 constexpr int KB_TERMS_MAX = 32;
+#ifndef TILES_GA_WAVES
+#define TILES_GA_WAVES 5           // waves per SIMD the gather-form kernels are compiled for
+#endif
+#ifndef TILES_GA_UNROLL
+#define TILES_GA_UNROLL 1          // gather slots unrolled together
+#endif
+
 
 template <typename T>
 struct TileArgs {
@@ -139,6 +146,14 @@ __device__ __forceinline__ void static_for_(F &&f, std::integer_sequence<int, I.
 template <int N, typename F>
 __device__ __forceinline__ void static_for(F &&f) { static_for_(f, std::make_integer_sequence<int, N>{}); }
 
+// acc + a b with the four products as FMAs.
+template <typename T>
+__device__ __forceinline__ cx<T> cmac(cx<T> acc, cx<T> a, cx<T> b) {
+    acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+    acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+    return acc;
+}
+
 template <typename T>
 __device__ __forceinline__ void lds_add(T *p, T v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -174,14 +189,27 @@ __device__ __forceinline__ void axis_weights(const TileArgs<T> &a, int m, int pl
 // Minimum waves per SIMD the register allocation must allow: the FP32
 // on-the-fly variants fit 64 VGPRs without spilling, which lets 8 waves (two
 // workgroups more per CU) hide the LDS latency; the others are left free (1).
-template <typename T, int GM>
-constexpr int tiles_min_waves() { return std::is_same<T, float>::value && GM != RI_G_CSR ? 8 : 1; }
+template <typename T, int GM, int GB>
+constexpr int tiles_min_waves() {
+    return GB > 0 ? TILES_GA_WAVES : (std::is_same<T, float>::value && GM != RI_G_CSR ? 8 : 1);
+}
+
+// LDS of the gather form: per group a slot with the padded vectors P and g_v
+// of its current visibility (complex arrays of LEN entries; the window's 17
+// entries start at PAD = W - 7, the rest reads zero), then the window origins.
+__host__ __device__ constexpr int ga_pad(int W) { return W - 7; }
+__host__ __device__ constexpr int ga_len(int W, int GB) { return (W - 7 + 8 * GB + 1) & ~1; }
+__host__ __device__ constexpr int ga_slot_cx(int W, int GB) { return 2 * ga_len(W, GB); }
 
 // GM: RI_G_CSR (stored rows), RI_G_OTF (weights computed), RI_G_SEP (stored axis factors).
-template <typename T, int OP, int GM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiles_min_waves<T, GM>())))
+// GB = 0: scatter-form gridding (FP64 LDS atomics into the output subgrid).
+// GB = 3, 4: gather-form gridding (GB x GB output cells per lane; see the
+// comment at the gather).
+template <typename T, int OP, int GM, int GB>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiles_min_waves<T, GM, GB>())))
 k_tiles(TileArgs<T> a) {
-    constexpr bool OTF = GM == RI_G_OTF, SEP = GM == RI_G_SEP;
+    constexpr bool OTF = GM == RI_G_OTF, SEP = GM == RI_G_SEP, GA = GB > 0;
+    static_assert(!GA || ((OP & OP_GRID) && GM != RI_G_CSR), "gather form: gridding with separable rows only");
     // All LDS is dynamic and starts at byte 0: a static __shared__ variable
     // would shift the dynamic block by its size and misalign the 8-byte
     // atomics on the subgrid. Layout: Xs (input subgrid, T), Yr and Yi (output
@@ -190,12 +218,17 @@ k_tiles(TileArgs<T> a) {
     // part a multiple of 16 bytes). The output accumulates in FP64 for both
     // precisions: on gfx950 an LDS FP64 atomic add costs ~8 cycles per wave
     // against ~190 for FP32.
+    // The gather form keeps X's region also when only gridding (it holds a
+    // partial subgrid at the item's end) and has slots instead of Yr, Yi.
     extern __shared__ unsigned char smem_raw[];
     const int W = a.W, WW = W * W;
+    const int PAD = ga_pad(W), LEN = ga_len(W, GB), SLOT = ga_slot_cx(W, GB);
     cx<T> *Xs = reinterpret_cast<cx<T> *>(smem_raw);
-    double *Yr = reinterpret_cast<double *>(Xs + ((OP & OP_DEGRID) ? WW : 0));
-    double *Yi = Yr + ((OP & OP_GRID) ? WW : 0);
-    cx<T> *wks = reinterpret_cast<cx<T> *>(Yi + ((OP & OP_GRID) ? WW : 0));
+    double *Yr = reinterpret_cast<double *>(Xs + ((GA || (OP & OP_DEGRID)) ? WW : 0));
+    double *Yi = Yr + ((!GA && (OP & OP_GRID)) ? WW : 0);
+    cx<T> *slot = reinterpret_cast<cx<T> *>(Yi + ((!GA && (OP & OP_GRID)) ? WW : 0));
+    int *sorg = reinterpret_cast<int *>(slot + (GA ? GROUPS * SLOT : 0));
+    cx<T> *wks = reinterpret_cast<cx<T> *>(sorg + (GA ? GROUPS : 0));
     double *s_red = reinterpret_cast<double *>(wks + GROUPS * SCR_W);
     int &s_item = *reinterpret_cast<int *>(s_red + 4);
     const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
@@ -220,10 +253,18 @@ k_tiles(TileArgs<T> a) {
                 Xs[e] = Xg[((size_t)((y0 + r) & Npm) << a.logNp) + ((x0 + cc) & Npm)];
             }
         }
-        if (OP & OP_GRID) {
+        if (!GA && (OP & OP_GRID)) {
             for (int e = tid; e < WW; e += blockDim.x) { Yr[e] = 0.0; Yi[e] = 0.0; }
         }
+        if (GA) {   // the slots' padding must read zero (the item's end reuses them)
+            for (int e = tid; e < GROUPS * SLOT; e += blockDim.x) slot[e] = mk<T>((T)0, (T)0);
+        }
         __syncthreads();
+        constexpr int NB = GA ? GB : 1;
+        cx<T> gacc[NB][NB];
+        if (GA) {
+            static_for<NB>([&](auto I) { static_for<NB>([&](auto J) { gacc[I][J] = mk<T>((T)0, (T)0); }); });
+        }
 
         // the group's next record (and on the fly its fraction: lane l < 8 the
         // u one, 8.. the v one) is loaded one visibility ahead
@@ -235,7 +276,11 @@ k_tiles(TileArgs<T> a) {
             if (OTF) f_n = a.frac[2 * (size_t)(item.vb + grp) + (lane >> 3)];
             if (SEP) sep_load(a.sepw, item.vb + grp, lane, su_n, sv_n, su16_n, sv16_n);
         }
-        for (int vi = grp; vi < item.vc; vi += GROUPS) {
+        // The gather form steps whole waves (visibility vb + g for group g of
+        // the wave) so that each wave can gather its four visibilities together.
+        for (int vb = GA ? (grp & ~3) : grp; vb < item.vc; vb += GROUPS) {
+          const int vi = GA ? vb + (grp & 3) : vb;
+          if (!GA || vi < item.vc) {
             const int m = item.vb + vi;
             const uint2 rec = rec_n;
             const T f = f_n;
@@ -307,19 +352,19 @@ k_tiles(TileArgs<T> a) {
                     cx<T> accv = mk<T>((T)0, (T)0);
                     cx<T> xv[7];
                     static_for<7>([&](auto J) { xv[J] = xp[J * W]; });
-                    static_for<7>([&](auto J) { accv = accv + row_share<decltype(J)::value>(gv) * xv[J]; });
+                    static_for<7>([&](auto J) { accv = cmac(accv, row_share<decltype(J)::value>(gv), xv[J]); });
                     static_for<5>([&](auto P) {
                         constexpr int y0 = 7 + 2 * decltype(P)::value, y1 = y0 + 1;
                         if (y0 < S) {
                             const cx<T> x0 = xp[y0 * W], x1 = xp[y1 * W];
-                            accv = accv + row_share<y0>(gv) * x0;
-                            accv = accv + (y1 < 16 ? row_share<y1 & 15>(gv) : row_share<0>(gv16)) * x1;
+                            accv = cmac(accv, row_share<y0>(gv), x0);
+                            accv = cmac(accv, y1 < 16 ? row_share<y1 & 15>(gv) : row_share<0>(gv16), x1);
                         }
                     });
                     acc = accv * gu;
                     if (S == 17) {
-                        acc = acc + (gv * row_share<0>(gu16)) * Xs[base + lane * W + 16];
-                        if (lane == 0) acc = acc + (gv16 * gu16) * Xs[base + 16 * W + 16];
+                        acc = cmac(acc, gv * row_share<0>(gu16), Xs[base + lane * W + 16]);
+                        if (lane == 0) acc = cmac(acc, gv16 * gu16, Xs[base + 16 * W + 16]);
                     }
                     acc.x = sum16(acc.x);
                     acc.y = sum16(acc.y);
@@ -334,7 +379,18 @@ k_tiles(TileArgs<T> a) {
                 } else {
                     r = a.yuser[a.perm[m]];
                 }
-                if (OP & OP_GRID) {
+                if (GA) {
+                    // publish P = r conj(g_u), g_v and the window origin in the
+                    // group's slot (entries past the window are zero)
+                    cx<T> *ps = slot + grp * SLOT + PAD;
+                    ps[lane] = mulc(r, gu);
+                    ps[LEN + lane] = gv;
+                    if (lane == 0) {
+                        ps[16] = mulc(r, gu16);
+                        ps[LEN + 16] = gv16;
+                        sorg[grp] = (cu - item.tx0 + a.H - h - 3) | ((cv - item.ty0 + a.H - h - 3) << 16);
+                    }
+                } else if (OP & OP_GRID) {
                     // Y[ay][c] += r conj(g_v[ay] g_u[c])
                     const cx<T> rc = mulc(r, gu);
                     double *yr = Yr + base + lane, *yi = Yi + base + lane;
@@ -382,7 +438,7 @@ k_tiles(TileArgs<T> a) {
                     int ay = ay0, ax = ax0;
 #pragma unroll
                     for (int i = 0; i < MAXI; ++i) {
-                        if (i < NI && lane + 16 * i < SS) acc = acc + wv[i] * Xs[base + ay * W + ax];
+                        if (i < NI && lane + 16 * i < SS) acc = cmac(acc, wv[i], Xs[base + ay * W + ax]);
                         ax += 16 - q16 * S;
                         ay += q16;
                         if (ax >= S) { ax -= S; ++ay; }
@@ -416,10 +472,81 @@ k_tiles(TileArgs<T> a) {
                     }
                 }
             }
-            if (OTF) wave_sync();   // wk is rewritten by the group's next visibility
+            if (OTF && !GA) wave_sync();   // wk is rewritten by the group's next visibility
+          } else if (GA) {
+            // no visibility left for this group: its slot adds zeros
+            cx<T> *ps = slot + grp * SLOT + PAD;
+            ps[lane] = mk<T>((T)0, (T)0);
+            if (lane == 0) {
+                ps[16] = mk<T>((T)0, (T)0);
+                sorg[grp] = 0;
+            }
+          }
+          if constexpr (GA) {
+            // Gather-form gridding: each wave holds the whole output subgrid
+            // in registers, lane l the GB x GB cells x = GB (l & 7) + j,
+            // y = GB (l >> 3) + i, and adds for each of its four visibilities
+            //   Y[y][x] += P[x - bx] conj(g_v[y - by])
+            // with P and g_v read from the slot at offsets padded with zeros
+            // (W - 7 entries before the window, the rest after it), so cells
+            // outside a window add exact zeros without a test. No atomics: the
+            // cost per visibility is 2 GB LDS reads per lane.
+            wave_sync();
+            const int wl = tid & 63, lx = wl & 7, ly = wl >> 3, sb = grp & ~3;
+            const int4 o4 = *reinterpret_cast<const int4 *>(sorg + sb);
+#pragma unroll TILES_GA_UNROLL
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int org = s4 == 0 ? o4.x : (s4 == 1 ? o4.y : (s4 == 2 ? o4.z : o4.w));
+                const cx<T> *pp = slot + (sb + s4) * SLOT + PAD - (org & 0xFFFF) + NB * lx;
+                const cx<T> *qq = slot + (sb + s4) * SLOT + LEN + PAD - (org >> 16) + NB * ly;
+                cx<T> p[NB], q[NB];
+                static_for<NB>([&](auto J) { p[J] = pp[J]; q[J] = qq[J]; });
+                // Y += p conj(q), two FMAs per component
+                static_for<NB>([&](auto I) {
+                    static_for<NB>([&](auto J) {
+                        gacc[I][J].x = fma(p[J].x, q[I].x, fma(p[J].y, q[I].y, gacc[I][J].x));
+                        gacc[I][J].y = fma(p[J].y, q[I].x, fma(-p[J].x, q[I].y, gacc[I][J].y));
+                    });
+                });
+            }
+            wave_sync();   // the slots are rewritten by the next four visibilities
+          }
         }
         __syncthreads();
-        if (OP & OP_GRID) {
+        if constexpr (GA) {
+            // sum of the four waves' subgrids: waves 0 and 1 store theirs (in
+            // X's region and the slots), waves 2 and 3 add theirs, then the
+            // two partial sums are added and flushed
+            const int w = tid >> 6, wl = tid & 63, lx = wl & 7, ly = wl >> 3;
+            cx<T> *R = (w & 1) ? slot : Xs;
+            if (w < 2) {
+                static_for<NB>([&](auto I) {
+                    static_for<NB>([&](auto J) {
+                        const int y = NB * ly + I, x = NB * lx + J;
+                        if (x < W && y < W) R[y * W + x] = gacc[I][J];
+                    });
+                });
+            }
+            __syncthreads();
+            if (w >= 2) {
+                static_for<NB>([&](auto I) {
+                    static_for<NB>([&](auto J) {
+                        const int y = NB * ly + I, x = NB * lx + J;
+                        if (x < W && y < W) R[y * W + x] = R[y * W + x] + gacc[I][J];
+                    });
+                });
+            }
+            __syncthreads();
+            for (int e = tid; e < WW; e += blockDim.x) {
+                const cx<T> v = Xs[e] + slot[e];
+                if (v.x != (T)0 || v.y != (T)0) {
+                    const int r = e / W, cc = e - r * W;
+                    cx<T> *dst = Yg + ((size_t)((y0 + r) & Npm) << a.logNp) + ((x0 + cc) & Npm);
+                    global_add(&dst->x, v.x);
+                    global_add(&dst->y, v.y);
+                }
+            }
+        } else if constexpr ((OP & OP_GRID) != 0) {
             for (int e = tid; e < WW; e += blockDim.x) {
                 const double vr = Yr[e], vi = Yi[e];
                 if (vr != 0.0 || vi != 0.0) {
@@ -576,15 +703,24 @@ TileArgs<T> make_args(ri_ctx *c, const View &v, Prec<T> &p) {
 // Dynamic LDS of one k_tiles workgroup on a W x W subgrid (the layout at the
 // kernel's top): X (cx<T>) when degridding, the FP64 real and imaginary planes
 // when gridding, the groups' w-taps, the reduction slots and the item index.
-size_t tiles_lds(size_t W, bool degrid, bool grid, size_t cx_bytes) {
+// The gather form (GB > 0) has X's region in every case, the groups' slots
+// and window origins in place of the FP64 planes.
+size_t tiles_lds(size_t W, bool degrid, bool grid, size_t cx_bytes, int GB = 0) {
     const size_t WW = W * W;
+    if (GB > 0)
+        return cx_bytes * WW + cx_bytes * GROUPS * (size_t)ga_slot_cx((int)W, GB) + sizeof(int) * GROUPS +
+               cx_bytes * GROUPS * SCR_W + 4 * sizeof(double) + 16;
     return cx_bytes * WW * (degrid ? 1 : 0) + 2 * sizeof(double) * WW * (grid ? 1 : 0) +
            cx_bytes * GROUPS * SCR_W + 4 * sizeof(double) + 16;
 }
 
-template <typename T, int OP, int GM>
-void launch_op(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
-    const size_t lds = tiles_lds((size_t)a.W, (OP & OP_DEGRID) != 0, (OP & OP_GRID) != 0, sizeof(cx<T>));
+template <typename T, int OP, int GM, int GB>
+void launch_op_gb(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
+    // the gather form's subgrid fits 8 GB cells a side, and its reduction
+    // stores a W x W partial subgrid in the slots
+    if (GB > 0 && (a.W > 8 * GB || (size_t)a.W * a.W > (size_t)GROUPS * ga_slot_cx(a.W, GB)))
+        throw Error(RI_EUNSUPPORTED, "gather-form tile kernel launched on a subgrid it does not cover");
+    const size_t lds = tiles_lds((size_t)a.W, (OP & OP_DEGRID) != 0, (OP & OP_GRID) != 0, sizeof(cx<T>), GB);
     if (lds + 64 > (size_t)c->dev.lds_per_block)
         throw Error(RI_EUNSUPPORTED, "tile " + std::to_string(a.tile) + " needs " + std::to_string(lds) +
                                          " B of LDS per workgroup; device allows " +
@@ -592,8 +728,19 @@ void launch_op(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
     int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / (lds + 1024)));
     int nwg = std::min(c->dev.cu_count * per_cu, std::max(1, a.n_items));
     if (nwg > c->n_partials) nwg = c->n_partials;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tiles<T, OP, GM>), dim3(nwg), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tiles<T, OP, GM, GB>), dim3(nwg), dim3(256), lds, s, a);
     if (OP == OP_FUSED && nwg < c->n_partials) fill_zero_f64(a.r2part + nwg, c->n_partials - nwg, s);
+}
+
+// Gridding through separable rows in FP32 takes the gather form when the
+// subgrid fits it (W <= 32) unless the context asks for the scatter form.
+template <typename T, int OP, int GM>
+void launch_op(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
+    if constexpr (std::is_same<T, float>::value && GM != RI_G_CSR && (OP & OP_GRID) != 0) {
+        if (c->d.grid_form == RI_GRID_GATHER && a.W <= 24) return launch_op_gb<T, OP, GM, 3>(c, a, s);
+        if (c->d.grid_form == RI_GRID_GATHER && a.W <= 32) return launch_op_gb<T, OP, GM, 4>(c, a, s);
+    }
+    launch_op_gb<T, OP, GM, 0>(c, a, s);
 }
 
 }  // namespace

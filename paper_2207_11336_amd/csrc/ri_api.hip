@@ -565,6 +565,7 @@ ri_status ri_create(const ri_plan_desc *desc, const double *uvw, ri_ctx **out) {
         require(d.item_vis >= 0 && d.item_vis <= (1 << 20), "item_vis must be in [0, 2^20]");
         require(d.n_wstacks >= 0 && d.n_wstacks <= 64, "n_wstacks must be in [0, 64]");
         require(d.n_wstacks <= 1 || d.w_max > 0.0, "w-stacking needs w_max > 0");
+        require(d.grid_form == RI_GRID_GATHER || d.grid_form == RI_GRID_SCATTER, "grid_form must be 0 or 1");
         c = new ri_ctx();
         c->d = d;
         c->d.block_offsets = nullptr;

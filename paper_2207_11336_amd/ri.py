@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libri.so")
 
 RI_OK, RI_EINVAL, RI_ENOMEM, RI_EDEVICE, RI_EUNSUPPORTED, RI_ENOTCONV, RI_FELLBACK = 0, -1, -2, -3, -4, -5, 1
 RI_G_CSR, RI_G_OTF, RI_G_SEP = 0, 1, 2
+RI_GRID_GATHER, RI_GRID_SCATTER = 0, 1
 RI_PROX_HAAR, RI_PROX_CNN, RI_PROX_SARA = 0, 1, 2
 RI_NO_DATA = c_void_p(-1 & 0xFFFFFFFFFFFFFFFF)
 
@@ -44,7 +45,7 @@ class ri_plan_desc(ctypes.Structure):
                 ("cell_rad", c_double), ("w_max", c_double), ("n_wplanes", c_int32), ("g_mode", c_int32),
                 ("precision", c_int32), ("tile", c_int32), ("M", c_int64), ("n_blocks", c_int32),
                 ("block_offsets", c_void_p), ("facet_core", c_int32), ("facet_halo", c_int32),
-                ("item_vis", c_int32), ("n_wstacks", c_int32)]
+                ("item_vis", c_int32), ("n_wstacks", c_int32), ("grid_form", c_int32)]
 
 
 class ri_solve_opts(ctypes.Structure):
@@ -236,7 +237,8 @@ def _vis(ctx, t, name):
 
 def plan_desc(N: int, M: int, *, cell_rad: float = 0.0, w_max: float = 0.0, n_wplanes: int = 1,
               hmax: int = 5, g_mode: int = RI_G_CSR, precision: int = 32, tile: int = 0, n_blocks: int = 1,
-              facet_core: int = 0, facet_halo: int = 0, item_vis: int = 0, n_wstacks: int = 0) -> ri_plan_desc:
+              facet_core: int = 0, facet_halo: int = 0, item_vis: int = 0, n_wstacks: int = 0,
+              grid_form: int = RI_GRID_GATHER) -> ri_plan_desc:
     d = ri_plan_desc()
     d.N, d.oversample, d.kb_support, d.hmax = N, 2, 7, hmax
     d.cell_rad, d.w_max, d.n_wplanes = cell_rad, w_max, n_wplanes
@@ -246,6 +248,7 @@ def plan_desc(N: int, M: int, *, cell_rad: float = 0.0, w_max: float = 0.0, n_wp
     d.facet_core, d.facet_halo = facet_core, facet_halo
     d.item_vis = item_vis
     d.n_wstacks = n_wstacks
+    d.grid_form = grid_form
     return d
 
 

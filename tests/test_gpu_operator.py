@@ -92,6 +92,53 @@ def test_gram(case, prec, mode):
     assert err <= TOL_GRAM[prec]
 
 
+# FP32 gridding forms: the scatter form (FP64 LDS atomics) chosen explicitly,
+# and the gather form on a 32-cell subgrid side (tile 16: four cells a side
+# per lane); tile 32 falls back to the scatter form
+FORMS = [(R.RI_G_OTF, R.RI_GRID_SCATTER, 0), (R.RI_G_SEP, R.RI_GRID_SCATTER, 0),
+         (R.RI_G_OTF, R.RI_GRID_GATHER, 16), (R.RI_G_SEP, R.RI_GRID_GATHER, 16),
+         (R.RI_G_OTF, R.RI_GRID_GATHER, 32)]
+
+
+@pytest.mark.parametrize("mode,form,tile", FORMS)
+@pytest.mark.parametrize("case", [wide, edge], ids=["wide", "edge"])
+def test_grid_forms_fp32(case, mode, form, tile):
+    c = case()
+    d = R.plan_desc(c.N, c.M, cell_rad=c.cell, w_max=c.W, n_wplanes=c.n_wplanes, precision=32, g_mode=mode,
+                    tile=tile, grid_form=form)
+    ctx = R.ri_create(d, c.uvw)
+    x = _img(np.zeros((c.N, c.N)), 32)
+    R.phi_adjoint(ctx, _vis(c.y, 32), x)
+    e_adj = rel(x.cpu().numpy(), c.adj_y)
+    g = _img(np.zeros((c.N, c.N)), 32)
+    r2 = torch.zeros(1, dtype=torch.float64, device=DEV)
+    R.ri_gradient(ctx, _img(c.xr, 32), _vis(c.y, 32), g, r2)
+    gref, rref = c.grad_x
+    e_g = rel(g.cpu().numpy(), gref)
+    e_r = abs(float(r2.item()) - rref) / rref
+    print(f"{c.name} mode {mode} form {form} tile {R.ri_get_plan_stats(ctx).tile}: Phi^dagger {e_adj:.3e}, "
+          f"gradient {e_g:.3e}, ||r||^2 {e_r:.3e}")
+    assert e_adj <= TOL_PHI[32]
+    assert e_g <= TOL_GRAM[32]
+    assert e_r <= 5e-6
+
+
+def test_gather_and_scatter_forms_agree():
+    # the two forms sum the same FP32 products in a different order
+    c = wide()
+    out = {}
+    for form in (R.RI_GRID_GATHER, R.RI_GRID_SCATTER):
+        d = R.plan_desc(c.N, c.M, cell_rad=c.cell, w_max=c.W, n_wplanes=c.n_wplanes, precision=32,
+                        g_mode=R.RI_G_OTF, tile=8, grid_form=form)
+        ctx = R.ri_create(d, c.uvw)
+        g = _img(np.zeros((c.N, c.N)), 32)
+        R.ri_gradient(ctx, _img(c.xr, 32), _vis(c.y, 32), g)
+        out[form] = g.cpu().numpy()
+    err = rel(out[R.RI_GRID_GATHER], out[R.RI_GRID_SCATTER])
+    print(f"gather against scatter: rel l2 {err:.3e}")
+    assert err <= 2e-6
+
+
 @pytest.mark.parametrize("prec,mode", MODES)
 def test_gradient_with_data_and_residual(prec, mode):
     c = wide()

@@ -132,11 +132,26 @@ __device__ __forceinline__ T sum16(T v) {
     return v;
 }
 
-// Lane N of the caller's 16-lane DPP row, broadcast to the whole row.
-template <int N, typename T>
-__device__ __forceinline__ T row_share(T v) { return dpp_f<0x150 + N>(v); }
-template <int N, typename T>
-__device__ __forceinline__ cx<T> row_share(cx<T> v) { return mk<T>(row_share<N>(v.x), row_share<N>(v.y)); }
+// Lane N of the caller's 16-lane DPP row, broadcast to the whole row
+// (row_newbcast, which gfx950 also performs on 64-bit operands: one
+// v_mov_b64_dpp per complex float or double).
+template <int N>
+__device__ __forceinline__ float row_share(float v) { return dpp_f<0x150 + N>(v); }
+template <int N>
+__device__ __forceinline__ long long row_share64(long long v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x150 + N, 0xF, 0xF, false);
+}
+template <int N>
+__device__ __forceinline__ double row_share(double v) {
+    return __builtin_bit_cast(double, row_share64<N>(__builtin_bit_cast(long long, v)));
+}
+template <int N>
+__device__ __forceinline__ cx<float> row_share(cx<float> v) {
+    static_assert(sizeof(cx<float>) == 8, "complex float is two packed floats");
+    return __builtin_bit_cast(cx<float>, row_share64<N>(__builtin_bit_cast(long long, v)));
+}
+template <int N>
+__device__ __forceinline__ cx<double> row_share(cx<double> v) { return mk<double>(row_share<N>(v.x), row_share<N>(v.y)); }
 
 // f(integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time.
 template <typename F, int... I>
@@ -350,9 +365,18 @@ k_tiles(TileArgs<T> a) {
                     // come in pairs (S is odd), so loads issue two at a time.
                     const cx<T> *xp = Xs + base + min(lane, S - 1);
                     cx<T> accv = mk<T>((T)0, (T)0);
-                    cx<T> xv[7];
-                    static_for<7>([&](auto J) { xv[J] = xp[J * W]; });
-                    static_for<7>([&](auto J) { accv = cmac(accv, row_share<decltype(J)::value>(gv), xv[J]); });
+                    // rows 0..6 in two batches of loads (4, then 3), which
+                    // keeps the gather-form kernel's registers within 96
+                    {
+                        cx<T> xv[4];
+                        static_for<4>([&](auto J) { xv[J] = xp[J * W]; });
+                        static_for<4>([&](auto J) { accv = cmac(accv, row_share<decltype(J)::value>(gv), xv[J]); });
+                    }
+                    {
+                        cx<T> xv[3];
+                        static_for<3>([&](auto J) { xv[J] = xp[(4 + J) * W]; });
+                        static_for<3>([&](auto J) { accv = cmac(accv, row_share<4 + decltype(J)::value>(gv), xv[J]); });
+                    }
                     static_for<5>([&](auto P) {
                         constexpr int y0 = 7 + 2 * decltype(P)::value, y1 = y0 + 1;
                         if (y0 < S) {
@@ -388,7 +412,9 @@ k_tiles(TileArgs<T> a) {
                     if (lane == 0) {
                         ps[16] = mulc(r, gu16);
                         ps[LEN + 16] = gv16;
-                        sorg[grp] = (cu - item.tx0 + a.H - h - 3) | ((cv - item.ty0 + a.H - h - 3) << 16);
+                        // where the gather reads: slot entries of P[-bx] and g_v[-by]
+                        sorg[grp] = (grp * SLOT + PAD - (cu - item.tx0 + a.H - h - 3)) |
+                                    ((grp * SLOT + LEN + PAD - (cv - item.ty0 + a.H - h - 3)) << 16);
                     }
                 } else if (OP & OP_GRID) {
                     // Y[ay][c] += r conj(g_v[ay] g_u[c])
@@ -479,7 +505,7 @@ k_tiles(TileArgs<T> a) {
             ps[lane] = mk<T>((T)0, (T)0);
             if (lane == 0) {
                 ps[16] = mk<T>((T)0, (T)0);
-                sorg[grp] = 0;
+                sorg[grp] = (grp * SLOT) | ((grp * SLOT + LEN) << 16);
             }
           }
           if constexpr (GA) {
@@ -497,8 +523,8 @@ k_tiles(TileArgs<T> a) {
 #pragma unroll TILES_GA_UNROLL
             for (int s4 = 0; s4 < 4; ++s4) {
                 const int org = s4 == 0 ? o4.x : (s4 == 1 ? o4.y : (s4 == 2 ? o4.z : o4.w));
-                const cx<T> *pp = slot + (sb + s4) * SLOT + PAD - (org & 0xFFFF) + NB * lx;
-                const cx<T> *qq = slot + (sb + s4) * SLOT + LEN + PAD - (org >> 16) + NB * ly;
+                const cx<T> *pp = slot + (org & 0xFFFF) + NB * lx;
+                const cx<T> *qq = slot + (org >> 16) + NB * ly;
                 cx<T> p[NB], q[NB];
                 static_for<NB>([&](auto J) { p[J] = pp[J]; q[J] = qq[J]; });
                 // Y += p conj(q), two FMAs per component

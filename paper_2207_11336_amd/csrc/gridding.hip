@@ -38,6 +38,9 @@ constexpr int KB_TERMS_MAX = 32;
 #ifndef TILES_GA_WAVES
 #define TILES_GA_WAVES 5           // waves per SIMD the gather-form kernels are compiled for
 #endif
+#ifndef TILES_CSR_WAVES
+#define TILES_CSR_WAVES 4          // waves per SIMD the FP32 stored-G kernels are compiled for
+#endif
 #ifndef TILES_GA_UNROLL
 #define TILES_GA_UNROLL 1          // gather slots unrolled together
 #endif
@@ -206,7 +209,7 @@ __device__ __forceinline__ void axis_weights(const TileArgs<T> &a, int m, int pl
 // workgroups more per CU) hide the LDS latency; the others are left free (1).
 template <typename T, int GM, int GB>
 constexpr int tiles_min_waves() {
-    return GB > 0 ? TILES_GA_WAVES : (std::is_same<T, float>::value && GM != RI_G_CSR ? 8 : 1);
+    return GB > 0 ? TILES_GA_WAVES : (std::is_same<T, float>::value ? (GM != RI_G_CSR ? 8 : TILES_CSR_WAVES) : 1);
 }
 
 // LDS of the gather form: per group a slot with the padded vectors P and g_v
@@ -283,11 +286,21 @@ k_tiles(TileArgs<T> a) {
 
         // the group's next record (and on the fly its fraction: lane l < 8 the
         // u one, 8.. the v one) is loaded one visibility ahead
+        // with its data value (subtracted when fused, gridded when gridding;
+        // with G stored the data are read where used, which keeps that
+        // kernel's registers within four waves)
+        auto ydata = [&](int mm) -> cx<T> {
+            if (OP == OP_GRID) return a.yuser[a.perm[mm]];
+            if (a.ysorted) return a.ysorted[mm];
+            if (a.yuser) return a.yuser[a.perm[mm]];
+            return mk<T>((T)0, (T)0);
+        };
         uint2 rec_n = make_uint2(0u, 0u);
         T f_n = (T)0;
-        cx<T> su_n = mk<T>((T)0, (T)0), sv_n = su_n, su16_n = su_n, sv16_n = su_n;
+        cx<T> su_n = mk<T>((T)0, (T)0), sv_n = su_n, su16_n = su_n, sv16_n = su_n, y_n = su_n;
         if (grp < item.vc) {
             rec_n = a.rec[item.vb + grp];
+            if ((OP & OP_GRID) && GM != RI_G_CSR) y_n = ydata(item.vb + grp);
             if (OTF) f_n = a.frac[2 * (size_t)(item.vb + grp) + (lane >> 3)];
             if (SEP) sep_load(a.sepw, item.vb + grp, lane, su_n, sv_n, su16_n, sv16_n);
         }
@@ -298,6 +311,7 @@ k_tiles(TileArgs<T> a) {
           if (!GA || vi < item.vc) {
             const int m = item.vb + vi;
             const uint2 rec = rec_n;
+            const cx<T> yv = y_n;
             const T f = f_n;
             const int cu = (int)(rec.x & 0xFFFFu), cv = (int)(rec.x >> 16);
             const int pl = (int)(rec.y & 0xFFFFu), h = (int)((rec.y >> 16) & 0xFu);
@@ -316,6 +330,7 @@ k_tiles(TileArgs<T> a) {
                     gv16 = sv16_n;
                     if (vi + GROUPS < item.vc) {
                         rec_n = a.rec[m + GROUPS];
+                        if (OP & OP_GRID) y_n = ydata(m + GROUPS);
                         sep_load(a.sepw, m + GROUPS, lane, su_n, sv_n, su16_n, sv16_n);
                     }
                 } else {
@@ -335,6 +350,7 @@ k_tiles(TileArgs<T> a) {
                 if (lane <= 2 * h) wk[lane] = a.wtaps[(size_t)pl * (2 * a.hmax + 1) + a.hmax - h + lane];
                 if (vi + GROUPS < item.vc) {
                     rec_n = a.rec[m + GROUPS];
+                    if (OP & OP_GRID) y_n = ydata(m + GROUPS);
                     f_n = a.frac[2 * (size_t)(m + GROUPS) + (lane >> 3)];
                 }
                 // one Horner series for all 14 taps (lanes 7 and 15 compute an
@@ -396,12 +412,10 @@ k_tiles(TileArgs<T> a) {
                 if (OP == OP_DEGRID) {
                     if (lane == 0) a.yout[a.perm[m]] = acc;
                 } else if (OP == OP_FUSED) {
-                    r = acc;
-                    if (a.ysorted) r = r - a.ysorted[m];
-                    else if (a.yuser) r = r - a.yuser[a.perm[m]];
+                    r = acc - yv;
                     if (lane == 0) r2 += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
                 } else {
-                    r = a.yuser[a.perm[m]];
+                    r = yv;
                 }
                 if (GA) {
                     // publish P = r conj(g_u), g_v and the window origin in the
@@ -450,6 +464,8 @@ k_tiles(TileArgs<T> a) {
                 // (ay, ax) of entry t advances by 16 entries per slot without a
                 // division: 16 = q16 S + (16 - q16 S), q16 = floor(16 / S).
                 if (vi + GROUPS < item.vc) rec_n = a.rec[m + GROUPS];
+                // the data value is issued with the row, ahead of the sum
+                const cx<T> ydv = (OP & OP_GRID) ? ydata(m) : mk<T>((T)0, (T)0);
                 const cx<T> *gp = a.gval + a.rowptr[m];
                 cx<T> wv[MAXI];
 #pragma unroll
@@ -475,12 +491,10 @@ k_tiles(TileArgs<T> a) {
                 if (OP == OP_DEGRID) {
                     if (lane == 0) a.yout[a.perm[m]] = acc;
                 } else if (OP == OP_FUSED) {
-                    r = acc;
-                    if (a.ysorted) r = r - a.ysorted[m];
-                    else if (a.yuser) r = r - a.yuser[a.perm[m]];
+                    r = acc - ydv;
                     if (lane == 0) r2 += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
                 } else {
-                    r = a.yuser[a.perm[m]];
+                    r = ydv;
                 }
                 if (OP & OP_GRID) {
                     int ay = ay0, ax = ax0;

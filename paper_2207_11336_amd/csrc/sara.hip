@@ -58,6 +58,10 @@ __device__ __forceinline__ void static_for_(F &&f, std::integer_sequence<int, I.
 template <int N, typename F>
 __device__ __forceinline__ void static_for(F &&f) { static_for_(f, std::make_integer_sequence<int, N>{}); }
 
+// 16 bytes of T as one LDS vector load.
+template <typename T>
+using vec16 = T __attribute__((ext_vector_type(16 / sizeof(T))));
+
 enum { FIN_DUAL = 0, FIN_WEIGHT = 1, FIN_COEF = 2 };
 enum { SYN_PROX = 0, SYN_PLAIN = 1 };
 
@@ -131,6 +135,81 @@ __global__ void __launch_bounds__(256) k_ana_rows(const T *__restrict__ in, int6
             dst[half + k] = d;
         }
     });
+}
+
+// Register-blocked row analysis (n a multiple of 8). The row is staged in LDS
+// with a periodic tail, s[e] = row[e mod n] for e < n + AH; a lane computes the
+// four output pairs k = 4 j .. 4 j + 3 from the window s[8 j .. 8 j + 24)
+// (outputs need s[2 k + t], t < L <= 16) read as 16-byte vectors, and stores
+// each half as one 4-element vector. ALLB: the eight bases share the input
+// row (the finest level) and one workgroup computes all of them; otherwise
+// one workgroup per row and basis (blockIdx.z).
+constexpr int AH = 16;
+constexpr int AWIN = 24;
+
+template <typename T>
+using vec4o = T __attribute__((ext_vector_type(4)));
+
+template <typename T, int L>
+__device__ __forceinline__ void ana_row_block(int b, const T *s, T (&a)[4], T (&d)[4]) {
+    constexpr int E = 16 / sizeof(T);
+    T w[AWIN];
+#pragma unroll
+    for (int i = 0; i < AWIN / E; ++i) {
+        const vec16<T> v = reinterpret_cast<const vec16<T> *>(s)[i];
+#pragma unroll
+        for (int e = 0; e < E; ++e) w[i * E + e] = v[e];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        T aa = 0, dd = 0;
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+            aa = fma(fh<T>(b, t), w[2 * u + t], aa);
+            dd = fma(fg<T>(b, t), w[2 * u + t], dd);
+        }
+        a[u] = aa;
+        d[u] = dd;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store4(T *p, const T (&v)[4]) {
+    vec4o<T> o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[e] = v[e];
+    *reinterpret_cast<vec4o<T> *>(p) = o;
+}
+
+template <typename T, int ALLB>
+__global__ void __launch_bounds__(256) k_ana_rows_rb(const T *__restrict__ in, int64_t in_bs, T *__restrict__ tmp,
+                                                     int N, int n) {
+    extern __shared__ unsigned char smem_raw[];
+    T *s = reinterpret_cast<T *>(smem_raw);
+    const int row = blockIdx.y, half = n >> 1, m = n - 1, tid = threadIdx.x;
+    const int b0 = ALLB ? 0 : (int)blockIdx.z;
+    const T *src = in + b0 * in_bs + (size_t)row * N;
+    for (int e = tid; e < n + AH; e += blockDim.x) s[e] = src[e & m];
+    __syncthreads();
+    const size_t NN = (size_t)N * N;
+    auto basis = [&](int b, auto Lc) {
+        constexpr int L = decltype(Lc)::value;
+        T *dst = tmp + (size_t)b * NN + (size_t)row * N;
+        for (int j = tid; 4 * j < half; j += blockDim.x) {
+            T a[4], d[4];
+            ana_row_block<T, L>(b, s + 8 * j, a, d);
+            store4<T>(dst + 4 * j, a);
+            store4<T>(dst + half + 4 * j, d);
+        }
+    };
+    if (ALLB) {
+        static_for<NW>([&](auto bc) {
+            constexpr int b = decltype(bc)::value;
+            basis(b, std::integral_constant<int, 2 * (b + 1)>{});
+        });
+    } else {
+        with_length(b0, [&](auto Lc) { basis(b0, Lc); });
+    }
 }
 
 // Column analysis: tmp -> low-low block into work (unless last) and every
@@ -269,8 +348,6 @@ __global__ void __launch_bounds__(64) k_syn_rows_small(const T *__restrict__ tmp
 constexpr int RH = 8;
 constexpr int RWIN = 12;
 
-template <typename T>
-using vec16 = T __attribute__((ext_vector_type(16 / sizeof(T))));
 template <typename T>
 using vec8o = T __attribute__((ext_vector_type(8)));   // the 8 outputs of a lane block
 
@@ -521,7 +598,15 @@ void analysis(ri_ctx *c, const T *x, T *dst9, T par, bool dirac, hipStream_t s) 
         const int n = N >> l;
         const T *in = l == 0 ? x : work;
         const int64_t in_bs = l == 0 ? 0 : (int64_t)N * N;
-        hipLaunchKernelGGL(k_ana_rows<T>, dim3(1, n, NW), dim3(256), sizeof(T) * n, s, in, in_bs, tmp, N, n);
+        if (n % 8 != 0)
+            hipLaunchKernelGGL(k_ana_rows<T>, dim3(1, n, NW), dim3(256), sizeof(T) * n, s, in, in_bs, tmp, N, n);
+        else if (l == 0)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ana_rows_rb<T, 1>), dim3(1, n, 1), dim3(256),
+                               sizeof(T) * (n + AH), s, in, in_bs, tmp, N, n);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ana_rows_rb<T, 0>), dim3(1, n, NW),
+                               dim3(std::min(256, std::max(64, n / 8))), sizeof(T) * (n + AH), s, in, in_bs, tmp,
+                               N, n);
         const int kb = col_block(n), last = l == LEVELS - 1 ? 1 : 0;
         const dim3 g(cdiv(n, 64), cdiv(n / 2, 4 * kb), NW);
         if (kb == 8)

@@ -41,9 +41,6 @@ constexpr int KB_TERMS_MAX = 32;
 #ifndef TILES_CSR_WAVES
 #define TILES_CSR_WAVES 4          // waves per SIMD the FP32 stored-G kernels are compiled for
 #endif
-#ifndef TILES_GA_UNROLL
-#define TILES_GA_UNROLL 1          // gather slots unrolled together
-#endif
 
 
 template <typename T>
@@ -534,21 +531,33 @@ k_tiles(TileArgs<T> a) {
             wave_sync();
             const int wl = tid & 63, lx = wl & 7, ly = wl >> 3, sb = grp & ~3;
             const int4 o4 = *reinterpret_cast<const int4 *>(sorg + sb);
-#pragma unroll TILES_GA_UNROLL
-            for (int s4 = 0; s4 < 4; ++s4) {
-                const int org = s4 == 0 ? o4.x : (s4 == 1 ? o4.y : (s4 == 2 ? o4.z : o4.w));
-                const cx<T> *pp = slot + (org & 0xFFFF) + NB * lx;
-                const cx<T> *qq = slot + (org >> 16) + NB * ly;
-                cx<T> p[NB], q[NB];
+            // software-pipelined: the next slot's vectors load while this
+            // slot's products accumulate
+            cx<T> p[NB], q[NB];
+            {
+                const cx<T> *pp = slot + (o4.x & 0xFFFF) + NB * lx;
+                const cx<T> *qq = slot + (o4.x >> 16) + NB * ly;
                 static_for<NB>([&](auto J) { p[J] = pp[J]; q[J] = qq[J]; });
-                // Y += p conj(q), two FMAs per component
+            }
+            static_for<4>([&](auto S4) {
+                constexpr int s4 = decltype(S4)::value;
+                cx<T> pn[NB], qn[NB];
+                if constexpr (s4 < 3) {
+                    const int org = s4 == 0 ? o4.y : (s4 == 1 ? o4.z : o4.w);
+                    const cx<T> *pp = slot + (org & 0xFFFF) + NB * lx;
+                    const cx<T> *qq = slot + (org >> 16) + NB * ly;
+                    static_for<NB>([&](auto J) { pn[J] = pp[J]; qn[J] = qq[J]; });
+                }
                 static_for<NB>([&](auto I) {
                     static_for<NB>([&](auto J) {
                         gacc[I][J].x = fma(p[J].x, q[I].x, fma(p[J].y, q[I].y, gacc[I][J].x));
                         gacc[I][J].y = fma(p[J].y, q[I].x, fma(-p[J].x, q[I].y, gacc[I][J].y));
                     });
                 });
-            }
+                if constexpr (s4 < 3) {
+                    static_for<NB>([&](auto J) { p[J] = pn[J]; q[J] = qn[J]; });
+                }
+            });
             wave_sync();   // the slots are rewritten by the next four visibilities
           }
         }

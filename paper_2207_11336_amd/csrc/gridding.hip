@@ -9,14 +9,17 @@
 // kappa the Kaiser-Bessel kernel (J = 7) and k_w the w-plane taps.
 //
 // Work item = one uv tile (T x T cells) of one data block, or a chunk of it.
-// A workgroup stages the item's input subgrid X (T + 2H)^2 and an output
-// subgrid Y in LDS, walks the item's visibilities (one 16-lane group per
-// visibility), and flushes Y to the global grid with float atomics.
+// A workgroup stages the item's input subgrid X (T + 2H)^2 in LDS, walks the
+// item's visibilities (one 16-lane group per visibility), accumulates the
+// output subgrid Y and flushes it to the global grid with float atomics.
 // Workgroups pull items from a global counter (persistent launch), largest
 // items first. With G stored (CSR) the taps are spread over the lanes in row
-// order; on the fly, lane c of the group owns window column c, holds g_u[c]
-// and g_v[c] in registers and receives each row weight by a DPP broadcast,
-// so the weights never pass through LDS.
+// order; on the fly, or with the axis factors stored, lane c of the group owns
+// window column c, holds g_u[c] and g_v[c] in registers and receives each row
+// weight by a DPP broadcast, so the weights never pass through LDS.
+// Y accumulates either in FP64 LDS planes by atomic adds (scatter form) or,
+// for separable rows in FP32, in registers: every wave holds the whole
+// subgrid and gathers its visibilities' outer products (gather form).
 //
 // The same row weights fill the stored G (k_fill_csr) and the holographic
 // matrix H = G^H G of appendix E (k_fill_holo; its storage and banded product
@@ -202,8 +205,9 @@ __device__ __forceinline__ void axis_weights(const TileArgs<T> &a, int m, int pl
 }
 
 // Minimum waves per SIMD the register allocation must allow: the FP32
-// on-the-fly variants fit 64 VGPRs without spilling, which lets 8 waves (two
-// workgroups more per CU) hide the LDS latency; the others are left free (1).
+// scatter-form variants with separable rows fit 64 VGPRs without spilling (8
+// waves), the gather form 96 (TILES_GA_WAVES), the FP32 stored-G kernels 128
+// (TILES_CSR_WAVES); FP64 is left free (1).
 template <typename T, int GM, int GB>
 constexpr int tiles_min_waves() {
     return GB > 0 ? TILES_GA_WAVES : (std::is_same<T, float>::value ? (GM != RI_G_CSR ? 8 : TILES_CSR_WAVES) : 1);
@@ -228,11 +232,11 @@ k_tiles(TileArgs<T> a) {
     // All LDS is dynamic and starts at byte 0: a static __shared__ variable
     // would shift the dynamic block by its size and misalign the 8-byte
     // atomics on the subgrid. Layout: Xs (input subgrid, T), Yr and Yi (output
-    // subgrid, FP64 real and imaginary planes), then per group the KB taps,
-    // w-taps and axis weights, then reduction slots and the item slot (every
-    // part a multiple of 16 bytes). The output accumulates in FP64 for both
-    // precisions: on gfx950 an LDS FP64 atomic add costs ~8 cycles per wave
-    // against ~190 for FP32.
+    // subgrid, FP64 real and imaginary planes), then per group the w-taps,
+    // then reduction slots and the item slot (every part a multiple of 16
+    // bytes). The scatter form accumulates in FP64 for both precisions: on
+    // gfx950 an LDS FP64 atomic add costs ~8 cycles per wave against ~190 for
+    // FP32.
     // The gather form keeps X's region also when only gridding (it holds a
     // partial subgrid at the item's end) and has slots instead of Yr, Yi.
     extern __shared__ unsigned char smem_raw[];

@@ -286,10 +286,10 @@ k_tiles(TileArgs<T> a) {
         }
 
         // the group's next record (and on the fly its fraction: lane l < 8 the
-        // u one, 8.. the v one) is loaded one visibility ahead
-        // with its data value (subtracted when fused, gridded when gridding;
-        // with G stored the data are read where used, which keeps that
-        // kernel's registers within four waves)
+        // u one, 8.. the v one) is loaded one visibility ahead, with its data
+        // value (subtracted when fused, gridded when gridding); with G stored
+        // the data value is issued with the row instead, which keeps that
+        // kernel's registers within four waves
         auto ydata = [&](int mm) -> cx<T> {
             if (OP == OP_GRID) return a.yuser[a.perm[mm]];
             if (a.ysorted) return a.ysorted[mm];

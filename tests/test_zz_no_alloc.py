@@ -70,6 +70,18 @@ def test_noalloc_matches_gradient_twice_second_smaller(prec, tol):
     small.close()
 
 
+@pytest.mark.parametrize("prec,tol", [(32, 1e-6), (64, 1e-13)])
+def test_noalloc_axis_factors_twice_second_smaller(prec, tol):
+    # G as stored axis factors (FP32: the gather-form tile kernel)
+    big, xb, yb = _case(128, 20000, prec, R.RI_G_SEP, 7)
+    small, xs, ys = _case(64, 3001, prec, R.RI_G_SEP, 11)
+    e_big = _compare(big, xb, yb, tol)
+    e_small = _compare(small, xs, ys, tol)
+    print(f"FP{prec} axis factors: 128^2 {e_big}, then 64^2 {e_small}")
+    big.close()
+    small.close()
+
+
 def test_noalloc_workspace_limits():
     # FP32 at N' = 2048 fills 64 MiB of the 72 MiB workspace: accepted
     ctx, x, y = _case(1024, 4000, 32, R.RI_G_OTF, 21)

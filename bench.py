@@ -321,7 +321,7 @@ def train_pnp_denoiser(args, synth, sigma, device):
     t0 = time.perf_counter()
     params, hist = train_denoiser(patches, sigma, steps=args.train_steps, batch=batch, lr=args.train_lr,
                                   lr_min=args.train_lr / 100, log_every=max(1, args.train_steps // 4), log=log,
-                                  fne_lambda=args.fne_lambda, fne_iters=4, fne_every=args.fne_every,
+                                  fne_lambda=args.fne_lambda, fne_iters=args.fne_iters, fne_every=args.fne_every,
                                   fne_point=args.fne_point)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
@@ -581,6 +581,8 @@ def main():
     ap.add_argument("--fne-lambda", type=float, default=1e-6,
                     help="weight of the relaxed firm-nonexpansiveness penalty in the denoiser training (0: off)")
     ap.add_argument("--fne-every", type=int, default=4, help="penalised training step every this many steps")
+    ap.add_argument("--fne-iters", type=int, default=4,
+                    help="warm-started power iterations per penalised step (the Jacobian-norm estimate)")
     ap.add_argument("--fne-point", type=int, default=0, choices=[0, 1],
                     help="where the penalty takes the Jacobian: 0 the noisy training input, 1 random points between "
                          "the clean and the denoised images")

@@ -771,7 +771,7 @@ def main():
             ach = b / (r["tile_ms"] * 1e-3) / 1e9
             return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("csr", r["tile"]),
-                    "kernel": "k_tiles<float, fused, csr>", "bytes_per_launch": b, "avg_launch_ms": r["tile_ms"]}
+                    "kernel": "k_tiles<float, fused, csr, scatter>", "bytes_per_launch": b, "avg_launch_ms": r["tile_ms"]}
         if r["mode"] == "sep":
             # time at the HBM peak exceeds time at the FP32 vector peak, so HBM is the roofline bound
             b = sep_tile_bytes(r["nnz"], M, wl.Np)
@@ -779,7 +779,7 @@ def main():
             ach = b / (r["tile_ms"] * 1e-3) / 1e9
             return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("sep", r["tile"]),
-                    "kernel": "k_tiles<float, fused, sep>", "bytes_per_launch": b, "avg_launch_ms": r["tile_ms"],
+                    "kernel": "k_tiles<float, fused, sep, gather>", "bytes_per_launch": b, "avg_launch_ms": r["tile_ms"],
                     "flops_per_launch": fl,
                     "alu_frac": fl / (r["tile_ms"] * 1e-3) / 1e12 / FP32_VALU_PEAK_TFS}
         fl = otf_tile_flops(r["nnz"], M)
@@ -787,7 +787,7 @@ def main():
         hb = 24.0 * M + 16.0 * wl.Np * wl.Np
         return {"bound": "alu", "achieved": ach, "peak": FP32_VALU_PEAK_TFS, "unit": "TFLOP/s",
                 "frac": ach / FP32_VALU_PEAK_TFS, "traffic": measured_traffic("otf", r["tile"]),
-                "kernel": "k_tiles<float, fused, otf>", "flops_per_launch": fl, "avg_launch_ms": r["tile_ms"],
+                "kernel": "k_tiles<float, fused, otf, gather>", "flops_per_launch": fl, "avg_launch_ms": r["tile_ms"],
                 "hbm_bytes_per_launch": hb, "hbm_frac": hb / (r["tile_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     roof = roofline(best)
@@ -849,7 +849,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "N": N, "grid": wl.Np, "M": M, "g_mode": best["mode"], "nnz": st_nnz,
                    "w_stacks": max(args.wstacks, 1),
-                   "tile": best["tile"], "step": "fb_step: fused gradient + Haar-l1 prox + FP64 norms",
+                   "tile": best["tile"], "grid_form": "scatter" if best["mode"] == "csr" else "gather",
+                   "step": "fb_step: fused gradient + Haar-l1 prox + FP64 norms",
                    "roofline_other_modes": roof_other,
                    "fp64_gram_vis_per_s": fp64_rate, "plan_s": plan_s, "L": L, "snr_db": snr, **extra,
                    "fb_time_to_snr": fb_trace, "pnp": pnp, "holographic": holo},

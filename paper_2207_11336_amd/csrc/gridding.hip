@@ -115,9 +115,12 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Sum over the 16 lanes of a DPP row (quad swaps, then rotations by 4 and 8).
+// Every control used here reads a lane inside the row, so bound_ctrl never
+// applies; with it set (and old = 0) the compiler folds the move into the
+// consuming VALU instruction (v_add_f32_dpp).
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_f(double v) {
@@ -217,7 +220,8 @@ constexpr int tiles_min_waves() {
 // of its current visibility (complex arrays of LEN entries; the window's 17
 // entries start at PAD = W - 7, the rest reads zero), then the window origins.
 __host__ __device__ constexpr int ga_pad(int W) { return W - 7; }
-__host__ __device__ constexpr int ga_len(int W, int GB) { return (W - 7 + 8 * GB + 1) & ~1; }
+__host__ __device__ constexpr int ga_cover(int GB) { return 8 * GB; }   // subgrid side the lanes cover
+__host__ __device__ constexpr int ga_len(int W, int GB) { return (W - 7 + ga_cover(GB) + 1) & ~1; }
 __host__ __device__ constexpr int ga_slot_cx(int W, int GB) { return 2 * ga_len(W, GB); }
 
 // GM: RI_G_CSR (stored rows), RI_G_OTF (weights computed), RI_G_SEP (stored axis factors).
@@ -241,9 +245,15 @@ k_tiles(TileArgs<T> a) {
     // partial subgrid at the item's end) and has slots instead of Yr, Yi.
     extern __shared__ unsigned char smem_raw[];
     const int W = a.W, WW = W * W;
+    // row stride of the staged X: with stored axis factors in the gather form
+    // the covered side, a compile-time constant, so the degrid's row offsets
+    // are immediates (on the fly that costs the kernel a spilled register); W
+    // otherwise. The gather form's X region holds W x (covered side) entries.
+    constexpr int XSC = (GA && SEP) ? ga_cover(GB) : 0;
+    const int XS = XSC ? XSC : W;
     const int PAD = ga_pad(W), LEN = ga_len(W, GB), SLOT = ga_slot_cx(W, GB);
     cx<T> *Xs = reinterpret_cast<cx<T> *>(smem_raw);
-    double *Yr = reinterpret_cast<double *>(Xs + ((GA || (OP & OP_DEGRID)) ? WW : 0));
+    double *Yr = reinterpret_cast<double *>(Xs + (GA ? W * ga_cover(GB) : (OP & OP_DEGRID) ? WW : 0));
     double *Yi = Yr + ((!GA && (OP & OP_GRID)) ? WW : 0);
     cx<T> *slot = reinterpret_cast<cx<T> *>(Yi + ((!GA && (OP & OP_GRID)) ? WW : 0));
     int *sorg = reinterpret_cast<int *>(slot + (GA ? GROUPS * SLOT : 0));
@@ -269,7 +279,7 @@ k_tiles(TileArgs<T> a) {
         if (OP & OP_DEGRID) {
             for (int e = tid; e < WW; e += blockDim.x) {
                 const int r = e / W, cc = e - r * W;
-                Xs[e] = Xg[((size_t)((y0 + r) & Npm) << a.logNp) + ((x0 + cc) & Npm)];
+                Xs[r * XS + cc] = Xg[((size_t)((y0 + r) & Npm) << a.logNp) + ((x0 + cc) & Npm)];
             }
         }
         if (!GA && (OP & OP_GRID)) {
@@ -317,7 +327,7 @@ k_tiles(TileArgs<T> a) {
             const int cu = (int)(rec.x & 0xFFFFu), cv = (int)(rec.x >> 16);
             const int pl = (int)(rec.y & 0xFFFFu), h = (int)((rec.y >> 16) & 0xFu);
             const int S = 2 * h + 7, SS = S * S;
-            const int base = (cv - item.ty0 + a.H - h - 3) * W + (cu - item.tx0 + a.H - h - 3);
+            const int base = (cv - item.ty0 + a.H - h - 3) * XS + (cu - item.tx0 + a.H - h - 3);
             const int NI = (SS + 15) >> 4;
             cx<T> acc = mk<T>((T)0, (T)0);
             cx<T> r;
@@ -329,10 +339,13 @@ k_tiles(TileArgs<T> a) {
                     gv = sv_n;
                     gu16 = su16_n;
                     gv16 = sv16_n;
-                    if (vi + GROUPS < item.vc) {
-                        rec_n = a.rec[m + GROUPS];
-                        if (OP & OP_GRID) y_n = ydata(m + GROUPS);
-                        sep_load(a.sepw, m + GROUPS, lane, su_n, sv_n, su16_n, sv16_n);
+                    // (the item's last visibility again at its end: no branch,
+                    // so no register copies for the not-loaded case)
+                    {
+                        const int mn = item.vb + min(vi + GROUPS, item.vc - 1);
+                        rec_n = a.rec[mn];
+                        if (OP & OP_GRID) y_n = ydata(mn);
+                        sep_load(a.sepw, mn, lane, su_n, sv_n, su16_n, sv16_n);
                     }
                 } else {
                 // G row from its separable axis weights, all in registers:
@@ -386,26 +399,26 @@ k_tiles(TileArgs<T> a) {
                     // keeps the gather-form kernel's registers within 96
                     {
                         cx<T> xv[4];
-                        static_for<4>([&](auto J) { xv[J] = xp[J * W]; });
+                        static_for<4>([&](auto J) { xv[J] = xp[J * XS]; });
                         static_for<4>([&](auto J) { accv = cmac(accv, row_share<decltype(J)::value>(gv), xv[J]); });
                     }
                     {
                         cx<T> xv[3];
-                        static_for<3>([&](auto J) { xv[J] = xp[(4 + J) * W]; });
+                        static_for<3>([&](auto J) { xv[J] = xp[(4 + J) * XS]; });
                         static_for<3>([&](auto J) { accv = cmac(accv, row_share<4 + decltype(J)::value>(gv), xv[J]); });
                     }
                     static_for<5>([&](auto P) {
                         constexpr int y0 = 7 + 2 * decltype(P)::value, y1 = y0 + 1;
                         if (y0 < S) {
-                            const cx<T> x0 = xp[y0 * W], x1 = xp[y1 * W];
+                            const cx<T> x0 = xp[y0 * XS], x1 = xp[y1 * XS];
                             accv = cmac(accv, row_share<y0>(gv), x0);
                             accv = cmac(accv, y1 < 16 ? row_share<y1 & 15>(gv) : row_share<0>(gv16), x1);
                         }
                     });
                     acc = accv * gu;
                     if (S == 17) {
-                        acc = cmac(acc, gv * row_share<0>(gu16), Xs[base + lane * W + 16]);
-                        if (lane == 0) acc = cmac(acc, gv16 * gu16, Xs[base + 16 * W + 16]);
+                        acc = cmac(acc, gv * row_share<0>(gu16), Xs[base + lane * XS + 16]);
+                        if (lane == 0) acc = cmac(acc, gv16 * gu16, Xs[base + 16 * XS + 16]);
                     }
                     acc.x = sum16(acc.x);
                     acc.y = sum16(acc.y);
@@ -464,7 +477,7 @@ k_tiles(TileArgs<T> a) {
                 // window); its columns follow from the window. The window cell
                 // (ay, ax) of entry t advances by 16 entries per slot without a
                 // division: 16 = q16 S + (16 - q16 S), q16 = floor(16 / S).
-                if (vi + GROUPS < item.vc) rec_n = a.rec[m + GROUPS];
+                rec_n = a.rec[item.vb + min(vi + GROUPS, item.vc - 1)];
                 // the data value is issued with the row, ahead of the sum
                 const cx<T> ydv = (OP & OP_GRID) ? ydata(m) : mk<T>((T)0, (T)0);
                 const cx<T> *gp = a.gval + a.rowptr[m];
@@ -756,12 +769,13 @@ TileArgs<T> make_args(ri_ctx *c, const View &v, Prec<T> &p) {
 // Dynamic LDS of one k_tiles workgroup on a W x W subgrid (the layout at the
 // kernel's top): X (cx<T>) when degridding, the FP64 real and imaginary planes
 // when gridding, the groups' w-taps, the reduction slots and the item index.
-// The gather form (GB > 0) has X's region in every case, the groups' slots
-// and window origins in place of the FP64 planes.
+// The gather form (GB > 0) has X's region (W rows of its covered side) in
+// every case, the groups' slots and window origins in place of the FP64 planes.
 size_t tiles_lds(size_t W, bool degrid, bool grid, size_t cx_bytes, int GB = 0) {
     const size_t WW = W * W;
     if (GB > 0)
-        return cx_bytes * WW + cx_bytes * GROUPS * (size_t)ga_slot_cx((int)W, GB) + sizeof(int) * GROUPS +
+        return cx_bytes * W * (size_t)ga_cover(GB) + cx_bytes * GROUPS * (size_t)ga_slot_cx((int)W, GB) +
+               sizeof(int) * GROUPS +
                cx_bytes * GROUPS * SCR_W + 4 * sizeof(double) + 16;
     return cx_bytes * WW * (degrid ? 1 : 0) + 2 * sizeof(double) * WW * (grid ? 1 : 0) +
            cx_bytes * GROUPS * SCR_W + 4 * sizeof(double) + 16;
@@ -771,7 +785,7 @@ template <typename T, int OP, int GM, int GB>
 void launch_op_gb(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
     // the gather form's subgrid fits 8 GB cells a side, and its reduction
     // stores a W x W partial subgrid in the slots
-    if (GB > 0 && (a.W > 8 * GB || (size_t)a.W * a.W > (size_t)GROUPS * ga_slot_cx(a.W, GB)))
+    if (GB > 0 && (a.W > ga_cover(GB) || (size_t)a.W * a.W > (size_t)GROUPS * ga_slot_cx(a.W, GB)))
         throw Error(RI_EUNSUPPORTED, "gather-form tile kernel launched on a subgrid it does not cover");
     const size_t lds = tiles_lds((size_t)a.W, (OP & OP_DEGRID) != 0, (OP & OP_GRID) != 0, sizeof(cx<T>), GB);
     if (lds + 64 > (size_t)c->dev.lds_per_block)

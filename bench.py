@@ -49,6 +49,16 @@ def csr_tile_bytes(nnz: int, M: int, Np: int) -> float:
     return 8.0 * nnz + 22.0 * M + 16.0 * Np * Np
 
 
+def tile_form(mode: str, tile: int, hmax: int = 5) -> str:
+    """Gridding form the library runs in an FP32 context at this tile: the VALU
+    gather up to a 24-cell subgrid side (tile + 2 (hmax + 3)), the matrix-core
+    gather up to 32, the scatter form beyond that and with G stored."""
+    W = tile + 2 * (hmax + 3)
+    if mode == "csr" or W > 32:
+        return "scatter"
+    return "gather" if W <= 24 else "gather on the matrix cores"
+
+
 def measured_traffic(mode: str, tile: int):
     """HBM bytes per launch of the fused tile kernel from the committed rocprofv3
     counter summary, or None when the kernel source changed since it was taken
@@ -771,7 +781,8 @@ def main():
             ach = b / (r["tile_ms"] * 1e-3) / 1e9
             return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("csr", r["tile"]),
-                    "kernel": "k_tiles<float, fused, csr, scatter>", "bytes_per_launch": b, "avg_launch_ms": r["tile_ms"]}
+                    "kernel": f"k_tiles<float, fused, csr, {tile_form('csr', r['tile'])}>", "bytes_per_launch": b,
+                    "avg_launch_ms": r["tile_ms"]}
         if r["mode"] == "sep":
             # time at the HBM peak exceeds time at the FP32 vector peak, so HBM is the roofline bound
             b = sep_tile_bytes(r["nnz"], M, wl.Np)
@@ -779,7 +790,8 @@ def main():
             ach = b / (r["tile_ms"] * 1e-3) / 1e9
             return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("sep", r["tile"]),
-                    "kernel": "k_tiles<float, fused, sep, gather>", "bytes_per_launch": b, "avg_launch_ms": r["tile_ms"],
+                    "kernel": f"k_tiles<float, fused, sep, {tile_form('sep', r['tile'])}>", "bytes_per_launch": b,
+                    "avg_launch_ms": r["tile_ms"],
                     "flops_per_launch": fl,
                     "alu_frac": fl / (r["tile_ms"] * 1e-3) / 1e12 / FP32_VALU_PEAK_TFS}
         fl = otf_tile_flops(r["nnz"], M)
@@ -787,7 +799,8 @@ def main():
         hb = 24.0 * M + 16.0 * wl.Np * wl.Np
         return {"bound": "alu", "achieved": ach, "peak": FP32_VALU_PEAK_TFS, "unit": "TFLOP/s",
                 "frac": ach / FP32_VALU_PEAK_TFS, "traffic": measured_traffic("otf", r["tile"]),
-                "kernel": "k_tiles<float, fused, otf, gather>", "flops_per_launch": fl, "avg_launch_ms": r["tile_ms"],
+                "kernel": f"k_tiles<float, fused, otf, {tile_form('otf', r['tile'])}>", "flops_per_launch": fl,
+                "avg_launch_ms": r["tile_ms"],
                 "hbm_bytes_per_launch": hb, "hbm_frac": hb / (r["tile_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     roof = roofline(best)
@@ -849,7 +862,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "N": N, "grid": wl.Np, "M": M, "g_mode": best["mode"], "nnz": st_nnz,
                    "w_stacks": max(args.wstacks, 1),
-                   "tile": best["tile"], "grid_form": "scatter" if best["mode"] == "csr" else "gather",
+                   "tile": best["tile"], "grid_form": tile_form(best["mode"], best["tile"]),
                    "step": "fb_step: fused gradient + Haar-l1 prox + FP64 norms",
                    "roofline_other_modes": roof_other,
                    "fp64_gram_vis_per_s": fp64_rate, "plan_s": plan_s, "L": L, "snr_db": snr, **extra,

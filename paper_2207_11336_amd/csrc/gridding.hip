@@ -19,7 +19,8 @@
 // weight by a DPP broadcast, so the weights never pass through LDS.
 // Y accumulates either in FP64 LDS planes by atomic adds (scatter form) or,
 // for separable rows in FP32, in registers: every wave holds the whole
-// subgrid and gathers its visibilities' outer products (gather form).
+// subgrid and gathers its visibilities' outer products (gather form: on the
+// VALU for subgrids up to 24 a side, on the matrix cores up to 32).
 //
 // The same row weights fill the stored G (k_fill_csr) and the holographic
 // matrix H = G^H G of appendix E (k_fill_holo; its storage and banded product
@@ -44,6 +45,11 @@ constexpr int KB_TERMS_MAX = 32;
 #ifndef TILES_CSR_WAVES
 #define TILES_CSR_WAVES 4          // waves per SIMD the FP32 stored-G kernels are compiled for
 #endif
+#ifndef TILES_MF_WAVES
+#define TILES_MF_WAVES 4           // waves per SIMD the matrix-core gather kernels are compiled for
+#endif
+constexpr int GB_MF = 16;          // gridding-form code of the matrix-core gather (16 x 16 tiles)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 
 template <typename T>
@@ -209,30 +215,36 @@ __device__ __forceinline__ void axis_weights(const TileArgs<T> &a, int m, int pl
 
 // Minimum waves per SIMD the register allocation must allow: the FP32
 // scatter-form variants with separable rows fit 64 VGPRs without spilling (8
-// waves), the gather form 96 (TILES_GA_WAVES), the FP32 stored-G kernels 128
-// (TILES_CSR_WAVES); FP64 is left free (1).
+// waves), the VALU gather form 96 (TILES_GA_WAVES), the matrix-core gather
+// and the FP32 stored-G kernels 128 (TILES_MF_WAVES, TILES_CSR_WAVES); FP64 is
+// left free (1).
 template <typename T, int GM, int GB>
 constexpr int tiles_min_waves() {
-    return GB > 0 ? TILES_GA_WAVES : (std::is_same<T, float>::value ? (GM != RI_G_CSR ? 8 : TILES_CSR_WAVES) : 1);
+    return GB == GB_MF ? TILES_MF_WAVES
+           : GB > 0    ? TILES_GA_WAVES
+                       : (std::is_same<T, float>::value ? (GM != RI_G_CSR ? 8 : TILES_CSR_WAVES) : 1);
 }
 
 // LDS of the gather form: per group a slot with the padded vectors P and g_v
 // of its current visibility (complex arrays of LEN entries; the window's 17
 // entries start at PAD = W - 7, the rest reads zero), then the window origins.
 __host__ __device__ constexpr int ga_pad(int W) { return W - 7; }
-__host__ __device__ constexpr int ga_cover(int GB) { return 8 * GB; }   // subgrid side the lanes cover
+// subgrid side the lanes cover: 8 GB on the VALU, two 16-cell tiles on the matrix cores
+__host__ __device__ constexpr int ga_cover(int GB) { return GB == GB_MF ? 32 : 8 * GB; }
 __host__ __device__ constexpr int ga_len(int W, int GB) { return (W - 7 + ga_cover(GB) + 1) & ~1; }
 __host__ __device__ constexpr int ga_slot_cx(int W, int GB) { return 2 * ga_len(W, GB); }
 
 // GM: RI_G_CSR (stored rows), RI_G_OTF (weights computed), RI_G_SEP (stored axis factors).
 // GB = 0: scatter-form gridding (FP64 LDS atomics into the output subgrid).
-// GB = 3, 4: gather-form gridding (GB x GB output cells per lane; see the
-// comment at the gather).
+// GB = 3: gather-form gridding on the VALU (3 x 3 output cells per lane);
+// GB = GB_MF: gather-form gridding on the matrix cores (see the comments at
+// the gather).
 template <typename T, int OP, int GM, int GB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiles_min_waves<T, GM, GB>())))
 k_tiles(TileArgs<T> a) {
-    constexpr bool OTF = GM == RI_G_OTF, SEP = GM == RI_G_SEP, GA = GB > 0;
+    constexpr bool OTF = GM == RI_G_OTF, SEP = GM == RI_G_SEP, GA = GB > 0, MF = GB == GB_MF;
     static_assert(!GA || ((OP & OP_GRID) && GM != RI_G_CSR), "gather form: gridding with separable rows only");
+    static_assert(!MF || std::is_same<T, float>::value, "matrix-core gather: FP32 only");
     // All LDS is dynamic and starts at byte 0: a static __shared__ variable
     // would shift the dynamic block by its size and misalign the 8-byte
     // atomics on the subgrid. Layout: Xs (input subgrid, T), Yr and Yi (output
@@ -289,9 +301,15 @@ k_tiles(TileArgs<T> a) {
             for (int e = tid; e < GROUPS * SLOT; e += blockDim.x) slot[e] = mk<T>((T)0, (T)0);
         }
         __syncthreads();
-        constexpr int NB = GA ? GB : 1;
+        constexpr int NB = (GA && !MF) ? GB : 1;
         cx<T> gacc[NB][NB];
-        if (GA) {
+        f32x4 mre[2][2], mim[2][2];   // matrix-core gather: real and imaginary parts per tile
+        if constexpr (MF) {
+            static_for<2>([&](auto I) { static_for<2>([&](auto J) {
+                mre[I][J] = f32x4{0.f, 0.f, 0.f, 0.f};
+                mim[I][J] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }); });
+        } else if (GA) {
             static_for<NB>([&](auto I) { static_for<NB>([&](auto J) { gacc[I][J] = mk<T>((T)0, (T)0); }); });
         }
 
@@ -536,7 +554,40 @@ k_tiles(TileArgs<T> a) {
                 sorg[grp] = (grp * SLOT) | ((grp * SLOT + LEN) << 16);
             }
           }
-          if constexpr (GA) {
+          if constexpr (MF) {
+            // Gather-form gridding on the matrix cores: the same sum as below
+            // as v_mfma_f32_16x16x4_f32 products with K = the wave's four
+            // visibilities. Lane 16 v + c supplies visibility v (its own
+            // group's slot): A[c][v] = g_v of subgrid row 16 ty + c and
+            // B[v][c] = P of subgrid column 16 tx + c, so the product adds
+            // sum_v g_v[y] P_v[x] to tile (ty, tx) of the subgrid; the real
+            // part takes Re g Re P + Im g Im P, the imaginary part
+            // Re g Im P - Im g Re P (P conj g_v). Two tiles a side cover 32
+            // cells; 16 products per four visibilities, 4 LDS reads per lane.
+            wave_sync();
+            const int org = sorg[grp];
+            const cx<T> *pp = slot + (org & 0xFFFF) + lane;
+            const cx<T> *qq = slot + (org >> 16) + lane;
+            const cx<T> p0 = pp[0], p1 = pp[16], q0 = qq[0], q1 = qq[16];
+            static_for<2>([&](auto TY) {
+                constexpr int ty = decltype(TY)::value;
+                const cx<T> q = ty ? q1 : q0;
+                const float nqy = -q.y;
+                static_for<2>([&](auto TX) {
+                    constexpr int tx = decltype(TX)::value;
+                    const cx<T> p = tx ? p1 : p0;
+                    mre[ty][tx] = __builtin_amdgcn_mfma_f32_16x16x4f32(q.x, p.x, mre[ty][tx], 0, 0, 0);
+                    mim[ty][tx] = __builtin_amdgcn_mfma_f32_16x16x4f32(q.x, p.y, mim[ty][tx], 0, 0, 0);
+                });
+                static_for<2>([&](auto TX) {
+                    constexpr int tx = decltype(TX)::value;
+                    const cx<T> p = tx ? p1 : p0;
+                    mre[ty][tx] = __builtin_amdgcn_mfma_f32_16x16x4f32(q.y, p.y, mre[ty][tx], 0, 0, 0);
+                    mim[ty][tx] = __builtin_amdgcn_mfma_f32_16x16x4f32(nqy, p.x, mim[ty][tx], 0, 0, 0);
+                });
+            });
+            wave_sync();   // the slots are rewritten by the next four visibilities
+          } else if constexpr (GA) {
             // Gather-form gridding: each wave holds the whole output subgrid
             // in registers, lane l the GB x GB cells x = GB (l & 7) + j,
             // y = GB (l >> 3) + i, and adds for each of its four visibilities
@@ -585,6 +636,22 @@ k_tiles(TileArgs<T> a) {
             // two partial sums are added and flushed
             const int w = tid >> 6, wl = tid & 63, lx = wl & 7, ly = wl >> 3;
             cx<T> *R = (w & 1) ? slot : Xs;
+            if constexpr (MF) {
+                // lane l holds rows 4 (l / 16) + e, column l % 16 of each tile
+                auto put = [&](bool add) {
+                    static_for<2>([&](auto TY) { static_for<2>([&](auto TX) { static_for<4>([&](auto E) {
+                        constexpr int ty = decltype(TY)::value, tx = decltype(TX)::value, e = decltype(E)::value;
+                        const int y = 16 * ty + 4 * (wl >> 4) + e, x = 16 * tx + (wl & 15);
+                        if (x < W && y < W) {
+                            const cx<T> v = mk<T>(mre[ty][tx][e], mim[ty][tx][e]);
+                            R[y * W + x] = add ? R[y * W + x] + v : v;
+                        }
+                    }); }); });
+                };
+                if (w < 2) put(false);
+                __syncthreads();
+                if (w >= 2) put(true);
+            } else {
             if (w < 2) {
                 static_for<NB>([&](auto I) {
                     static_for<NB>([&](auto J) {
@@ -601,6 +668,7 @@ k_tiles(TileArgs<T> a) {
                         if (x < W && y < W) R[y * W + x] = R[y * W + x] + gacc[I][J];
                     });
                 });
+            }
             }
             __syncthreads();
             for (int e = tid; e < WW; e += blockDim.x) {
@@ -783,8 +851,8 @@ size_t tiles_lds(size_t W, bool degrid, bool grid, size_t cx_bytes, int GB = 0) 
 
 template <typename T, int OP, int GM, int GB>
 void launch_op_gb(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
-    // the gather form's subgrid fits 8 GB cells a side, and its reduction
-    // stores a W x W partial subgrid in the slots
+    // the gather form's subgrid fits the side its lanes cover, and its
+    // reduction stores a W x W partial subgrid in the slots
     if (GB > 0 && (a.W > ga_cover(GB) || (size_t)a.W * a.W > (size_t)GROUPS * ga_slot_cx(a.W, GB)))
         throw Error(RI_EUNSUPPORTED, "gather-form tile kernel launched on a subgrid it does not cover");
     const size_t lds = tiles_lds((size_t)a.W, (OP & OP_DEGRID) != 0, (OP & OP_GRID) != 0, sizeof(cx<T>), GB);
@@ -800,12 +868,13 @@ void launch_op_gb(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
 }
 
 // Gridding through separable rows in FP32 takes the gather form when the
-// subgrid fits it (W <= 32) unless the context asks for the scatter form.
+// subgrid fits it unless the context asks for the scatter form: on the VALU
+// up to 24 cells a side, on the matrix cores up to 32.
 template <typename T, int OP, int GM>
 void launch_op(ri_ctx *c, TileArgs<T> &a, hipStream_t s) {
     if constexpr (std::is_same<T, float>::value && GM != RI_G_CSR && (OP & OP_GRID) != 0) {
         if (c->d.grid_form == RI_GRID_GATHER && a.W <= 24) return launch_op_gb<T, OP, GM, 3>(c, a, s);
-        if (c->d.grid_form == RI_GRID_GATHER && a.W <= 32) return launch_op_gb<T, OP, GM, 4>(c, a, s);
+        if (c->d.grid_form == RI_GRID_GATHER && a.W <= 32) return launch_op_gb<T, OP, GM, GB_MF>(c, a, s);
     }
     launch_op_gb<T, OP, GM, 0>(c, a, s);
 }

@@ -93,8 +93,8 @@ def test_gram(case, prec, mode):
 
 
 # FP32 gridding forms: the scatter form (FP64 LDS atomics) chosen explicitly,
-# and the gather form on a 32-cell subgrid side (tile 16: four cells a side
-# per lane); tile 32 falls back to the scatter form
+# and the gather form on a 32-cell subgrid side (tile 16 at supports up to 17:
+# the matrix-core gather); tile 32 falls back to the scatter form
 FORMS = [(R.RI_G_OTF, R.RI_GRID_SCATTER, 0), (R.RI_G_SEP, R.RI_GRID_SCATTER, 0),
          (R.RI_G_OTF, R.RI_GRID_GATHER, 16), (R.RI_G_SEP, R.RI_GRID_GATHER, 16),
          (R.RI_G_OTF, R.RI_GRID_GATHER, 32)]
@@ -123,19 +123,22 @@ def test_grid_forms_fp32(case, mode, form, tile):
     assert e_r <= 5e-6
 
 
-def test_gather_and_scatter_forms_agree():
-    # the two forms sum the same FP32 products in a different order
+@pytest.mark.parametrize("mode,tile", [(R.RI_G_OTF, 8), (R.RI_G_OTF, 16), (R.RI_G_SEP, 8), (R.RI_G_SEP, 16)])
+def test_gather_and_scatter_forms_agree(mode, tile):
+    # the forms sum the same FP32 products in a different order (tile 8: the
+    # VALU gather on a 24-cell subgrid side, tile 16: the matrix-core gather
+    # on 32)
     c = wide()
     out = {}
     for form in (R.RI_GRID_GATHER, R.RI_GRID_SCATTER):
         d = R.plan_desc(c.N, c.M, cell_rad=c.cell, w_max=c.W, n_wplanes=c.n_wplanes, precision=32,
-                        g_mode=R.RI_G_OTF, tile=8, grid_form=form)
+                        g_mode=mode, tile=tile, grid_form=form)
         ctx = R.ri_create(d, c.uvw)
         g = _img(np.zeros((c.N, c.N)), 32)
         R.ri_gradient(ctx, _img(c.xr, 32), _vis(c.y, 32), g)
         out[form] = g.cpu().numpy()
     err = rel(out[R.RI_GRID_GATHER], out[R.RI_GRID_SCATTER])
-    print(f"gather against scatter: rel l2 {err:.3e}")
+    print(f"mode {mode} tile {tile}: gather against scatter: rel l2 {err:.3e}")
     assert err <= 2e-6
 
 

@@ -7,7 +7,9 @@ Re{Phi^dagger (Phi x - y)} = Re{Phi^dagger Phi} x - Re{Phi^dagger y}, one fused
 degrid -> residual -> grid pass on the GPU in the launch configuration the
 benchmark times (FP32, autotuned tile, default work items), for the stored,
 the on-the-fly and the axis-factor G and for the 64 uneven angular-sector blocks of eq. (E2) in
-one persistent launch. The oracle computes all three cases once (about 12 s
+one persistent launch; with the axis factors also at tiles 8 and 16 explicitly, so both gather
+forms (the VALU one on a 24-cell subgrid side, the matrix-core one on 32) are compared whichever
+tile the autotuner picks. The oracle computes all three cases once (about 12 s
 per gradient on 16 cores), so the dense uv core, where the GPU accumulates
 tens of visibilities per cell through FP64 LDS partial sums and FP32 global
 atomics, is compared as a whole.
@@ -58,7 +60,7 @@ def c1():
     return uvw, x, xr, y, ref
 
 
-@pytest.mark.parametrize("which", ["otf", "csr", "sep", "otf-64-blocks"])
+@pytest.mark.parametrize("which", ["otf", "csr", "sep", "sep-tile8", "sep-tile16", "otf-64-blocks"])
 def test_gradient_equals_oracle_at_full_size(c1, which):
     uvw, x, xr, y, ref = c1
     ctx, perm = _make_ctx(uvw, which)
@@ -105,8 +107,9 @@ def _make_ctx(uvw, which):
         return R.ri_create(R.plan_desc(WL.N, WL.M, g_mode=R.RI_G_OTF, **base), uvw), None
     if which == "csr":
         return R.ri_create(R.plan_desc(WL.N, WL.M, g_mode=R.RI_G_CSR, **base), uvw), None
-    if which == "sep":
-        return R.ri_create(R.plan_desc(WL.N, WL.M, g_mode=R.RI_G_SEP, **base), uvw), None
+    if which.startswith("sep"):
+        tile = int(which[len("sep-tile"):]) if which != "sep" else 0
+        return R.ri_create(R.plan_desc(WL.N, WL.M, g_mode=R.RI_G_SEP, tile=tile, **base), uvw), None
     W2 = synth.C2
     sizes = synth.block_sizes(W2.n_blocks, WL.M, W2.block_lo, W2.block_hi)
     perm, offs = synth.blocked(uvw, sizes)

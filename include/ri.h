@@ -76,7 +76,11 @@ typedef struct {
                               visibility, 34 complex values, computed once in FP64 */
     int32_t precision;     /* 32 or 64: element type of Phi, Phi^dagger and the FFT */
     int32_t tile;          /* uv tile side in grid cells (8..128, divides N'); 0 => autotuned at
-                              ri_create among 8, 16, 32 by timing fused gradient passes */
+                              ri_create among 8, 16, 32 by timing fused gradient passes (the
+                              side also selects the gridding form, see grid_form). The choice
+                              depends on the coverage; a caller creating several contexts on
+                              one coverage passes the tile found once (ri_get_plan_stats) and
+                              skips the timing. */
     int64_t M;             /* number of visibilities, >= 0 */
     int32_t n_blocks;      /* data blocks (eq. E1), >= 1 */
     const int64_t *block_offsets; /* host, n_blocks+1 ascending offsets into the caller's
@@ -95,8 +99,9 @@ typedef struct {
                               default): in FP32 with G on the fly or as stored axis factors and a
                               subgrid side tile + 2 (hmax + 3) <= 32, every wave keeps the whole
                               subgrid in FP32 registers and gathers its visibilities' separable
-                              contributions (no LDS atomics); other cases fall back to the scatter
-                              form. RI_GRID_SCATTER (1): each visibility's window is added into
+                              contributions (no LDS atomics): by VALU FMAs up to a side of 24, by
+                              FP32 matrix-core products (K = a wave's four visibilities) up to
+                              32; other cases fall back to the scatter form. RI_GRID_SCATTER (1): each visibility's window is added into
                               FP64 LDS planes by atomics. The two differ by FP32 rounding order. */
 } ri_plan_desc;
 

@@ -212,6 +212,9 @@ void build_main_view(ri_ctx *c, int tile) {
 // Tile autotuner: for each candidate tile side whose subgrids fit the
 // workgroup LDS, build the view (and the CSR G in its order), time three fused
 // gradient passes on a constant image after one warm-up, keep the fastest.
+// The side also selects the gridding form of FP32 contexts with separable
+// rows (VALU gather, matrix-core gather or scatter by the subgrid side), so
+// the timing compares forms as well as item sizes.
 template <typename T>
 void autotune_tile(ri_ctx *c) {
     const int eb = sizeof(T) == 4 ? 8 : 16;

@@ -87,7 +87,7 @@ typedef struct {
                                      visibility order (0 ... M); NULL => one block */
     int32_t facet_core;    /* denoiser facet core side (multiple of 16); 0 => whole image */
     int32_t facet_halo;    /* facet halo in pixels (the CNN needs >= its receptive radius) */
-    int32_t item_vis;      /* visibilities per work item of the tile launch (0 => 1024) */
+    int32_t item_vis;      /* visibilities per work item of the tile launch (0 => 2048) */
     int32_t n_wstacks;     /* w-stacking hybrid (appendix E): 0 or 1 => the w-term rides on the
                               w-kernels alone; P in 2..64 => P stacks of equal width over [-W, W]
                               (centres w_p = -W + (2p+1) W/P, a visibility joins the stack whose

@@ -343,7 +343,7 @@ void build_view(ri_ctx *c, View &v, int tile, int frac_bytes) {
     });
 
     // work items (one bucket = one block, one stack, one uv tile; chunks of VMAX)
-    const int64_t VMAX = c->d.item_vis > 0 ? c->d.item_vis : 1024;
+    const int64_t VMAX = c->d.item_vis > 0 ? c->d.item_vis : 2048;
     std::vector<TileItem> items;
     std::vector<int64_t> work;
     for (const Bucket &bk : buckets) {

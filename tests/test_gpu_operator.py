@@ -142,6 +142,29 @@ def test_gather_and_scatter_forms_agree(mode, tile):
     assert err <= 2e-6
 
 
+@pytest.mark.parametrize("mode", [R.RI_G_OTF, R.RI_G_SEP])
+@pytest.mark.parametrize("hmax", [2, 4])
+def test_matrix_core_gather_on_partial_tiles(mode, hmax):
+    # tile 16 with w-kernels up to hmax 2 or 4: subgrid sides 26 and 30, so the
+    # matrix-core gather's 16 x 16 tiles reach past the subgrid (cells dropped
+    # at the item's end); against the oracle built with the same hmax
+    from oracle import phi as OP
+    c = wide()
+    op = OP.Operator(c.N, c.uvw, cell=c.cell, W=c.W, n_wplanes=c.n_wplanes, hmax=hmax)
+    gref, rref = op.grad(c.xr, c.y)
+    d = R.plan_desc(c.N, c.M, cell_rad=c.cell, w_max=c.W, n_wplanes=c.n_wplanes, hmax=hmax, precision=32,
+                    g_mode=mode, tile=16)
+    ctx = R.ri_create(d, c.uvw)
+    g = _img(np.zeros((c.N, c.N)), 32)
+    r2 = torch.zeros(1, dtype=torch.float64, device=DEV)
+    R.ri_gradient(ctx, _img(c.xr, 32), _vis(c.y, 32), g, r2)
+    e_g = rel(g.cpu().numpy(), gref)
+    e_r = abs(float(r2.item()) - rref) / rref
+    print(f"mode {mode} hmax {hmax} (subgrid side {16 + 2 * (hmax + 3)}): gradient {e_g:.3e}, ||r||^2 {e_r:.3e}")
+    assert e_g <= TOL_GRAM[32]
+    assert e_r <= 5e-6
+
+
 @pytest.mark.parametrize("prec,mode", MODES)
 def test_gradient_with_data_and_residual(prec, mode):
     c = wide()
